@@ -1,0 +1,208 @@
+/*
+ * lattice_coulomb.h -- C ABI of the MI355X heat-bath estimator of the
+ * lattice N-body Coulomb energy.
+ *
+ * The method (Sugihara, Higo, Nakamura, "Local Representation of N-body
+ * Coulomb Energy with Path Integrals"):
+ *   - The Coulomb energy of charges q_i at sites r_i, summed over ordered
+ *     pairs, E_N = (1/4pi) sum_{i != j} q_i q_j / |r_i - r_j| (Eq. s1), is a
+ *     sum of Green's functions of -Laplacian, and each Green's function is a
+ *     two-point average of a free scalar field (Eq. path).
+ *   - On a cubic lattice with unit spacing and action
+ *     H_L = 1/2 sum_<m,n> (phi_m - phi_n)^2 (Eq. proplat), the field average
+ *     E_N ~ < (sum_i q_i phi_{n_i})^2 - sum_i (q_i phi_{n_i})^2 > (Eq. nsum)
+ *     is estimated by the mean over M Monte-Carlo samples (Eq. nsum2).
+ *   - Samples come from a Gaussian heat bath: a site takes the mean of its 6
+ *     neighbours plus a Gaussian of variance 1/6, drawn by inverting the
+ *     conditional CDF at a uniform r (Eqs. hb1 and phi).
+ *
+ * What this library computes, exactly:
+ *   - Box lx * ly * lz, sites (x, y, z) 0-based, x fastest.  The paper's open
+ *     boundary is read as Dirichlet ghosts: phi = 0 outside the box, so every
+ *     site keeps 6 neighbours and the update is unchanged at the boundary.
+ *   - Red-black order: colour c = (x + y + z) & 1; sweep t updates colour 0
+ *     (half-sweep h = 2t) then colour 1 (h = 2t + 1).  t counts every sweep
+ *     since lattice_create (thermalisation included).
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11).  Site
+ *     i = x + lx (y + ly z), compact index j = i >> 1, half-sweep h, uses word
+ *     (j & 3) of Philox(counter = (j >> 2, h, chain_id, 0),
+ *     key = (lo32(seed), hi32(seed))); k = word >> 8; r = (k + 1/2) 2^-24.
+ *   - Update: phi = (1/6) sum of the 6 neighbours + erfinv(2r - 1)/sqrt(3)
+ *     (= Eq. phi's -erfc^{-1}(2r)/sqrt(3)), in FP32 arithmetic, stored
+ *     rounded to nearest even in the storage format.
+ *   - A measured sweep adds O = X^2 - Y, X = sum_i q_i phi(n_i),
+ *     Y = sum_i q_i^2 phi(n_i)^2 (FP64), into bins of bin_size consecutive
+ *     samples with compensated (Kahan) FP64 sums.
+ *
+ * Conventions for every call:
+ *   - Sizes are int64_t; host arrays are read during the call and copied
+ *     (the caller keeps ownership).  Device memory belongs to the handle.
+ *   - Work is enqueued on the HIP stream given at creation (NULL = the null
+ *     stream).  Calls that return data to the host synchronise that stream.
+ *   - Every call returns LAT_OK or an error code; nothing is thrown across
+ *     the ABI.  A failed validation leaves the handle unchanged.  The message
+ *     of the last error on the calling thread is lattice_last_error().
+ *   - A handle is not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef LATTICE_COULOMB_H
+#define LATTICE_COULOMB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lattice lattice_t;
+typedef struct lattice_batch lattice_batch_t;
+
+/* Device-memory provider.  alloc returns device memory of `bytes` bytes on
+ * the current device (NULL on failure); release frees it.  A NULL provider
+ * means hipMalloc / hipFree.  The provider must outlive the handle. */
+typedef struct {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes);
+    void (*release)(void *ctx, void *ptr);
+} lat_allocator;
+
+enum {
+    LAT_OK = 0,
+    LAT_ERR_ARG = 1,    /* invalid argument                                   */
+    LAT_ERR_STATE = 2,  /* call not valid in the handle's state               */
+    LAT_ERR_ALLOC = 3,  /* the allocator returned NULL                         */
+    LAT_ERR_DEVICE = 4  /* a HIP call failed                                   */
+};
+
+enum { LAT_FP32 = 0, LAT_BF16 = 1, LAT_FP16 = 2 }; /* field storage format */
+
+/* Sweep kernel selection for lattice_set_variant. */
+enum {
+    LAT_SWEEP_AUTO = 0,    /* library choice                                       */
+    LAT_SWEEP_QUAD = 1,    /* 4 sites per thread, one pass per half-sweep (lx % 8 == 0) */
+    LAT_SWEEP_GENERIC = 2, /* 1 site per thread, any even lx                        */
+    LAT_SWEEP_ZSLAB = 3,   /* z-marching slabs, plane staged in LDS (lx % 8 == 0)   */
+    LAT_SWEEP_FUSED = 4    /* both half-sweeps in one pass (lx % 8 == 0)             */
+};
+
+/* ------------------------------------------------------------------ */
+/* Single lattice                                                      */
+/* ------------------------------------------------------------------ */
+
+/* Create a chain on an lx*ly*lz box with field phi = 0 and sweep counter 0.
+ * lx must be even and >= 2, ly, lz >= 1, lx*ly*lz < 2^31.  storage is a
+ * LAT_FP32/BF16/FP16 value.  seed keys Philox; chain_id is counter word 2
+ * (independent chains of one seed use distinct chain_ids).  hip_stream is a
+ * hipStream_t (NULL = null stream), borrowed, never destroyed.
+ * Paper: the lattice L^3 and spacing a = 1 of the discretisation (Eq.
+ * proplat), the open boundary of the paper's tests. */
+int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t seed,
+                   uint32_t chain_id, const lat_allocator *alloc, void *hip_stream,
+                   lattice_t **out);
+
+/* Place n charges: xyz = 3n int32 (x, y, z) host array, q = n doubles (host).
+ * Charges on one site are summed per site keeping the ordered-pair sum of
+ * Eq. (nsum) exact (co-located i != j pairs included).  n = 0 is allowed
+ * (E = 0).  Errors: LAT_ERR_ARG for a site outside the box or a non-finite q.
+ * Resets the measurement bins (samples of a different charge set do not
+ * mix); the field and the sweep counter are kept (the samples of the field
+ * do not depend on the charges, as the paper notes). */
+int set_charges(lattice_t *lat, int64_t n, const int32_t *xyz, const double *q);
+
+/* Enqueue n_sweeps sweeps without measurement (thermalisation). n_sweeps >= 0. */
+int thermalise(lattice_t *lat, int64_t n_sweeps);
+
+/* Enqueue n_sweeps sweeps; after every measure_every-th one (counted within
+ * this call) take one sample O = X^2 - Y into the bins (Eq. nsum2).
+ * bin_size >= 1 must equal the value used by earlier calls since the last
+ * set_charges.  Errors: LAT_ERR_ARG for n_sweeps < 0, measure_every < 1,
+ * bin_size < 1 or a changed bin_size. */
+int sweep_and_measure(lattice_t *lat, int64_t n_sweeps, int64_t measure_every,
+                      int64_t bin_size);
+
+/* Synchronise and form the estimate (Eq. nsum2): mean = (sum of all samples)
+ * / M; stderr_binned = sqrt(sum_b (m_b - m)^2 / (n_b (n_b - 1))) over the
+ * n_b full bins (m_b bin means, m their mean); a partial last bin enters the
+ * mean only.  Any output pointer may be NULL.  Errors: LAT_ERR_STATE with
+ * fewer than 2 full bins (outputs still written, stderr = NaN) or when a
+ * non-finite sample is found. */
+int energy_estimate(lattice_t *lat, double *mean, double *stderr_binned, int64_t *n_samples,
+                    int64_t *n_bins);
+
+/* Release all device memory of the handle (NULL is ignored). */
+void lattice_destroy(lattice_t *lat);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *lattice_last_error(void);
+
+/* Number of sweeps done since creation. */
+int lattice_sweep_count(const lattice_t *lat, int64_t *sweeps);
+
+/* Choose the sweep kernel (LAT_SWEEP_*).  Every variant draws the same
+ * random numbers and computes the same update; LAT_ERR_ARG if the variant
+ * cannot handle this box. */
+int lattice_set_variant(lattice_t *lat, int variant);
+
+/* Tuning of the slab kernels (LAT_SWEEP_ZSLAB, LAT_SWEEP_FUSED): planes of
+ * the box one workgroup walks along z (0 = library default, at most lz), and
+ * whether workgroups are ordered so that each of the chip's 8 XCDs gets a
+ * contiguous run of tiles.  Results do not depend on either. */
+int lattice_set_slab(lattice_t *lat, int64_t planes, int xcd_order);
+
+/* ---- test / checkpoint hooks (all synchronise the stream) ---------- */
+
+/* Copy the field to host_out: lx*ly*lz floats, natural order x fastest. */
+int lattice_get_field(lattice_t *lat, float *host_out);
+
+/* Replace the field from host_in (natural order), rounded to the storage
+ * format.  Errors: LAT_ERR_ARG for non-finite values. */
+int lattice_set_field(lattice_t *lat, const float *host_in);
+
+/* The (X, Y) of the most recent sample. */
+int lattice_last_measure(lattice_t *lat, double *X, double *Y);
+
+/* Checkpoint: sweep counter, number of samples and the bins
+ * (2 doubles per bin: compensated sum, compensation; at most cap bins
+ * copied to bins_host, which may be NULL); *n_bins = bins in use. */
+int lattice_get_state(lattice_t *lat, int64_t *sweep_counter, int64_t *n_samples,
+                      double *bins_host, int64_t cap, int64_t *n_bins);
+
+/* Restore a checkpoint taken by lattice_get_state (field restored separately
+ * with lattice_set_field).  bin_size as used when it was taken. */
+int lattice_set_state(lattice_t *lat, int64_t sweep_counter, int64_t n_samples, int64_t bin_size,
+                      const double *bins_host, int64_t n_bins);
+
+/* ------------------------------------------------------------------ */
+/* Batch of independent chains on boxes of uneven size                 */
+/* ------------------------------------------------------------------ */
+
+/* n_chains chains; edges = 3 int64 per chain (lx, ly, lz; lx even, each box
+ * below 2^31 sites); chain_ids = n_chains uint32 (NULL: 0 .. n_chains-1).
+ * All chains share storage, seed and stream.  Chain k draws the same random
+ * numbers as a single lattice with chain_id = chain_ids[k]. */
+int batch_create(int64_t n_chains, const int64_t *edges, const uint32_t *chain_ids, int storage,
+                 uint64_t seed, const lat_allocator *alloc, void *hip_stream,
+                 lattice_batch_t **out);
+
+/* Charges of one chain (as set_charges).  Resets that chain's bins. */
+int batch_set_charges(lattice_batch_t *b, int64_t chain, int64_t n, const int32_t *xyz,
+                      const double *q);
+
+/* Enqueue n_therm sweeps then n_meas measured sweeps (one sample per sweep,
+ * bins of bin_size) for every chain, in one persistent launch. */
+int batch_run(lattice_batch_t *b, int64_t n_therm, int64_t n_meas, int64_t bin_size);
+
+/* Estimate of one chain (as energy_estimate). */
+int batch_energy_estimate(lattice_batch_t *b, int64_t chain, double *mean,
+                          double *stderr_binned, int64_t *n_samples, int64_t *n_bins);
+
+/* Field of one chain, natural order (synchronises). */
+int batch_get_field(lattice_batch_t *b, int64_t chain, float *host_out);
+
+void batch_destroy(lattice_batch_t *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LATTICE_COULOMB_H */

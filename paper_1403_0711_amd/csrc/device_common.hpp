@@ -1,0 +1,194 @@
+// Device building blocks of the heat-bath sweep: counter-based random
+// numbers, the uniform -> Gaussian transform, field storage formats and
+// wavefront reductions.  gfx950 (CDNA4), wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "erfinv_coeffs.h"
+
+namespace latcoul {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
+// 32x32->64-bit products on words 0 and 2, high halves xor-ed into the other
+// words with the round key, key bumped by the Weyl constants between rounds.
+// Counter words 1..3 and the key are wave-uniform here, so the compiler keeps
+// them (and the first rounds' uniform products) on the scalar unit.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        // one 32x32->64 product per word: lowers to a single v_mad_u64_u32
+        // (full rate on gfx950) instead of separate low and high multiplies
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0;
+        c1 = (uint32_t)p1;
+        c2 = n2;
+        c3 = (uint32_t)p0;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ---------------------------------------------------------------------------
+// Heat-bath noise.  A 32-bit word u gives k = u >> 8 and the exact FP32
+// s = 2r - 1 = (2k + 1 - 2^24) 2^-24 of the midpoint grid r = (k + 1/2) 2^-24.
+// The noise of the paper's Eq. (phi), -erfc^{-1}(2r)/sqrt(3), equals
+// erfinv(s)/sqrt(3); it is evaluated in Giles' two-region form with
+// w = -log(1 - s^2) and coefficients fitted for this library
+// (erfinv_coeffs.h, max relative error 3.3e-7 on the grid).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float grid_s(uint32_t u) {
+    const int t = (int)((u >> 7) | 1u) - (1 << 24);  // 2k + 1 - 2^24, |t| < 2^24: exact in FP32
+    return (float)t * 0x1p-24f;
+}
+
+__device__ __forceinline__ float heatbath_noise(uint32_t u) {
+    const float s = grid_s(u);
+    const float omx2 = fmaf(-s, s, 1.0f);  // 1 - s^2, one rounding
+    // v_log_f32 is log2; w = -ln(1 - s^2)
+    const float w = -0.69314718055994531f * __builtin_amdgcn_logf(omx2);
+    float p;
+    if (w < LATCOUL_ERFINV_W_SPLIT) {
+        const float x = w - 2.5f;
+        p = kErfinvP[8];
+#pragma unroll
+        for (int i = 7; i >= 0; --i) p = fmaf(p, x, kErfinvP[i]);
+    } else {
+        const float x = __builtin_amdgcn_sqrtf(w) - 3.0f;
+        p = kErfinvQ[8];
+#pragma unroll
+        for (int i = 7; i >= 0; --i) p = fmaf(p, x, kErfinvQ[i]);
+    }
+    return p * s;
+}
+
+// ---------------------------------------------------------------------------
+// Field storage formats: FP32, BF16, FP16.  Arithmetic is always FP32; a
+// stored value is rounded to nearest even.
+// ---------------------------------------------------------------------------
+struct StoreF32 {
+    using T = float;
+    static constexpr int kBytes = 4;
+    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return p[i]; }
+    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) {
+        return *reinterpret_cast<const float4*>(p + i);
+    }
+    __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) {
+        *reinterpret_cast<float4*>(p + i) = v;
+    }
+    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { p[i] = v; }
+};
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;  // finite inputs only
+}
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+struct StoreBF16 {
+    using T = uint16_t;
+    static constexpr int kBytes = 2;
+    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return bf16_to_f32(p[i]); }
+    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) {
+        const uint2 w = *reinterpret_cast<const uint2*>(p + i);
+        return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                           __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
+    }
+    __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) {
+        uint2 w;
+        w.x = bf16_rne_bits(v.x) | (bf16_rne_bits(v.y) << 16);
+        w.y = bf16_rne_bits(v.z) | (bf16_rne_bits(v.w) << 16);
+        *reinterpret_cast<uint2*>(p + i) = w;
+    }
+    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { p[i] = (T)bf16_rne_bits(v); }
+};
+
+struct StoreF16 {
+    using T = _Float16;
+    static constexpr int kBytes = 2;
+    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return (float)p[i]; }
+    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        const h4 w = *reinterpret_cast<const h4*>(p + i);
+        return make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
+    }
+    __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        h4 w;
+        w[0] = (_Float16)v.x;
+        w[1] = (_Float16)v.y;
+        w[2] = (_Float16)v.z;
+        w[3] = (_Float16)v.w;
+        *reinterpret_cast<h4*>(p + i) = w;
+    }
+    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { p[i] = (_Float16)v; }
+};
+
+// ---------------------------------------------------------------------------
+// Wave64 FP64 sum by DPP data movement (each 32-bit half moved separately,
+// the add in FP64): xor-1 and xor-2 quad permutes, row half-mirror and row
+// mirror leave every lane of a 16-lane row holding the row sum; row_bcast:15
+// and row_bcast:31 then fold the four rows into lane 63.  Fixed order, so the
+// result is deterministic.  Returns the total in every lane (readlane 63).
+// ---------------------------------------------------------------------------
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, kCtrl, kRowMask, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), kCtrl, kRowMask, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_move<0x140, 0xF>(v);  // row_mirror
+    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Block sum of two FP64 values over kThreads threads (multiple of 64); the
+// result is valid in every thread.  Fixed order: waves reduced by wave_sum,
+// then wave totals added in wave order.
+template <int kThreads>
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+    constexpr int kWaves = kThreads / 64;
+    __shared__ double sa[kWaves], sb[kWaves];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int wid = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        sa[wid] = a;
+        sb[wid] = b;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        ta += sa[w];
+        tb += sb[w];
+    }
+    a = ta;
+    b = tb;
+    __syncthreads();
+}
+
+}  // namespace latcoul

@@ -1,0 +1,83 @@
+// Host-side launch interface of the library's kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace latcoul {
+
+enum : int { kVariantQuad = 1, kVariantGeneric = 2, kVariantZslab = 3, kVariantFused = 4 };
+
+// One half-sweep of colour c = h & 1 on one lattice.
+struct SweepArgs {
+    void* field;      // 2 * vh elements: colour 0 then colour 1
+    uint32_t lh, ly, lz, vh;
+    uint32_t c, h;    // colour, half-sweep index (Philox counter word 1)
+    uint32_t k0, k1;  // Philox key
+    uint32_t chain;   // Philox counter word 2
+    int storage;      // 0 FP32, 1 BF16, 2 FP16
+    int variant;      // kVariantQuad / kVariantGeneric / kVariantZslab
+    uint32_t zc;      // zslab: planes per workgroup (0 = default)
+    uint32_t xcd_order;  // zslab: XCD-aware block order
+};
+hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream);
+
+// Both half-sweeps of sweep t in one pass (z-marching slabs), lh % 4 == 0.
+struct FusedArgs {
+    void* field;
+    uint32_t lh, ly, lz, vh;
+    uint32_t h0;      // 2t: colour 0 uses h0, colour 1 uses h0 + 1
+    uint32_t k0, k1, chain;
+    int storage;
+    uint32_t slab;    // planes per workgroup along z
+};
+hipError_t launch_fused_sweep(const FusedArgs& a, hipStream_t stream);
+
+// Gather of the charge-weighted correlator after a sweep (Eq. nsum2):
+// X = sum_s Q_s phi_s, Y = sum_s S_s phi_s^2 over the site-aggregated charge
+// list, O = X^2 - Y compensated-added into bins[2*bin], bins[2*bin+1].
+struct MeasureArgs {
+    const void* field;
+    const uint32_t* site;  // c * vh + j, sorted ascending
+    const double* Q;       // sum of q on the site
+    const double* S;       // sum of q^2 on the site
+    uint32_t n;            // number of charged sites
+    double* partials;      // 2 * blocks scratch
+    uint32_t* ticket;      // zero between launches
+    double* bins;
+    uint32_t bin;
+    double* last_xy;       // X, Y of this sample
+    int storage;
+    uint32_t blocks;       // grid size (fixed for a given n: fixes the sum order)
+};
+hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream);
+uint32_t measure_blocks(uint32_t n);
+
+// Batched chains: one workgroup owns one chain and runs all its sweeps.
+struct BatchChainDesc {
+    uint64_t field_off;   // element offset of the chain's field (2 * vh elements)
+    uint32_t lh, ly, lz, vh;
+    uint32_t chain_id;
+    uint32_t site_off, n_sites;  // range in the concatenated charge arrays
+    uint32_t bin_off;            // first bin slot of this chain (2 doubles each)
+    uint32_t pad;
+};
+struct BatchArgs {
+    void* field;
+    const BatchChainDesc* desc;
+    const uint32_t* order;  // chains in launch order (largest first)
+    uint32_t n_chains;
+    const uint32_t* site;
+    const double* Q;
+    const double* S;
+    double* bins;
+    uint32_t t0;        // sweep counter at the start of this run (same for all chains)
+    uint32_t n_therm, n_meas, bin_size;
+    uint32_t meas0;     // samples already taken (same for all chains)
+    uint32_t k0, k1;
+    int storage;
+    uint32_t threads;   // workgroup size
+};
+hipError_t launch_batch(const BatchArgs& a, hipStream_t stream);
+
+}  // namespace latcoul

@@ -1,0 +1,396 @@
+// C-ABI runtime of the heat-bath Coulomb-energy estimator: lattice objects,
+// charge upload, sweep scheduling, sample bins and the final estimate.
+// The kernels live in sweep_kernels.hip, fused_sweep.hip, measure_kernels.hip
+// and batch_kernels.hip.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lattice_coulomb.h"
+#include "runtime_common.hpp"
+
+using namespace latcoul;
+
+struct lattice {
+    int64_t lx = 0, ly = 0, lz = 0;
+    uint32_t lh = 0, vh = 0;
+    int storage = 0;
+    size_t esz = 4;
+    uint64_t seed = 0;
+    uint32_t chain = 0;
+    DeviceAllocator mem;
+    hipStream_t stream = nullptr;
+    void* field = nullptr;
+    // charges, aggregated per site
+    int64_t n_raw = 0;
+    uint32_t n_sites = 0;
+    uint32_t* d_site = nullptr;
+    double* d_Q = nullptr;
+    double* d_S = nullptr;
+    double* d_partials = nullptr;
+    uint32_t meas_blocks = 1;
+    // misc block: ticket (uint32 at 0), last X, Y (doubles at 64)
+    void* d_misc = nullptr;
+    // samples
+    double* d_bins = nullptr;
+    int64_t bin_cap = 0;
+    int64_t bin_size = 0;
+    int64_t n_meas = 0;
+    int64_t t = 0;
+    int variant = LAT_SWEEP_AUTO;
+    uint32_t slab = 16;      // planes per workgroup for the slab kernels (0 = kernel default)
+    uint32_t xcd_order = 1;  // XCD-aware workgroup order for the slab kernels
+
+    uint32_t* ticket() { return static_cast<uint32_t*>(d_misc); }
+    double* last_xy() { return reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
+    int effective_variant() const {
+        if (variant != LAT_SWEEP_AUTO) return variant;
+        if (lh % 4 != 0) return LAT_SWEEP_GENERIC;
+        // boxes that spill out of the 256 MB last-level cache: z-marching slabs
+        return (size_t)2 * vh * esz > ((size_t)256 << 20) ? LAT_SWEEP_ZSLAB : LAT_SWEEP_QUAD;
+    }
+};
+
+static int check_lattice(const lattice* L) {
+    if (!L) return set_error(LAT_ERR_ARG, "null lattice handle");
+    return LAT_OK;
+}
+
+static int enqueue_sweep(lattice* L) {
+    if (L->t >= (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_STATE, "sweep counter exhausted (2^31 sweeps)");
+    const uint32_t h0 = (uint32_t)(2 * L->t);
+    const int v = L->effective_variant();
+    hipError_t e;
+    if (v == LAT_SWEEP_FUSED) {
+        FusedArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, h0,
+                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, L->slab};
+        e = launch_fused_sweep(a, L->stream);
+    } else {
+        const int kv = v == LAT_SWEEP_QUAD ? kVariantQuad : v == LAT_SWEEP_ZSLAB ? kVariantZslab : kVariantGeneric;
+        SweepArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, 0u, h0,
+                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, kv, L->slab,
+                    L->xcd_order};
+        e = launch_halfsweep(a, L->stream);
+        if (e == hipSuccess) {
+            a.c = 1u;
+            a.h = h0 + 1u;
+            e = launch_halfsweep(a, L->stream);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    L->t += 1;
+    return LAT_OK;
+}
+
+static int enqueue_measure(lattice* L) {
+    MeasureArgs a{L->field, L->d_site, L->d_Q, L->d_S, L->n_sites, L->d_partials, L->ticket(),
+                  L->d_bins, (uint32_t)(L->n_meas / L->bin_size), L->last_xy(), L->storage,
+                  L->meas_blocks};
+    hipError_t e = launch_measure(a, L->stream);
+    if (e != hipSuccess) return hip_fail(e, "measure launch");
+    L->n_meas += 1;
+    return LAT_OK;
+}
+
+static int ensure_bins(lattice* L, int64_t n_bins_needed) {
+    if (n_bins_needed <= L->bin_cap) return LAT_OK;
+    int64_t cap = std::max<int64_t>({n_bins_needed, 2 * L->bin_cap, 64});
+    double* nb = static_cast<double*>(L->mem.alloc(sizeof(double) * 2 * (size_t)cap));
+    if (!nb) return set_error(LAT_ERR_ALLOC, "allocation of sample bins failed");
+    hipError_t e = hipMemsetAsync(nb, 0, sizeof(double) * 2 * (size_t)cap, L->stream);
+    if (e == hipSuccess && L->d_bins && L->bin_cap > 0)
+        e = hipMemcpyAsync(nb, L->d_bins, sizeof(double) * 2 * (size_t)L->bin_cap, hipMemcpyDeviceToDevice,
+                           L->stream);
+    if (e != hipSuccess) {
+        L->mem.release(nb);
+        return hip_fail(e, "bin resize");
+    }
+    if (L->d_bins) L->mem.release(L->d_bins);
+    L->d_bins = nb;
+    L->bin_cap = cap;
+    return LAT_OK;
+}
+
+extern "C" {
+
+int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t seed, uint32_t chain_id,
+                   const lat_allocator* alloc, void* hip_stream, lattice_t** out) {
+    if (!out) return set_error(LAT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (lx < 2 || (lx & 1)) return set_error(LAT_ERR_ARG, "lx must be even and >= 2");
+    if (ly < 1 || lz < 1) return set_error(LAT_ERR_ARG, "ly and lz must be >= 1");
+    if ((double)lx * (double)ly * (double)lz >= 2147483648.0)
+        return set_error(LAT_ERR_ARG, "lattice must have fewer than 2^31 sites");
+    if (storage < LAT_FP32 || storage > LAT_FP16) return set_error(LAT_ERR_ARG, "unknown storage format");
+    if (alloc && (!alloc->alloc || !alloc->release))
+        return set_error(LAT_ERR_ARG, "allocator needs both alloc and release");
+    lattice* L = new lattice();
+    L->lx = lx;
+    L->ly = ly;
+    L->lz = lz;
+    L->lh = (uint32_t)(lx / 2);
+    L->vh = (uint32_t)(lx / 2 * ly * lz);
+    L->storage = storage;
+    L->esz = storage == LAT_FP32 ? 4 : 2;
+    L->seed = seed;
+    L->chain = chain_id;
+    L->mem = DeviceAllocator(alloc);
+    L->stream = static_cast<hipStream_t>(hip_stream);
+    const size_t fbytes = round_up(2 * (size_t)L->vh * L->esz, 256);
+    L->field = L->mem.alloc(fbytes);
+    L->d_misc = L->mem.alloc(256);
+    if (!L->field || !L->d_misc) {
+        lattice_destroy(L);
+        return set_error(LAT_ERR_ALLOC, "allocation of the field failed");
+    }
+    hipError_t e = hipMemsetAsync(L->field, 0, fbytes, L->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(L->d_misc, 0, 256, L->stream);
+    if (e != hipSuccess) {
+        lattice_destroy(L);
+        return hip_fail(e, "field initialisation");
+    }
+    *out = L;
+    return LAT_OK;
+}
+
+void lattice_destroy(lattice_t* L) {
+    if (!L) return;
+    (void)hipStreamSynchronize(L->stream);
+    L->mem.release(L->field);
+    L->mem.release(L->d_misc);
+    L->mem.release(L->d_site);
+    L->mem.release(L->d_Q);
+    L->mem.release(L->d_S);
+    L->mem.release(L->d_partials);
+    L->mem.release(L->d_bins);
+    delete L;
+}
+
+int lattice_sweep_count(const lattice_t* L, int64_t* sweeps) {
+    if (int r = check_lattice(L)) return r;
+    if (!sweeps) return set_error(LAT_ERR_ARG, "sweeps is NULL");
+    *sweeps = L->t;
+    return LAT_OK;
+}
+
+int lattice_set_variant(lattice_t* L, int variant) {
+    if (int r = check_lattice(L)) return r;
+    switch (variant) {
+        case LAT_SWEEP_AUTO:
+        case LAT_SWEEP_GENERIC: break;
+        case LAT_SWEEP_QUAD:
+        case LAT_SWEEP_ZSLAB:
+            if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
+            break;
+        case LAT_SWEEP_FUSED:
+            if (L->lh % 4) return set_error(LAT_ERR_ARG, "fused sweep needs lx % 8 == 0");
+            if (!fused_sweep_supported(L->lh, (uint32_t)L->ly))
+                return set_error(LAT_ERR_ARG, "fused sweep not available for this box");
+            break;
+        default: return set_error(LAT_ERR_ARG, "unknown sweep variant");
+    }
+    L->variant = variant;
+    return LAT_OK;
+}
+
+int lattice_set_slab(lattice_t* L, int64_t planes, int xcd_order) {
+    if (int r = check_lattice(L)) return r;
+    if (planes < 0 || planes > L->lz) return set_error(LAT_ERR_ARG, "planes must be in [0, lz]");
+    L->slab = (uint32_t)planes;
+    L->xcd_order = xcd_order ? 1u : 0u;
+    return LAT_OK;
+}
+
+int set_charges(lattice_t* L, int64_t n, const int32_t* xyz, const double* q) {
+    if (int r = check_lattice(L)) return r;
+    if (n < 0) return set_error(LAT_ERR_ARG, "negative charge count");
+    if (n > 0 && (!xyz || !q)) return set_error(LAT_ERR_ARG, "xyz or q is NULL");
+    AggregatedCharges agg;
+    if (int r = aggregate_charges(n, xyz, q, L->lx, L->ly, L->lz, L->vh, &agg)) return r;
+    const uint32_t ns = (uint32_t)agg.site.size();
+    const uint32_t blocks = measure_blocks(ns);
+    uint32_t* d_site = nullptr;
+    double *d_Q = nullptr, *d_S = nullptr, *d_part = nullptr;
+    const size_t cap = std::max<size_t>(ns, 1);
+    d_site = static_cast<uint32_t*>(L->mem.alloc(cap * 4));
+    d_Q = static_cast<double*>(L->mem.alloc(cap * 8));
+    d_S = static_cast<double*>(L->mem.alloc(cap * 8));
+    d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * 16));
+    if (!d_site || !d_Q || !d_S || !d_part) {
+        L->mem.release(d_site);
+        L->mem.release(d_Q);
+        L->mem.release(d_S);
+        L->mem.release(d_part);
+        return set_error(LAT_ERR_ALLOC, "allocation of the charge list failed");
+    }
+    hipError_t e = hipSuccess;
+    if (ns > 0) {
+        e = hipMemcpyAsync(d_site, agg.site.data(), (size_t)ns * 4, hipMemcpyHostToDevice, L->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_Q, agg.Q.data(), (size_t)ns * 8, hipMemcpyHostToDevice, L->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_S, agg.S.data(), (size_t)ns * 8, hipMemcpyHostToDevice, L->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) {
+        L->mem.release(d_site);
+        L->mem.release(d_Q);
+        L->mem.release(d_S);
+        L->mem.release(d_part);
+        return hip_fail(e, "charge upload");
+    }
+    L->mem.release(L->d_site);
+    L->mem.release(L->d_Q);
+    L->mem.release(L->d_S);
+    L->mem.release(L->d_partials);
+    L->d_site = d_site;
+    L->d_Q = d_Q;
+    L->d_S = d_S;
+    L->d_partials = d_part;
+    L->n_sites = ns;
+    L->n_raw = n;
+    L->meas_blocks = blocks;
+    // new observable: start a new sample series
+    L->n_meas = 0;
+    L->bin_size = 0;
+    if (L->d_bins) {
+        e = hipMemsetAsync(L->d_bins, 0, sizeof(double) * 2 * (size_t)L->bin_cap, L->stream);
+        if (e != hipSuccess) return hip_fail(e, "bin reset");
+    }
+    return LAT_OK;
+}
+
+int thermalise(lattice_t* L, int64_t n_sweeps) {
+    if (int r = check_lattice(L)) return r;
+    if (n_sweeps < 0) return set_error(LAT_ERR_ARG, "n_sweeps < 0");
+    if (L->t + n_sweeps > (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_ARG, "sweep counter would exceed 2^31");
+    for (int64_t s = 0; s < n_sweeps; ++s)
+        if (int r = enqueue_sweep(L)) return r;
+    return LAT_OK;
+}
+
+int sweep_and_measure(lattice_t* L, int64_t n_sweeps, int64_t measure_every, int64_t bin_size) {
+    if (int r = check_lattice(L)) return r;
+    if (n_sweeps < 0) return set_error(LAT_ERR_ARG, "n_sweeps < 0");
+    if (measure_every < 1) return set_error(LAT_ERR_ARG, "measure_every < 1");
+    if (bin_size < 1) return set_error(LAT_ERR_ARG, "bin_size < 1");
+    if (L->bin_size != 0 && bin_size != L->bin_size)
+        return set_error(LAT_ERR_ARG, "bin_size differs from the one of earlier samples");
+    if (L->t + n_sweeps > (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_ARG, "sweep counter would exceed 2^31");
+    if (!L->d_partials) {
+        // no set_charges yet: an empty charge list
+        if (int r = set_charges(L, 0, nullptr, nullptr)) return r;
+    }
+    const int64_t m = n_sweeps / measure_every;
+    const int64_t total = L->n_meas + m;
+    if ((total + bin_size - 1) / bin_size >= (int64_t)0xFFFFFFFF)
+        return set_error(LAT_ERR_ARG, "too many bins");
+    if (int r = ensure_bins(L, (total + bin_size - 1) / bin_size)) return r;
+    L->bin_size = bin_size;
+    for (int64_t s = 0; s < n_sweeps; ++s) {
+        if (int r = enqueue_sweep(L)) return r;
+        if ((s + 1) % measure_every == 0)
+            if (int r = enqueue_measure(L)) return r;
+    }
+    return LAT_OK;
+}
+
+int energy_estimate(lattice_t* L, double* mean, double* stderr_binned, int64_t* n_samples, int64_t* n_bins) {
+    if (int r = check_lattice(L)) return r;
+    const int64_t M = L->n_meas;
+    const int64_t B = L->bin_size > 0 ? L->bin_size : 1;
+    const int64_t used = (M + B - 1) / B;
+    std::vector<double> h((size_t)std::max<int64_t>(used, 1) * 2, 0.0);
+    hipError_t e = hipStreamSynchronize(L->stream);
+    if (e == hipSuccess && used > 0)
+        e = hipMemcpy(h.data(), L->d_bins, sizeof(double) * 2 * (size_t)used, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "bin readback");
+    EstimateResult res = estimate_from_bins(h.data(), used, M, B);
+    if (mean) *mean = res.mean;
+    if (stderr_binned) *stderr_binned = res.stderr_binned;
+    if (n_samples) *n_samples = M;
+    if (n_bins) *n_bins = res.full_bins;
+    if (!res.finite) return set_error(LAT_ERR_STATE, "non-finite sample found (field or charges not finite)");
+    if (res.full_bins < 2) return set_error(LAT_ERR_STATE, "fewer than 2 full bins: no error estimate");
+    return LAT_OK;
+}
+
+int lattice_get_field(lattice_t* L, float* host_out) {
+    if (int r = check_lattice(L)) return r;
+    if (!host_out) return set_error(LAT_ERR_ARG, "host_out is NULL");
+    std::vector<unsigned char> buf(2 * (size_t)L->vh * L->esz);
+    hipError_t e = hipStreamSynchronize(L->stream);
+    if (e == hipSuccess) e = hipMemcpy(buf.data(), L->field, buf.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "field readback");
+    compact_to_natural(buf.data(), L->storage, L->lx, L->ly, L->lz, L->vh, host_out);
+    return LAT_OK;
+}
+
+int lattice_set_field(lattice_t* L, const float* host_in) {
+    if (int r = check_lattice(L)) return r;
+    if (!host_in) return set_error(LAT_ERR_ARG, "host_in is NULL");
+    const size_t V = (size_t)L->lx * L->ly * L->lz;
+    for (size_t i = 0; i < V; ++i)
+        if (!std::isfinite(host_in[i])) return set_error(LAT_ERR_ARG, "non-finite field value");
+    std::vector<unsigned char> buf(2 * (size_t)L->vh * L->esz);
+    natural_to_compact(host_in, L->storage, L->lx, L->ly, L->lz, L->vh, buf.data());
+    hipError_t e = hipStreamSynchronize(L->stream);
+    if (e == hipSuccess) e = hipMemcpy(L->field, buf.data(), buf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "field upload");
+    return LAT_OK;
+}
+
+int lattice_last_measure(lattice_t* L, double* X, double* Y) {
+    if (int r = check_lattice(L)) return r;
+    double h[2] = {0, 0};
+    hipError_t e = hipStreamSynchronize(L->stream);
+    if (e == hipSuccess) e = hipMemcpy(h, L->last_xy(), 16, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "readback");
+    if (X) *X = h[0];
+    if (Y) *Y = h[1];
+    return LAT_OK;
+}
+
+int lattice_get_state(lattice_t* L, int64_t* sweep_counter, int64_t* n_samples, double* bins_host, int64_t cap,
+                      int64_t* n_bins) {
+    if (int r = check_lattice(L)) return r;
+    const int64_t B = L->bin_size > 0 ? L->bin_size : 1;
+    const int64_t used = (L->n_meas + B - 1) / B;
+    if (sweep_counter) *sweep_counter = L->t;
+    if (n_samples) *n_samples = L->n_meas;
+    if (n_bins) *n_bins = used;
+    hipError_t e = hipStreamSynchronize(L->stream);
+    const int64_t k = std::min(cap, used);
+    if (e == hipSuccess && bins_host && k > 0)
+        e = hipMemcpy(bins_host, L->d_bins, sizeof(double) * 2 * (size_t)k, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "state readback");
+    return LAT_OK;
+}
+
+int lattice_set_state(lattice_t* L, int64_t sweep_counter, int64_t n_samples, int64_t bin_size,
+                      const double* bins_host, int64_t n_bins) {
+    if (int r = check_lattice(L)) return r;
+    if (sweep_counter < 0 || sweep_counter > (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_ARG, "bad sweep counter");
+    if (n_samples < 0 || (n_samples > 0 && bin_size < 1)) return set_error(LAT_ERR_ARG, "bad sample count or bin size");
+    const int64_t B = bin_size > 0 ? bin_size : 1;
+    const int64_t used = (n_samples + B - 1) / B;
+    if (n_bins != used || (used > 0 && !bins_host)) return set_error(LAT_ERR_ARG, "bins do not match n_samples/bin_size");
+    if (!L->d_partials)
+        if (int r = set_charges(L, 0, nullptr, nullptr)) return r;
+    if (int r = ensure_bins(L, std::max<int64_t>(used, 1))) return r;
+    hipError_t e = hipMemsetAsync(L->d_bins, 0, sizeof(double) * 2 * (size_t)L->bin_cap, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e == hipSuccess && used > 0)
+        e = hipMemcpy(L->d_bins, bins_host, sizeof(double) * 2 * (size_t)used, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "state upload");
+    L->t = sweep_counter;
+    L->n_meas = n_samples;
+    L->bin_size = n_samples > 0 ? bin_size : 0;
+    return LAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,322 @@
+"""Python binding of the C ABI in ``include/lattice_coulomb.h`` (ctypes).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  PyTorch supplies device memory (its caching allocator, through the
+ABI's allocator callbacks) and the stream (the current torch stream).  The
+library must have been built (``python -m paper_1403_0711_amd.build_lib``);
+nothing here falls back to another implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Lattice", "Batch", "LatticeError", "load_library", "STORAGE", "VARIANT"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "liblatcoul.so")
+
+STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
+VARIANT = {"auto": 0, "quad": 1, "generic": 2, "zslab": 3, "fused": 4}
+ERR_NAMES = {1: "LAT_ERR_ARG", 2: "LAT_ERR_STATE", 3: "LAT_ERR_ALLOC", 4: "LAT_ERR_DEVICE"}
+
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_int = ctypes.c_int
+_p = ctypes.c_void_p
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class LatAllocator(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("alloc", ALLOC_FN), ("release", RELEASE_FN)]
+
+
+class LatticeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load ``liblatcoul.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1403_0711_amd.build_lib` (or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "lattice_create": (_int, [_i64, _i64, _i64, _int, _u64, _u32, _p, _p, _p]),
+        "set_charges": (_int, [_p, _i64, _p, _p]),
+        "thermalise": (_int, [_p, _i64]),
+        "sweep_and_measure": (_int, [_p, _i64, _i64, _i64]),
+        "energy_estimate": (_int, [_p, _pd, _pd, _pi64, _pi64]),
+        "lattice_destroy": (None, [_p]),
+        "lattice_last_error": (ctypes.c_char_p, []),
+        "lattice_sweep_count": (_int, [_p, _pi64]),
+        "lattice_set_variant": (_int, [_p, _int]),
+        "lattice_set_slab": (_int, [_p, _i64, _int]),
+        "lattice_get_field": (_int, [_p, _p]),
+        "lattice_set_field": (_int, [_p, _p]),
+        "lattice_last_measure": (_int, [_p, _pd, _pd]),
+        "lattice_get_state": (_int, [_p, _pi64, _pi64, _p, _i64, _pi64]),
+        "lattice_set_state": (_int, [_p, _i64, _i64, _i64, _p, _i64]),
+        "batch_create": (_int, [_i64, _p, _p, _int, _u64, _p, _p, _p]),
+        "batch_set_charges": (_int, [_p, _i64, _i64, _p, _p]),
+        "batch_run": (_int, [_p, _i64, _i64, _i64]),
+        "batch_energy_estimate": (_int, [_p, _i64, _pd, _pd, _pi64, _pi64]),
+        "batch_get_field": (_int, [_p, _i64, _p]),
+        "batch_destroy": (None, [_p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LatticeError(rc, _lib.lattice_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _TorchMemory:
+    """Allocator callbacks backed by torch's caching allocator on one device
+    and stream (kept alive as long as the owning handle)."""
+
+    def __init__(self, device, stream):
+        import torch
+
+        self.torch = torch
+        self.device = device
+        self.stream = stream
+
+        def _alloc(ctx, nbytes):
+            try:
+                return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:  # out of memory -> NULL -> LAT_ERR_ALLOC
+                return None
+
+        def _release(ctx, ptr):
+            try:
+                self.torch.cuda.caching_allocator_delete(ptr)
+            except Exception:
+                pass
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._release = RELEASE_FN(_release)
+        self.struct = LatAllocator(None, self._alloc, self._release)
+
+
+def _device_and_stream(device, stream):
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible: the lattice estimator runs on the GPU only")
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else int(device))
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    return dev, stream
+
+
+class Lattice:
+    """One heat-bath chain on an ``lx*ly*lz`` Dirichlet box (see the header
+    for the exact method).  ``shape = (lx, ly, lz)``; fields are returned as
+    ``phi[z, y, x]`` float32 arrays."""
+
+    def __init__(self, shape, storage: str = "fp32", seed: int = 0, chain_id: int = 0,
+                 device=None, stream=None, allocator: str = "torch"):
+        import torch
+
+        self.lib = load_library()
+        self.shape = tuple(int(s) for s in shape)
+        self.storage = storage
+        self.device, self.stream = _device_and_stream(device, stream)
+        self._mem = _TorchMemory(self.device, self.stream) if allocator == "torch" else None
+        alloc_ptr = ctypes.cast(ctypes.pointer(self._mem.struct), ctypes.c_void_p) if self._mem else None
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.lattice_create(*self.shape, STORAGE[storage], int(seed), int(chain_id),
+                                           alloc_ptr, ctypes.c_void_p(self.stream.cuda_stream),
+                                           ctypes.byref(h)))
+        self.h = h
+
+    # -- lifetime --------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            import torch
+
+            with torch.cuda.device(self.device):
+                self.lib.lattice_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _call(self, fn, *args):
+        import torch
+
+        with torch.cuda.device(self.device):
+            _check(fn(self.h, *args))
+
+    # -- the five calls of the method ------------------------------------
+    def set_charges(self, xyz, q):
+        xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        if xyz.shape[0] != q.shape[0]:
+            raise ValueError("xyz and q differ in length")
+        self._call(self.lib.set_charges, q.shape[0], _ptr(xyz), _ptr(q))
+
+    def thermalise(self, n_sweeps: int):
+        self._call(self.lib.thermalise, int(n_sweeps))
+
+    def sweep_and_measure(self, n_sweeps: int, measure_every: int = 1, bin_size: int = 100):
+        self._call(self.lib.sweep_and_measure, int(n_sweeps), int(measure_every), int(bin_size))
+
+    def energy_estimate(self, allow_few_bins: bool = False):
+        """Returns ``(mean, stderr, n_samples, n_bins)``."""
+        import torch
+
+        m, s = ctypes.c_double(), ctypes.c_double()
+        n, nb = ctypes.c_int64(), ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            rc = self.lib.energy_estimate(self.h, ctypes.byref(m), ctypes.byref(s), ctypes.byref(n),
+                                          ctypes.byref(nb))
+        if rc != 0 and not (allow_few_bins and rc == 2 and nb.value < 2):
+            _check(rc)
+        return m.value, s.value, n.value, nb.value
+
+    # -- hooks -----------------------------------------------------------
+    @property
+    def sweeps(self) -> int:
+        v = ctypes.c_int64()
+        self._call(self.lib.lattice_sweep_count, ctypes.byref(v))
+        return v.value
+
+    def set_variant(self, name: str):
+        self._call(self.lib.lattice_set_variant, VARIANT[name])
+
+    def set_slab(self, planes: int = 0, xcd_order: bool = True):
+        self._call(self.lib.lattice_set_slab, int(planes), 1 if xcd_order else 0)
+
+    def get_field(self) -> np.ndarray:
+        lx, ly, lz = self.shape
+        out = np.empty((lz, ly, lx), dtype=np.float32)
+        self._call(self.lib.lattice_get_field, _ptr(out))
+        return out
+
+    def set_field(self, phi):
+        lx, ly, lz = self.shape
+        a = np.ascontiguousarray(phi, dtype=np.float32).reshape(lz, ly, lx)
+        self._call(self.lib.lattice_set_field, _ptr(a))
+
+    def last_measure(self):
+        X, Y = ctypes.c_double(), ctypes.c_double()
+        self._call(self.lib.lattice_last_measure, ctypes.byref(X), ctypes.byref(Y))
+        return X.value, Y.value
+
+    def get_state(self):
+        """Returns ``(sweep_counter, n_samples, bins)`` with bins (n, 2)."""
+        t, n, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._call(self.lib.lattice_get_state, ctypes.byref(t), ctypes.byref(n), None, 0, ctypes.byref(nb))
+        bins = np.zeros((max(nb.value, 1), 2), dtype=np.float64)
+        self._call(self.lib.lattice_get_state, ctypes.byref(t), ctypes.byref(n), _ptr(bins), nb.value,
+                   ctypes.byref(nb))
+        return t.value, n.value, bins[:nb.value]
+
+    def set_state(self, sweep_counter: int, n_samples: int, bin_size: int, bins):
+        b = np.ascontiguousarray(bins, dtype=np.float64).reshape(-1, 2)
+        self._call(self.lib.lattice_set_state, int(sweep_counter), int(n_samples), int(bin_size),
+                   _ptr(b), b.shape[0])
+
+
+class Batch:
+    """Independent chains on boxes of uneven size, run in one persistent
+    launch.  ``edges`` is a list of ``(lx, ly, lz)``."""
+
+    def __init__(self, edges, storage: str = "fp32", seed: int = 0, chain_ids=None, device=None,
+                 stream=None, allocator: str = "torch"):
+        import torch
+
+        self.lib = load_library()
+        self.edges = [tuple(int(v) for v in e) for e in edges]
+        self.device, self.stream = _device_and_stream(device, stream)
+        self._mem = _TorchMemory(self.device, self.stream) if allocator == "torch" else None
+        alloc_ptr = ctypes.cast(ctypes.pointer(self._mem.struct), ctypes.c_void_p) if self._mem else None
+        e = np.ascontiguousarray(self.edges, dtype=np.int64).reshape(-1, 3)
+        ids = None
+        if chain_ids is not None:
+            ids = np.ascontiguousarray(chain_ids, dtype=np.uint32)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.batch_create(e.shape[0], _ptr(e), _ptr(ids) if ids is not None else None,
+                                         STORAGE[storage], int(seed), alloc_ptr,
+                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            import torch
+
+            with torch.cuda.device(self.device):
+                self.lib.batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, *args):
+        import torch
+
+        with torch.cuda.device(self.device):
+            _check(fn(self.h, *args))
+
+    def set_charges(self, chain: int, xyz, q):
+        xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        self._call(self.lib.batch_set_charges, int(chain), q.shape[0], _ptr(xyz), _ptr(q))
+
+    def run(self, n_therm: int, n_meas: int, bin_size: int = 100):
+        self._call(self.lib.batch_run, int(n_therm), int(n_meas), int(bin_size))
+
+    def energy_estimate(self, chain: int):
+        m, s = ctypes.c_double(), ctypes.c_double()
+        n, nb = ctypes.c_int64(), ctypes.c_int64()
+        self._call(self.lib.batch_energy_estimate, int(chain), ctypes.byref(m), ctypes.byref(s),
+                   ctypes.byref(n), ctypes.byref(nb))
+        return m.value, s.value, n.value, nb.value
+
+    def get_field(self, chain: int) -> np.ndarray:
+        lx, ly, lz = self.edges[chain]
+        out = np.empty((lz, ly, lx), dtype=np.float32)
+        self._call(self.lib.batch_get_field, int(chain), _ptr(out))
+        return out

@@ -1,0 +1,347 @@
+"""GPU parity of the HIP heat-bath path against the CPU oracle, through the
+C ABI (``paper_1403_0711_amd.lattice`` is argument marshalling only).
+
+Tolerances:
+  * FP32 field, per sweep: max_x |phi_gpu - phi_oracle| <= 1e-5 max_x |phi_oracle|
+    (the update is linear and contracting, so FP32 rounding stays bounded;
+    the oracle computes in FP64 and rounds to FP32).
+  * A sample (X, Y) gathered from a field read back from the GPU matches the
+    oracle's gather of the same field to 1e-12 (FP64 sums, different order).
+  * BF16 / FP16 storage: one storage ulp may flip at a small fraction of
+    sites (FP32 vs FP64 arithmetic before rounding); bounded as stated in the
+    tests.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact as ex
+from paper_1403_0711_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lat_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1403_0711_amd import lattice
+
+    lattice.load_library()
+    return lattice
+
+
+def _field_err(a, b):
+    return float(np.abs(a.astype(np.float64) - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+SHAPES = [
+    ((16, 16, 16), "zslab"),
+    ((40, 24, 9), "zslab"),     # ragged y tile and z slab
+    ((264, 10, 7), "zslab"),    # 33 quads per row: a partial x tile
+    ((8, 1, 3), "zslab"),       # one row per plane: a tile with a single active row
+    ((16, 16, 16), "quad"),
+    ((24, 16, 8), "quad"),
+    ((40, 24, 9), "quad"),      # several tiles + ragged y and z
+    ((16, 16, 16), "generic"),
+    ((10, 6, 5), "generic"),    # lx % 8 != 0: quads straddle rows
+    ((6, 4, 3), "generic"),
+    ((2, 1, 1), "generic"),     # smallest box
+    ((8, 1, 3), "quad"),        # one-row planes
+]
+
+
+@pytest.mark.parametrize("shape,variant", SHAPES)
+def test_field_parity_per_sweep_fp32(lat_mod, shape, variant):
+    print(f"[gpu] field parity {shape} {variant}", flush=True)
+    seed = 0x1234ABCD5678
+    lat = lat_mod.Lattice(shape, "fp32", seed=seed, chain_id=3)
+    lat.set_variant(variant)
+    if variant == "zslab":
+        lat.set_slab(2 if shape[2] > 2 else 1, xcd_order=True)
+    ref = oracle.OracleChain(shape, "fp32", seed=seed, chain=3)
+    for s in range(6):
+        lat.thermalise(1)
+        ref.sweeps(1)
+        err = _field_err(lat.get_field(), ref.phi)
+        assert err <= 1e-5, (s, err)
+    lat.thermalise(60)
+    ref.sweeps(60)
+    assert _field_err(lat.get_field(), ref.phi) <= 1e-5
+    assert lat.sweeps == 66
+    lat.close()
+
+
+def test_variants_agree(lat_mod):
+    """Every sweep kernel computes the same update from the same random
+    numbers; slab depth and workgroup order do not change results."""
+    print("[gpu] variants agree", flush=True)
+    shape = (64, 24, 20)
+    ref = lat_mod.Lattice(shape, seed=7)
+    ref.set_variant("generic")
+    ref.thermalise(20)
+    fr = ref.get_field()
+    slab_fields = []
+    for variant, slab, xcd in (("quad", 0, True), ("zslab", 0, True), ("zslab", 1, False),
+                               ("zslab", 7, True), ("zslab", 20, False)):
+        a = lat_mod.Lattice(shape, seed=7)
+        a.set_variant(variant)
+        a.set_slab(slab, xcd)
+        a.thermalise(20)
+        fa = a.get_field()
+        assert np.abs(fa - fr).max() <= 1e-6 * np.abs(fr).max(), (variant, slab, xcd)
+        if variant == "zslab":
+            slab_fields.append(fa)
+    for f in slab_fields[1:]:
+        np.testing.assert_array_equal(f, slab_fields[0])
+
+
+def test_measure_parity_and_pair_sum(lat_mod):
+    """Samples taken on the GPU equal the oracle's gather of the read-back
+    field; duplicate sites are aggregated without changing X and Y."""
+    print("[gpu] measure parity", flush=True)
+    c = workloads.small_neutral(seed=2, L=16, n=40)
+    xyz = np.concatenate([c.xyz, c.xyz[:5]])  # 5 co-located pairs
+    q = np.concatenate([c.q, np.linspace(-1, 1, 5)])
+    lat = lat_mod.Lattice(c.shape, seed=9)
+    lat.set_charges(xyz, q)
+    ref = oracle.OracleChain(c.shape, seed=9)
+    ref.set_charges(xyz, q)
+    lat.thermalise(10)
+    for _ in range(5):
+        lat.sweep_and_measure(1, 1, 1)
+        phi = lat.get_field().astype(np.float64)
+        ref.phi = phi
+        X, Y = ref.gather()
+        Xg, Yg = lat.last_measure()
+        assert abs(Xg - X) <= 1e-12 * max(1.0, np.sum(np.abs(q)))
+        assert abs(Yg - Y) <= 1e-12 * max(1.0, abs(Y))
+    t, n, bins = lat.get_state()
+    assert n == 5 and bins.shape == (5, 2)
+    assert abs((bins[-1, 0] - bins[-1, 1]) - (Xg * Xg - Yg)) <= 1e-12 * max(1.0, abs(Xg * Xg))
+
+
+def test_estimator_parity_with_oracle_chain(lat_mod):
+    """GPU and oracle run the same chain: their per-sample O agree to the
+    field tolerance and their estimates agree far inside the error bar."""
+    print("[gpu] estimator parity", flush=True)
+    c = workloads.small_neutral(seed=0)
+    lat = lat_mod.Lattice(c.shape, seed=0)
+    lat.set_charges(c.xyz, c.q)
+    ref = oracle.OracleChain(c.shape, seed=0)
+    ref.set_charges(c.xyz, c.q)
+    lat.thermalise(100)
+    ref.sweeps(100)
+    lat.sweep_and_measure(400, 1, 1)
+    s = ref.sweeps(400, 1)
+    _, n, bins = lat.get_state()
+    O_gpu = bins[:, 0] - bins[:, 1]
+    scale = np.sum(np.abs(c.q)) ** 2 * np.abs(ref.phi).max() ** 2
+    assert np.abs(O_gpu - s[:, 2]).max() <= 1e-4 * scale
+    m, se, M, nb = lat.energy_estimate()
+    assert M == 400 and nb == 400
+    assert abs(m - s[:, 2].mean()) <= 1e-4 * scale
+
+
+def test_small_neutral_energy_vs_exact(lat_mod):
+    """16^3, 8 charges: 1e3 thermalisation + 2e5 measured sweeps; the GPU
+    estimate lies within 4 binned standard errors of the exact lattice
+    energy (dense Cholesky of the 4096 x 4096 Laplacian)."""
+    print("[gpu] small neutral vs exact", flush=True)
+    c = workloads.small_neutral(seed=0)
+    e_exact = ex.energy_dense(c.shape, c.xyz, c.q)
+    lat = lat_mod.Lattice(c.shape, seed=0)
+    lat.set_charges(c.xyz, c.q)
+    lat.thermalise(1000)
+    lat.sweep_and_measure(200000, 1, 1000)
+    m, se, M, nb = lat.energy_estimate()
+    assert M == 200000 and nb == 200
+    assert abs(m - e_exact) < 4 * se, (m, se, e_exact)
+    assert se < 0.2 * abs(e_exact) + 0.01
+
+
+def _ulp(v, storage):
+    """Spacing of the storage format at |v|: 2^(e - p) for |v| in
+    [2^(e-1), 2^e), p significant bits; fixed below the smallest normal."""
+    p, emin = (8, -126) if storage == "bf16" else (11, -14)
+    _, e = np.frexp(np.abs(v))
+    e = np.maximum(e - 1, emin)
+    return np.ldexp(1.0, e - p + 1)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_reduced_precision_parity(lat_mod, storage):
+    """16-bit storage, one sweep from a common field, checked half-sweep by
+    half-sweep: each colour's new values equal the oracle's heat-bath values
+    (FP64, rounded to the storage format) computed from the field the GPU
+    actually read, except at under 1% of sites where FP32 vs FP64 arithmetic
+    lands on the other side of a rounding boundary: there by one storage ulp.
+    After 30 more sweeps the field stays within a few ulps of the oracle's
+    chain (the map contracts)."""
+    print(f"[gpu] reduced precision {storage}", flush=True)
+    shape = (24, 16, 12)
+    lx, ly, lz = shape
+    lat = lat_mod.Lattice(shape, storage, seed=5)
+    ref = oracle.OracleChain(shape, storage, seed=5)
+    rng = np.random.default_rng(0)
+    start = rng.standard_normal(shape[::-1]).astype(np.float32) * 0.5
+    lat.set_field(start)
+    ref.set_field(start.astype(np.float64))
+    np.testing.assert_array_equal(lat.get_field().astype(np.float64), ref.phi)
+    lat.thermalise(1)
+    g = lat.get_field()
+    colour = (np.arange(lz)[:, None, None] + np.arange(ly)[None, :, None] + np.arange(lx)[None, None, :]) & 1
+    mid = np.where(colour == 1, ref.phi.astype(np.float32), g)  # field after the colour-0 half-sweep
+    for c, src in ((0, ref.phi.astype(np.float32)), (1, mid)):
+        zz, yy, xx = np.nonzero(colour == c)
+        pts = np.stack([xx, yy, zz], axis=1)
+        vals = oracle.site_values_f32(src, pts, 5, 0, c)
+        want = np.array([oracle.round_storage(v, storage) for v in vals])
+        got = g[zz, yy, xx].astype(np.float64)
+        diff = np.abs(got - want)
+        assert (diff > 0).mean() < 0.01, c
+        assert np.all(diff <= np.maximum(_ulp(got, storage), _ulp(want, storage))), c
+    ref.sweeps(1)
+    lat.thermalise(30)
+    ref.sweeps(30)
+    g = lat.get_field().astype(np.float64)
+    scale = np.abs(ref.phi).max()
+    assert np.abs(g - ref.phi).max() <= 8 * _ulp(np.array([scale]), storage)[0]
+
+
+def test_checkpoint_resume_bit_identical(lat_mod):
+    print("[gpu] checkpoint/resume", flush=True)
+    c = workloads.small_neutral(seed=1, L=16, n=12)
+    a = lat_mod.Lattice(c.shape, seed=77)
+    a.set_charges(c.xyz, c.q)
+    a.thermalise(50)
+    a.sweep_and_measure(300, 1, 10)
+    b = lat_mod.Lattice(c.shape, seed=77)
+    b.set_charges(c.xyz, c.q)
+    b.thermalise(50)
+    b.sweep_and_measure(150, 1, 10)
+    t, n, bins = b.get_state()
+    phi = b.get_field()
+    b.close()
+    r = lat_mod.Lattice(c.shape, seed=77)
+    r.set_charges(c.xyz, c.q)
+    r.set_field(phi)
+    r.set_state(t, n, 10, bins)
+    r.sweep_and_measure(150, 1, 10)
+    np.testing.assert_array_equal(r.get_field(), a.get_field())
+    ta, na, ba = a.get_state()
+    tr, nr, br = r.get_state()
+    assert (ta, na) == (tr, nr)
+    np.testing.assert_array_equal(ba, br)
+    assert a.energy_estimate() == r.energy_estimate()
+
+
+def test_empty_charges_and_edge_cases(lat_mod):
+    print("[gpu] edge cases", flush=True)
+    lat = lat_mod.Lattice((8, 8, 8), seed=1)
+    lat.set_charges(np.zeros((0, 3), np.int32), np.zeros(0))
+    lat.sweep_and_measure(20, 2, 5)
+    m, se, M, nb = lat.energy_estimate()
+    assert (m, se, M, nb) == (0.0, 0.0, 10, 2)
+    # fewer than 2 full bins -> LAT_ERR_STATE, outputs still written
+    lat2 = lat_mod.Lattice((8, 8, 8), seed=1)
+    lat2.set_charges([[1, 1, 1]], [1.0])
+    lat2.sweep_and_measure(3, 1, 2)
+    with pytest.raises(lat_mod.LatticeError) as ei:
+        lat2.energy_estimate()
+    assert ei.value.code == 2
+    m, se, M, nb = lat2.energy_estimate(allow_few_bins=True)
+    assert M == 3 and nb == 1 and np.isnan(se)
+
+
+def test_argument_errors(lat_mod):
+    print("[gpu] argument errors", flush=True)
+    lat = lat_mod.Lattice((8, 6, 4), seed=1)
+    with pytest.raises(lat_mod.LatticeError) as ei:
+        lat.set_charges([[8, 0, 0]], [1.0])
+    assert ei.value.code == 1
+    with pytest.raises(lat_mod.LatticeError):
+        lat.set_charges([[1, 1, 1]], [np.nan])
+    lat.set_charges([[1, 1, 1], [2, 2, 2]], [1.0, -1.0])
+    lat.sweep_and_measure(4, 1, 2)
+    with pytest.raises(lat_mod.LatticeError) as ei:
+        lat.sweep_and_measure(4, 1, 3)  # bin size changed
+    assert ei.value.code == 1
+    with pytest.raises(lat_mod.LatticeError):
+        lat.sweep_and_measure(4, 0, 2)
+    with pytest.raises(lat_mod.LatticeError):
+        lat.set_field(np.full((4, 6, 8), np.inf, np.float32))
+    lat.set_variant("quad")  # lx = 8: lh = 4, accepted
+    with pytest.raises(lat_mod.LatticeError):
+        lat_mod.Lattice((6, 6, 6)).set_variant("quad")  # lh = 3: rejected
+    # a state with a failed call is unchanged
+    assert lat.sweeps == 4
+
+
+def test_allocator_failure_reports_alloc_error(lat_mod):
+    """A provider that returns NULL gives LAT_ERR_ALLOC, not a crash."""
+    import ctypes
+
+    print("[gpu] allocator failure", flush=True)
+    lib = lat_mod.load_library()
+    fail = lat_mod.ALLOC_FN(lambda ctx, n: None)
+    rel = lat_mod.RELEASE_FN(lambda ctx, p: None)
+    a = lat_mod.LatAllocator(None, fail, rel)
+    h = ctypes.c_void_p()
+    rc = lib.lattice_create(8, 8, 8, 0, 0, 0, ctypes.cast(ctypes.pointer(a), ctypes.c_void_p), None,
+                            ctypes.byref(h))
+    assert rc == 3 and not h.value
+    assert b"allocation" in lib.lattice_last_error()
+
+
+def _sampled_sweep_parity(lat_mod, shape, variant, n_samples=4096, storage="fp32"):
+    """One sweep of a large lattice from a seeded random field; sampled sites
+    of each colour are recomputed one by one by the oracle from the read-back
+    fields (colour 0 from the field before the sweep, colour 1 from the field
+    after it), and the untouched-colour invariant is checked everywhere."""
+    lx, ly, lz = shape
+    seed = 99
+    lat = lat_mod.Lattice(shape, storage, seed=seed, chain_id=1)
+    lat.set_variant(variant)
+    rng = np.random.default_rng(0)
+    start = (rng.standard_normal((lz, ly, lx), dtype=np.float32) * 0.5)
+    lat.set_field(start)
+    lat.thermalise(3)  # counter t = 3 at the checked sweep
+    before = lat.get_field()
+    lat.thermalise(1)
+    after = lat.get_field()
+    colour = ((np.arange(lz, dtype=np.int16)[:, None, None] + np.arange(ly, dtype=np.int16)[None, :, None]
+               + np.arange(lx, dtype=np.int16)[None, None, :]) & 1).astype(bool)
+    # the other colour is untouched by each half-sweep, so after the sweep
+    # colour 1 holds new values and colour 0 the values colour 1 was drawn from
+    mid = np.where(colour, before, after)  # field after the colour-0 half-sweep
+    del colour
+    for c, src in ((0, before), (1, mid)):
+        pts = []
+        while len(pts) < n_samples:
+            s = rng.integers(0, [lx, ly, lz], size=(n_samples, 3))
+            s = s[(s.sum(axis=1) & 1) == c]
+            pts.extend(s.tolist())
+        # include the box corners and faces of this colour
+        extra = [(a, b, d) for a in (0, lx - 1) for b in (0, ly - 1) for d in (0, lz - 1) if (a + b + d) & 1 == c]
+        pts = np.array(pts[:n_samples] + extra, dtype=np.int64)
+        ref = oracle.site_values_f32(src, pts, seed, 1, 2 * 3 + c)
+        got = after[pts[:, 2], pts[:, 1], pts[:, 0]].astype(np.float64)
+        assert np.abs(got - ref).max() <= 2e-6 * max(1.0, np.abs(ref).max()), c
+    return before, after
+
+
+@pytest.mark.parametrize("variant", ["quad", "zslab"])
+def test_sampled_parity_large(lat_mod, variant):
+    print(f"[gpu] sampled parity 256^3 {variant}", flush=True)
+    _sampled_sweep_parity(lat_mod, (256, 256, 256), variant)
+
+
+def test_sampled_parity_largest_box(lat_mod):
+    """768^3 (the largest one-GPU machine benchmarked), with the kernel and launch
+    configuration the benchmark times (library default)."""
+    print("[gpu] sampled parity 768^3", flush=True)
+    _sampled_sweep_parity(lat_mod, (768, 768, 768), "auto", n_samples=2048)
