@@ -143,11 +143,12 @@ int lattice_sweep_count(const lattice_t *lat, int64_t *sweeps);
  * cannot handle this box. */
 int lattice_set_variant(lattice_t *lat, int variant);
 
-/* Tuning of the slab kernels (LAT_SWEEP_ZSLAB, LAT_SWEEP_FUSED): planes of
- * the box one workgroup walks along z (0 = library default, at most lz), and
+/* Tuning of the slab kernel (LAT_SWEEP_ZSLAB): planes of the box one
+ * workgroup walks along z (0 = library default, at most lz); tile
+ * configuration 0..7 (workgroup tile width x rows and register budget);
  * whether workgroups are ordered so that each of the chip's 8 XCDs gets a
- * contiguous run of tiles.  Results do not depend on either. */
-int lattice_set_slab(lattice_t *lat, int64_t planes, int xcd_order);
+ * contiguous run of tiles.  Results do not depend on any of them. */
+int lattice_set_tuning(lattice_t *lat, int64_t planes, int tile, int xcd_order);
 
 /* ---- test / checkpoint hooks (all synchronise the stream) ---------- */
 

@@ -1,0 +1,141 @@
+// Batched chains: many independent heat-bath chains on boxes of uneven size
+// in one persistent launch.  Workgroup b runs chain order[b] (chains sorted
+// largest first, so the longest chains start first) through all its sweeps:
+// colour-0 half-sweep, workgroup barrier, colour-1 half-sweep, barrier, and
+// after each measured sweep the gather of X = sum Q phi, Y = sum S phi^2 over
+// the chain's charges, O = X^2 - Y and its compensated add into the chain's
+// bin.  Only one workgroup touches a chain, so a workgroup barrier (which
+// orders the workgroup's global stores before its later loads) is the only
+// synchronisation.  Each site draws exactly the random numbers of a single
+// lattice with the chain's id (same Philox counter layout).
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace latcoul {
+
+constexpr int kBatchThreads = 512;
+
+// One half-sweep of colour c over a whole chain by one workgroup: 4 compact
+// sites of one row per iteration when lh % 4 == 0, else one site.
+template <class St>
+__device__ __forceinline__ void chain_halfsweep(typename St::T* field, const BatchChainDesc& d, uint32_t c,
+                                                uint32_t h, uint32_t k0, uint32_t k1) {
+    using T = typename St::T;
+    const T* other = field + (size_t)(c ^ 1u) * d.vh;
+    T* own = field + (size_t)c * d.vh;
+    const uint32_t lh = d.lh, ly = d.ly, lz = d.lz, plane = ly * lh;
+    const float sixth = 1.0f / 6.0f;
+    if ((lh & 3u) == 0) {
+        const uint32_t nq = lh >> 2, nquads = d.vh >> 2;
+        for (uint32_t qi = threadIdx.x; qi < nquads; qi += kBatchThreads) {
+            const uint32_t q = qi % nq, rowi = qi / nq;
+            const uint32_t y = rowi % ly, z = rowi / ly;
+            const uint32_t p = (c + y + z) & 1u;
+            const uint32_t j0 = rowi * lh + 4u * q;
+            const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 cen = St::ld4(other, j0);
+            const float4 ym = y > 0 ? St::ld4(other, j0 - lh) : zero;
+            const float4 yp = y + 1 < ly ? St::ld4(other, j0 + lh) : zero;
+            const float4 zm = z > 0 ? St::ld4(other, j0 - plane) : zero;
+            const float4 zp = z + 1 < lz ? St::ld4(other, j0 + plane) : zero;
+            float a0, a1, a2, a3;
+            if (p == 0) {
+                const float e = q > 0 ? St::ld(other, j0 - 1) : 0.f;
+                a0 = e + cen.x;
+                a1 = cen.x + cen.y;
+                a2 = cen.y + cen.z;
+                a3 = cen.z + cen.w;
+            } else {
+                const float e = q + 1 < nq ? St::ld(other, j0 + 4) : 0.f;
+                a0 = cen.x + cen.y;
+                a1 = cen.y + cen.z;
+                a2 = cen.z + cen.w;
+                a3 = cen.w + e;
+            }
+            const uint4 r = philox4x32_10(j0 >> 2, h, d.chain_id, 0u, k0, k1);
+            float4 out;
+            out.x = fmaf(a0 + ym.x + yp.x + zm.x + zp.x, sixth, heatbath_noise(r.x));
+            out.y = fmaf(a1 + ym.y + yp.y + zm.y + zp.y, sixth, heatbath_noise(r.y));
+            out.z = fmaf(a2 + ym.z + yp.z + zm.z + zp.z, sixth, heatbath_noise(r.z));
+            out.w = fmaf(a3 + ym.w + yp.w + zm.w + zp.w, sixth, heatbath_noise(r.w));
+            St::st4(own, j0, out);
+        }
+    } else {
+        for (uint32_t j = threadIdx.x; j < d.vh; j += kBatchThreads) {
+            const uint32_t hx = j % lh, rowi = j / lh;
+            const uint32_t y = rowi % ly, z = rowi / ly;
+            const uint32_t p = (c + y + z) & 1u;
+            float s = 0.f;
+            if (hx + p >= 1) s += St::ld(other, j - 1 + p);
+            if (hx + p < lh) s += St::ld(other, j + p);
+            if (y > 0) s += St::ld(other, j - lh);
+            if (y + 1 < ly) s += St::ld(other, j + lh);
+            if (z > 0) s += St::ld(other, j - plane);
+            if (z + 1 < lz) s += St::ld(other, j + plane);
+            const uint4 r = philox4x32_10(j >> 2, h, d.chain_id, 0u, k0, k1);
+            const uint32_t w = (j & 3u) == 0 ? r.x : (j & 3u) == 1 ? r.y : (j & 3u) == 2 ? r.z : r.w;
+            St::st(own, j, fmaf(s, sixth, heatbath_noise(w)));
+        }
+    }
+}
+
+template <class St>
+__global__ __launch_bounds__(kBatchThreads) void batch_chains(typename St::T* __restrict__ fields,
+                                                              const BatchChainDesc* __restrict__ desc,
+                                                              const uint32_t* __restrict__ order,
+                                                              const uint32_t* __restrict__ site,
+                                                              const double* __restrict__ Q,
+                                                              const double* __restrict__ S, double* bins,
+                                                              uint32_t t0, uint32_t n_therm, uint32_t n_meas,
+                                                              uint32_t bin_size, uint32_t k0, uint32_t k1) {
+    const BatchChainDesc d = desc[order[blockIdx.x]];
+    typename St::T* field = fields + d.field_off;
+    const typename St::T* cfield = field;
+    const uint32_t n_sweeps = n_therm + n_meas;
+    for (uint32_t s = 0; s < n_sweeps; ++s) {
+        const uint32_t t = t0 + s;
+        chain_halfsweep<St>(field, d, 0u, 2u * t, k0, k1);
+        __syncthreads();
+        chain_halfsweep<St>(field, d, 1u, 2u * t + 1u, k0, k1);
+        __syncthreads();
+        if (s >= n_therm) {
+            double x = 0.0, y = 0.0;
+            for (uint32_t i = d.site_off + threadIdx.x; i < d.site_off + d.n_sites; i += kBatchThreads) {
+                const double v = (double)St::ld(cfield, site[i]);
+                x = fma(Q[i], v, x);
+                y = fma(S[i], v * v, y);
+            }
+            block_sum2<kBatchThreads>(x, y);  // ends with a barrier
+            if (threadIdx.x == 0) {
+                const uint32_t b = d.bin_off + (d.meas0 + (s - n_therm)) / bin_size;
+                const double O = x * x - y;
+                double sum = bins[2 * b], comp = bins[2 * b + 1];
+                const double yk = O - comp;
+                const double tk = sum + yk;
+                comp = (tk - sum) - yk;
+                bins[2 * b] = tk;
+                bins[2 * b + 1] = comp;
+            }
+        }
+    }
+}
+
+template <class St>
+static hipError_t launch_batch_t(const BatchArgs& a, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_chains<St>, dim3(a.n_chains), dim3(kBatchThreads), 0, stream,
+                       static_cast<typename St::T*>(a.field), a.desc, a.order, a.site, a.Q, a.S, a.bins, a.t0,
+                       a.n_therm, a.n_meas, a.bin_size, a.k0, a.k1);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& a, hipStream_t stream) {
+    switch (a.storage) {
+        case 0: return launch_batch_t<StoreF32>(a, stream);
+        case 1: return launch_batch_t<StoreBF16>(a, stream);
+        case 2: return launch_batch_t<StoreF16>(a, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace latcoul

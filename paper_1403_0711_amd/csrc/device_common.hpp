@@ -22,6 +22,12 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
+// a ^ b ^ c in one v_bitop3_b32 (gfx950's three-input bitwise op, truth
+// table 0x96 = odd parity)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -30,8 +36,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
         // (full rate on gfx950) instead of separate low and high multiplies
         const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c0 = n0;
         c1 = (uint32_t)p1;
         c2 = n2;
@@ -51,23 +57,25 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 // (erfinv_coeffs.h, max relative error 3.3e-7 on the grid).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float grid_s(uint32_t u) {
-    const int t = (int)((u >> 7) | 1u) - (1 << 24);  // 2k + 1 - 2^24, |t| < 2^24: exact in FP32
-    return (float)t * 0x1p-24f;
+    // ((u & ~0xFF) | 0x80) = 2^7 (2k + 1); flipping bit 31 subtracts 2^31, so as
+    // a signed integer it is 2^7 (2k + 1 - 2^24): |.| < 2^31 with 24 significant
+    // bits, exact in FP32.  Two integer ops (v_and_or_b32, v_xor_b32).
+    const uint32_t v = ((u & 0xFFFFFF00u) | 0x80u) ^ 0x80000000u;
+    return (float)(int)v * 0x1p-31f;
 }
 
 __device__ __forceinline__ float heatbath_noise(uint32_t u) {
     const float s = grid_s(u);
     const float omx2 = fmaf(-s, s, 1.0f);  // 1 - s^2, one rounding
-    // v_log_f32 is log2; w = -ln(1 - s^2)
-    const float w = -0.69314718055994531f * __builtin_amdgcn_logf(omx2);
+    // v_log_f32 is log2: w - 2.5 = -ln(1 - s^2) - 2.5 in one fma
+    const float wm = fmaf(__builtin_amdgcn_logf(omx2), -0.69314718055994531f, -2.5f);
     float p;
-    if (w < LATCOUL_ERFINV_W_SPLIT) {
-        const float x = w - 2.5f;
+    if (wm < LATCOUL_ERFINV_W_SPLIT - 2.5f) {
         p = kErfinvP[8];
 #pragma unroll
-        for (int i = 7; i >= 0; --i) p = fmaf(p, x, kErfinvP[i]);
+        for (int i = 7; i >= 0; --i) p = fmaf(p, wm, kErfinvP[i]);
     } else {
-        const float x = __builtin_amdgcn_sqrtf(w) - 3.0f;
+        const float x = __builtin_amdgcn_sqrtf(wm + 2.5f) - 3.0f;
         p = kErfinvQ[8];
 #pragma unroll
         for (int i = 7; i >= 0; --i) p = fmaf(p, x, kErfinvQ[i]);
@@ -76,20 +84,53 @@ __device__ __forceinline__ float heatbath_noise(uint32_t u) {
 }
 
 // ---------------------------------------------------------------------------
+// Raw buffer loads.  A buffer resource carries the array's size; a load at a
+// byte offset >= that size returns 0 and fetches nothing (gfx9-family range
+// check of raw buffers).  Kernels use this for Dirichlet ghosts and for lanes
+// with nothing to load: such lanes get offset kNoLoad, which is out of range
+// whenever the array is below 2 GiB (checked on the host), so no lane needs
+// a predicate or a zeroing move.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kNoLoad = 0x80000000u;
+constexpr int kRawBufferDword3 = 0x00020000;  // gfx9-family raw buffer: no format conversion
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRawBufferDword3);
+}
+
+__device__ __forceinline__ float4 bload_f32x4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
+}
+__device__ __forceinline__ float bload_f32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// ---------------------------------------------------------------------------
 // Field storage formats: FP32, BF16, FP16.  Arithmetic is always FP32; a
 // stored value is rounded to nearest even.
 // ---------------------------------------------------------------------------
+// Element i of an array as a 32-bit byte offset from its base (every array
+// here is below 4 GiB), so loads use an SGPR base plus a VGPR offset instead
+// of a 64-bit address per lane.
+template <class V, class T>
+__device__ __forceinline__ const V& at(const T* p, uint32_t i) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(p) + i * (uint32_t)sizeof(T));
+}
+template <class V, class T>
+__device__ __forceinline__ V& at(T* p, uint32_t i) {
+    return *reinterpret_cast<V*>(reinterpret_cast<char*>(p) + i * (uint32_t)sizeof(T));
+}
+
 struct StoreF32 {
     using T = float;
     static constexpr int kBytes = 4;
-    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return p[i]; }
-    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) {
-        return *reinterpret_cast<const float4*>(p + i);
-    }
-    __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) {
-        *reinterpret_cast<float4*>(p + i) = v;
-    }
-    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { p[i] = v; }
+    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return at<float>(p, i); }
+    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) { return at<float4>(p, i); }
+    __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) { at<float4>(p, i) = v; }
+    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<float>(p, i) = v; }
+    __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32x4(r, off); }
+    __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32(r, off); }
 };
 
 __device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
@@ -101,9 +142,9 @@ __device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as
 struct StoreBF16 {
     using T = uint16_t;
     static constexpr int kBytes = 2;
-    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return bf16_to_f32(p[i]); }
+    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return bf16_to_f32(at<uint16_t>(p, i)); }
     __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) {
-        const uint2 w = *reinterpret_cast<const uint2*>(p + i);
+        const uint2 w = at<uint2>(p, i);
         return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
                            __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
     }
@@ -111,18 +152,26 @@ struct StoreBF16 {
         uint2 w;
         w.x = bf16_rne_bits(v.x) | (bf16_rne_bits(v.y) << 16);
         w.y = bf16_rne_bits(v.z) | (bf16_rne_bits(v.w) << 16);
-        *reinterpret_cast<uint2*>(p + i) = w;
+        at<uint2>(p, i) = w;
     }
-    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { p[i] = (T)bf16_rne_bits(v); }
+    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<uint16_t>(p, i) = (T)bf16_rne_bits(v); }
+    __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return make_float4(__uint_as_float(w[0] << 16), __uint_as_float(w[0] & 0xFFFF0000u),
+                           __uint_as_float(w[1] << 16), __uint_as_float(w[1] & 0xFFFF0000u));
+    }
+    __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+    }
 };
 
 struct StoreF16 {
     using T = _Float16;
     static constexpr int kBytes = 2;
-    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return (float)p[i]; }
+    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return (float)at<_Float16>(p, i); }
     __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) {
         typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        const h4 w = *reinterpret_cast<const h4*>(p + i);
+        const h4 w = at<h4>(p, i);
         return make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
     }
     __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) {
@@ -132,9 +181,18 @@ struct StoreF16 {
         w[1] = (_Float16)v.y;
         w[2] = (_Float16)v.z;
         w[3] = (_Float16)v.w;
-        *reinterpret_cast<h4*>(p + i) = w;
+        at<h4>(p, i) = w;
     }
-    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { p[i] = (_Float16)v; }
+    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<_Float16>(p, i) = (_Float16)v; }
+    __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        const h4 hv = __builtin_bit_cast(h4, w);
+        return make_float4((float)hv[0], (float)hv[1], (float)hv[2], (float)hv[3]);
+    }
+    __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+    }
 };
 
 // ---------------------------------------------------------------------------

@@ -19,7 +19,9 @@ struct SweepArgs {
     int variant;      // kVariantQuad / kVariantGeneric / kVariantZslab
     uint32_t zc;      // zslab: planes per workgroup (0 = default)
     uint32_t xcd_order;  // zslab: XCD-aware block order
+    uint32_t tile;    // zslab: tile configuration, 0 .. kZslabTiles - 1
 };
+constexpr int kZslabTiles = 8;
 hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream);
 
 // Both half-sweeps of sweep t in one pass (z-marching slabs), lh % 4 == 0.
@@ -43,7 +45,6 @@ struct MeasureArgs {
     const double* S;       // sum of q^2 on the site
     uint32_t n;            // number of charged sites
     double* partials;      // 2 * blocks scratch
-    uint32_t* ticket;      // zero between launches
     double* bins;
     uint32_t bin;
     double* last_xy;       // X, Y of this sample
@@ -60,7 +61,7 @@ struct BatchChainDesc {
     uint32_t chain_id;
     uint32_t site_off, n_sites;  // range in the concatenated charge arrays
     uint32_t bin_off;            // first bin slot of this chain (2 doubles each)
-    uint32_t pad;
+    uint32_t meas0;              // samples this chain already holds
 };
 struct BatchArgs {
     void* field;
@@ -73,7 +74,6 @@ struct BatchArgs {
     double* bins;
     uint32_t t0;        // sweep counter at the start of this run (same for all chains)
     uint32_t n_therm, n_meas, bin_size;
-    uint32_t meas0;     // samples already taken (same for all chains)
     uint32_t k0, k1;
     int storage;
     uint32_t threads;   // workgroup size

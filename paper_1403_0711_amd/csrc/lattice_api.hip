@@ -33,7 +33,7 @@ struct lattice {
     double* d_S = nullptr;
     double* d_partials = nullptr;
     uint32_t meas_blocks = 1;
-    // misc block: ticket (uint32 at 0), last X, Y (doubles at 64)
+    // misc block: last X, Y (doubles at 64)
     void* d_misc = nullptr;
     // samples
     double* d_bins = nullptr;
@@ -44,14 +44,16 @@ struct lattice {
     int variant = LAT_SWEEP_AUTO;
     uint32_t slab = 16;      // planes per workgroup for the slab kernels (0 = kernel default)
     uint32_t xcd_order = 1;  // XCD-aware workgroup order for the slab kernels
+    uint32_t tile = 0;       // tile configuration of the slab kernel
 
-    uint32_t* ticket() { return static_cast<uint32_t*>(d_misc); }
     double* last_xy() { return reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
     int effective_variant() const {
         if (variant != LAT_SWEEP_AUTO) return variant;
         if (lh % 4 != 0) return LAT_SWEEP_GENERIC;
         // boxes that spill out of the 256 MB last-level cache: z-marching slabs
-        return (size_t)2 * vh * esz > ((size_t)256 << 20) ? LAT_SWEEP_ZSLAB : LAT_SWEEP_QUAD;
+        // (whose colour arrays must stay below 2 GiB)
+        const size_t bytes = (size_t)vh * esz;
+        return (2 * bytes > ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) ? LAT_SWEEP_ZSLAB : LAT_SWEEP_QUAD;
     }
 };
 
@@ -73,7 +75,7 @@ static int enqueue_sweep(lattice* L) {
         const int kv = v == LAT_SWEEP_QUAD ? kVariantQuad : v == LAT_SWEEP_ZSLAB ? kVariantZslab : kVariantGeneric;
         SweepArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, 0u, h0,
                     (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, kv, L->slab,
-                    L->xcd_order};
+                    L->xcd_order, L->tile};
         e = launch_halfsweep(a, L->stream);
         if (e == hipSuccess) {
             a.c = 1u;
@@ -87,7 +89,7 @@ static int enqueue_sweep(lattice* L) {
 }
 
 static int enqueue_measure(lattice* L) {
-    MeasureArgs a{L->field, L->d_site, L->d_Q, L->d_S, L->n_sites, L->d_partials, L->ticket(),
+    MeasureArgs a{L->field, L->d_site, L->d_Q, L->d_S, L->n_sites, L->d_partials,
                   L->d_bins, (uint32_t)(L->n_meas / L->bin_size), L->last_xy(), L->storage,
                   L->meas_blocks};
     hipError_t e = launch_measure(a, L->stream);
@@ -183,8 +185,12 @@ int lattice_set_variant(lattice_t* L, int variant) {
         case LAT_SWEEP_AUTO:
         case LAT_SWEEP_GENERIC: break;
         case LAT_SWEEP_QUAD:
+            if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
+            break;
         case LAT_SWEEP_ZSLAB:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
+            if ((size_t)L->vh * L->esz >= ((size_t)1 << 31))
+                return set_error(LAT_ERR_ARG, "slab kernel needs each colour array below 2 GiB");
             break;
         case LAT_SWEEP_FUSED:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "fused sweep needs lx % 8 == 0");
@@ -197,10 +203,12 @@ int lattice_set_variant(lattice_t* L, int variant) {
     return LAT_OK;
 }
 
-int lattice_set_slab(lattice_t* L, int64_t planes, int xcd_order) {
+int lattice_set_tuning(lattice_t* L, int64_t planes, int tile, int xcd_order) {
     if (int r = check_lattice(L)) return r;
     if (planes < 0 || planes > L->lz) return set_error(LAT_ERR_ARG, "planes must be in [0, lz]");
+    if (tile < 0 || tile >= kZslabTiles) return set_error(LAT_ERR_ARG, "unknown tile configuration");
     L->slab = (uint32_t)planes;
+    L->tile = (uint32_t)tile;
     L->xcd_order = xcd_order ? 1u : 0u;
     return LAT_OK;
 }

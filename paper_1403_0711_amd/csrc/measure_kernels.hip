@@ -3,11 +3,13 @@
 // X = sum_i q_i phi(n_i) and Y = sum_i q_i^2 phi(n_i)^2 are gathered from the
 // site-aggregated charge list (Q_s = sum of q on site s, S_s = sum of q^2),
 // which gives the same X and Y as the raw list.  Accumulation is FP64.  The
-// reduction has a fixed shape: each thread sums a fixed strided subset, waves
-// reduce by DPP, blocks write partials, and the last block to finish (integer
-// ticket) adds the partials in block order.  So the result does not depend on
-// scheduling.  The last block forms O = X^2 - Y and adds it to its bin with a
-// compensated (Kahan) FP64 sum; this replaces the paper's global reduce.
+// reduction has a fixed shape, so the result does not depend on scheduling:
+// each thread sums a fixed strided subset, waves reduce by DPP, and each block
+// writes one partial (X_b, Y_b).  A second one-block launch adds the partials
+// in block order, forms O = X^2 - Y and adds it to its bin with a compensated
+// (Kahan) FP64 sum; this replaces the paper's global reduce.  The kernel
+// boundary orders the two phases, so no device-scope fence or atomic is
+// needed (a device-scope release on this multi-XCD chip writes back L2).
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -15,46 +17,56 @@
 namespace latcoul {
 
 constexpr int kMeasureThreads = 256;
+constexpr int kGatherUnroll = 4;
 
 uint32_t measure_blocks(uint32_t n) {
-    // about 4 charged sites per thread, at most 2048 blocks
-    uint32_t b = (n + kMeasureThreads * 4 - 1) / (kMeasureThreads * 4);
+    // kGatherUnroll charged sites per thread per pass, at most 2048 blocks
+    uint32_t b = (n + kMeasureThreads * kGatherUnroll - 1) / (kMeasureThreads * kGatherUnroll);
     if (b < 1) b = 1;
     if (b > 2048) b = 2048;
     return b;
 }
 
 template <class St>
-__global__ __launch_bounds__(kMeasureThreads) void gather_measure(
-    const typename St::T* __restrict__ field, const uint32_t* __restrict__ site,
-    const double* __restrict__ Q, const double* __restrict__ S, uint32_t n,
-    double* __restrict__ partials, uint32_t* ticket, double* bins, uint32_t bin, double* last_xy) {
+__global__ __launch_bounds__(kMeasureThreads) void gather_partials(const typename St::T* __restrict__ field,
+                                                                   const uint32_t* __restrict__ site,
+                                                                   const double* __restrict__ Q,
+                                                                   const double* __restrict__ S, uint32_t n,
+                                                                   double* __restrict__ partials) {
     double x = 0.0, y = 0.0;
     const uint32_t stride = gridDim.x * kMeasureThreads;
-    for (uint32_t i = blockIdx.x * kMeasureThreads + threadIdx.x; i < n; i += stride) {
-        const double v = (double)St::ld(field, site[i]);
-        x = fma(Q[i], v, x);
-        y = fma(S[i], v * v, y);
+    uint32_t i = blockIdx.x * kMeasureThreads + threadIdx.x;
+    // kGatherUnroll independent loads in flight per thread
+    for (; i + (kGatherUnroll - 1) * stride < n; i += kGatherUnroll * stride) {
+        float v[kGatherUnroll];
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) v[u] = St::ld(field, site[i + u * stride]);
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+            const double d = (double)v[u];
+            x = fma(Q[i + u * stride], d, x);
+            y = fma(S[i + u * stride], d * d, y);
+        }
+    }
+    for (; i < n; i += stride) {
+        const double d = (double)St::ld(field, site[i]);
+        x = fma(Q[i], d, x);
+        y = fma(S[i], d * d, y);
     }
     block_sum2<kMeasureThreads>(x, y);
-
-    __shared__ uint32_t s_last;
     if (threadIdx.x == 0) {
         partials[2 * blockIdx.x] = x;
         partials[2 * blockIdx.x + 1] = y;
-        __threadfence();
-        const uint32_t prev = atomicAdd(ticket, 1u);
-        s_last = (prev == gridDim.x - 1) ? 1u : 0u;
     }
-    __syncthreads();
-    if (!s_last) return;
+}
 
-    // last block: add the partials in block order
-    __threadfence();
+__global__ __launch_bounds__(kMeasureThreads) void finalize_measure(const double* __restrict__ partials,
+                                                                    uint32_t blocks, double* bins, uint32_t bin,
+                                                                    double* last_xy) {
     double X = 0.0, Y = 0.0;
-    for (uint32_t b = threadIdx.x; b < gridDim.x; b += kMeasureThreads) {
-        X += __hip_atomic_load(&partials[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        Y += __hip_atomic_load(&partials[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t b = threadIdx.x; b < blocks; b += kMeasureThreads) {
+        X += partials[2 * b];
+        Y += partials[2 * b + 1];
     }
     block_sum2<kMeasureThreads>(X, Y);
     if (threadIdx.x == 0) {
@@ -70,15 +82,15 @@ __global__ __launch_bounds__(kMeasureThreads) void gather_measure(
         bins[2 * bin + 1] = comp;
         last_xy[0] = X;
         last_xy[1] = Y;
-        *ticket = 0u;
     }
 }
 
 template <class St>
 static hipError_t launch_measure_t(const MeasureArgs& a, hipStream_t stream) {
-    hipLaunchKernelGGL(gather_measure<St>, dim3(a.blocks), dim3(kMeasureThreads), 0, stream,
-                       static_cast<const typename St::T*>(a.field), a.site, a.Q, a.S, a.n,
-                       a.partials, a.ticket, a.bins, a.bin, a.last_xy);
+    hipLaunchKernelGGL(gather_partials<St>, dim3(a.blocks), dim3(kMeasureThreads), 0, stream,
+                       static_cast<const typename St::T*>(a.field), a.site, a.Q, a.S, a.n, a.partials);
+    hipLaunchKernelGGL(finalize_measure, dim3(1), dim3(kMeasureThreads), 0, stream, a.partials, a.blocks,
+                       a.bins, a.bin, a.last_xy);
     return hipGetLastError();
 }
 

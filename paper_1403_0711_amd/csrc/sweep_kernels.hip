@@ -101,25 +101,108 @@ __global__ __launch_bounds__(256) void halfsweep_generic(const typename St::T* _
 }
 
 // z-marching slab (2.5-D blocking): a workgroup owns a tile of kTX quads x
-// kTY rows and walks `zc` planes along z.  Planes z-1 and z+1 of the other
+// kTY rows and walks `zc` planes along z.  Planes z-1, z and z+1 of the other
 // colour stay in registers (each plane is loaded once per tile); plane z is
-// staged in double-buffered LDS with its two halo rows (y0-1, y0+kTY) and the
-// two x-edge columns, which give the y- and x-neighbours.  One barrier per
-// plane: with two buffers a thread can only overwrite buffer s-1 after every
-// thread has passed the barrier of step s, i.e. finished its reads of s-1.
-// Global loads per 4 sites: one float4 plus 2/kTY halo rows and 2/(4 kTX)
-// edges.  Optional XCD-aware order: hardware block b runs on XCD b % 8, so
-// b -> (b % 8) * (nb / 8) + b / 8 gives each XCD a contiguous run of tiles
-// (neighbouring tiles share halo rows in that XCD's L2).
+// also staged in double-buffered LDS with its two halo rows (y0-1, y0+kTY)
+// and the two x-edge columns, which give the y- and x-neighbours.  One
+// barrier per plane: with two buffers a thread only overwrites buffer s-1
+// after every thread has passed the barrier of step s, i.e. finished its
+// reads of s-1.  Global loads per 4 sites: one 16-byte load plus 2/kTY halo
+// rows and 2/(4 kTX) edges.
+//
+// The plane loop is unrolled 6-fold (lcm of the 3 register planes and the 2
+// LDS buffers) so no register is copied between planes.  A wave holds
+// R = 64 / kTX thread rows; thread rows are mapped to tile rows so that each
+// wave gets R rows of one parity (within every group of 2R rows the first
+// wave takes the even rows, the second the odd ones), so p = (c + y + z) & 1
+// and the x-pair branch are uniform per wave.  Optional XCD-aware order: hardware block b
+// runs on XCD b % 8, so b -> (b % 8) * (nb / 8) + b / 8 gives each XCD a
+// contiguous run of tiles, whose halo rows then meet in that XCD's L2.
 template <class St, int kTX, int kTY>
-__global__ __launch_bounds__(kTX* kTY) void halfsweep_zslab(const typename St::T* __restrict__ other,
+struct Zslab {
+    static constexpr int kR = 64 / kTX;  // thread rows per wave
+    static_assert(kTX * kR == 64 && kR >= 1, "a wave must hold whole thread rows");
+    static_assert(kTY >= 2 && kTY % (2 * kR) == 0, "rows are permuted in groups of two waves");
+    // thread row t -> tile row: t = g*2R + w*R + i  ->  g*2R + 2i + w
+    static __device__ __forceinline__ int tile_row(int t) {
+        const int g = t / (2 * kR), w = (t / kR) & 1, i = t % kR;
+        return g * 2 * kR + 2 * i + w;
+    }
+    static constexpr int kW = 4 * kTX + 8;  // LDS row: 3 pad, left edge, 4 kTX sites, right edge, 3 pad
+    static constexpr uint32_t kEsz = St::kBytes;
+    using T = typename St::T;
+
+    __amdgpu_buffer_rsrc_t src;  // the other colour; loads past its end read 0
+    T* __restrict__ own;
+    uint32_t plane, plane_b, c, h, k0, k1, chain;
+    uint32_t y, z1, rowj;
+    uint32_t rowb, halob, edgeb;  // byte offsets within a plane; kNoLoad for lanes with no load
+    int tx, ty, row;
+    bool active;
+    float (*tile)[kTY + 2][kW];
+
+    // plane z of the thread's quad (0 past the last plane or for inactive lanes)
+    __device__ __forceinline__ float4 centre(uint32_t z) const { return St::bld4(src, z * plane_b + rowb); }
+    __device__ __forceinline__ float4 halo(uint32_t z) const { return St::bld4(src, z * plane_b + halob); }
+    __device__ __forceinline__ float edge(uint32_t z) const { return St::bld(src, z * plane_b + edgeb); }
+
+    // one plane: stage bc (+ halo, edges) in LDS buffer kBuf, prefetch plane
+    // z+1 into bn/hn/en, update own colour at plane z
+    template <int kBuf>
+    __device__ __forceinline__ void step(uint32_t z, const float4& bm, const float4& bc, float4& bn,
+                                         const float4& hc, float4& hn, float ec, float& en) const {
+        *reinterpret_cast<float4*>(&tile[kBuf][row + 1][4 + 4 * tx]) = bc;
+        if (ty < 2) *reinterpret_cast<float4*>(&tile[kBuf][ty == 0 ? 0 : kTY + 1][4 + 4 * tx]) = hc;
+        if (tx == 0) tile[kBuf][row + 1][3] = ec;
+        if (tx == kTX - 1) tile[kBuf][row + 1][kW - 4] = ec;
+        bn = centre(z + 1);
+        if (z + 1 < z1) {  // block-uniform
+            if (ty < 2) hn = halo(z + 1);  // wave-uniform: the first wave loads the halo rows
+            en = edge(z + 1);
+        }
+        __syncthreads();
+        if (!active) return;
+        const float4 up = *reinterpret_cast<const float4*>(&tile[kBuf][row][4 + 4 * tx]);
+        const float4 dn = *reinterpret_cast<const float4*>(&tile[kBuf][row + 2][4 + 4 * tx]);
+        // uniform per wave (both rows of a wave have the same parity): say so,
+        // so the branch below is a scalar branch
+        const uint32_t p = __builtin_amdgcn_readfirstlane((c + y + z) & 1u);
+        float a0, a1, a2, a3;  // x-neighbours of site k: other columns h0+k-1+p and h0+k+p
+        if (p == 0) {
+            const float e = tile[kBuf][row + 1][3 + 4 * tx];
+            a0 = e + bc.x;
+            a1 = bc.x + bc.y;
+            a2 = bc.y + bc.z;
+            a3 = bc.z + bc.w;
+        } else {
+            const float e = tile[kBuf][row + 1][8 + 4 * tx];
+            a0 = bc.x + bc.y;
+            a1 = bc.y + bc.z;
+            a2 = bc.z + bc.w;
+            a3 = bc.w + e;
+        }
+        const uint32_t j0 = z * plane + rowj;
+        const uint4 r = philox4x32_10(j0 >> 2, h, chain, 0u, k0, k1);
+        const float sixth = 1.0f / 6.0f;
+        float4 out;
+        out.x = fmaf(a0 + up.x + dn.x + bm.x + bn.x, sixth, heatbath_noise(r.x));
+        out.y = fmaf(a1 + up.y + dn.y + bm.y + bn.y, sixth, heatbath_noise(r.y));
+        out.z = fmaf(a2 + up.z + dn.z + bm.z + bn.z, sixth, heatbath_noise(r.z));
+        out.w = fmaf(a3 + up.w + dn.w + bm.w + bn.w, sixth, heatbath_noise(r.w));
+        St::st4(own, j0, out);
+    }
+};
+
+// Requires vh * sizeof(storage) < 2^31 (kNoLoad must lie past the array).
+// kWPE: minimum waves per SIMD the register allocation must allow.
+template <class St, int kTX, int kTY, int kWPE>
+__global__ __launch_bounds__(kTX* kTY) __attribute__((amdgpu_waves_per_eu(kWPE, 8))) void halfsweep_zslab(const typename St::T* __restrict__ other,
                                                            typename St::T* __restrict__ own, uint32_t lh,
                                                            uint32_t ly, uint32_t lz, uint32_t zc, uint32_t c,
                                                            uint32_t h, uint32_t k0, uint32_t k1,
                                                            uint32_t chain, uint32_t xcd_order) {
-    static_assert(kTY >= 2, "halo rows are loaded by the first two thread rows");
-    constexpr int kW = 4 * kTX + 2;  // LDS row: left edge, 4 kTX sites, right edge
-    __shared__ float tile[2][kTY + 2][kW];
+    using K = Zslab<St, kTX, kTY>;
+    __shared__ __align__(16) float tile[2][kTY + 2][K::kW];
 
     const uint32_t nq = lh >> 2;
     const uint32_t nbx = (nq + kTX - 1) / kTX, nby = (ly + kTY - 1) / kTY;
@@ -130,90 +213,61 @@ __global__ __launch_bounds__(kTX* kTY) void halfsweep_zslab(const typename St::T
         if (b < 8u * per) b = (b % 8u) * per + b / 8u;
     }
     const uint32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-    const int tx = threadIdx.x, ty = threadIdx.y;
+    constexpr uint32_t E = K::kEsz;
+    K k;
+    k.plane = ly * lh;
+    k.plane_b = k.plane * E;
+    k.src = make_rsrc(other, k.plane_b * lz);
+    k.own = own;
+    k.c = c;
+    k.h = h;
+    k.k0 = k0;
+    k.k1 = k1;
+    k.chain = chain;
+    k.tile = tile;
+    k.tx = threadIdx.x;
+    k.ty = threadIdx.y;
+    k.row = K::tile_row(k.ty);
     const uint32_t q0 = bx * kTX, y0 = by * kTY;
-    const uint32_t q = q0 + tx, y = y0 + ty;
+    const uint32_t q = q0 + k.tx;
+    k.y = y0 + k.row;
     const uint32_t z0 = bz * zc;
-    const uint32_t z1 = min(z0 + zc, lz);
-    const bool active = q < nq && y < ly;
-    const uint32_t plane = ly * lh;
+    k.z1 = min(z0 + zc, lz);
+    k.active = q < nq && k.y < ly;
+    k.rowj = k.y * lh + 4u * q;
+    k.rowb = k.active ? k.rowj * E : kNoLoad;
+    // halo rows: thread row 0 loads row y0-1, thread row 1 loads row y0+kTY
+    const bool halo_in = k.ty < 2 && q < nq && (k.ty == 0 ? y0 > 0 : y0 + kTY < ly);
+    const uint32_t hy = k.ty == 0 ? y0 - 1u : y0 + kTY;
+    k.halob = halo_in ? (hy * lh + 4u * q) * E : kNoLoad;
+    // x-edges: the first thread of a row loads the column left of the tile,
+    // the last thread the column right of it
+    const uint32_t edge_row = k.y * lh + 4u * q0;
+    if (k.tx == 0 && k.y < ly && q0 > 0)
+        k.edgeb = (edge_row - 1u) * E;
+    else if (k.tx == kTX - 1 && k.y < ly && q0 + kTX < nq)
+        k.edgeb = (edge_row + 4u * kTX) * E;
+    else
+        k.edgeb = kNoLoad;
+
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-
-    // halo row handled by this thread (first two thread rows only)
-    const bool halo_thread = ty < 2 && q < nq;
-    const uint32_t hy = ty == 0 ? y0 - 1u : y0 + kTY;  // wraps for y0 = 0: excluded below
-    const bool halo_in = halo_thread && (ty == 0 ? y0 > 0 : y0 + kTY < ly);
-    // x-edge column handled by this thread (first and last columns of the tile)
-    const bool left_edge = tx == 0 && y < ly && q0 > 0;
-    const bool right_edge = tx == kTX - 1 && y < ly && (q0 + kTX) < nq;
-
-    const uint32_t rowj = y * lh + 4u * q;      // offset of the thread's quad within a plane
-    const uint32_t haloj = hy * lh + 4u * q;
-    const uint32_t edgej = y * lh + 4u * q0;    // first site of the tile row
-
-    float4 bm = (active && z0 > 0) ? St::ld4(other, (z0 - 1) * plane + rowj) : zero;
-    float4 bc = active ? St::ld4(other, z0 * plane + rowj) : zero;
-    float4 hc = halo_in ? St::ld4(other, z0 * plane + haloj) : zero;
-    float el = left_edge ? St::ld(other, z0 * plane + edgej - 1) : 0.f;
-    float er = right_edge ? St::ld(other, z0 * plane + edgej + 4 * kTX) : 0.f;
-
-    const float sixth = 1.0f / 6.0f;
-    for (uint32_t z = z0; z < z1; ++z) {
-        const int buf = (z - z0) & 1;
-        float* row = &tile[buf][ty + 1][1 + 4 * tx];
-        row[0] = bc.x;
-        row[1] = bc.y;
-        row[2] = bc.z;
-        row[3] = bc.w;
-        if (ty < 2) {
-            float* hr = &tile[buf][ty == 0 ? 0 : kTY + 1][1 + 4 * tx];
-            hr[0] = hc.x;
-            hr[1] = hc.y;
-            hr[2] = hc.z;
-            hr[3] = hc.w;
-        }
-        if (tx == 0) tile[buf][ty + 1][0] = el;
-        if (tx == kTX - 1) tile[buf][ty + 1][kW - 1] = er;
-        // prefetch plane z + 1 (the z+1 neighbour now, the centre next step)
-        const bool more = z + 1 < lz;
-        const float4 bn = (active && more) ? St::ld4(other, (z + 1) * plane + rowj) : zero;
-        const float4 hn = (halo_in && z + 1 < z1) ? St::ld4(other, (z + 1) * plane + haloj) : zero;
-        const float eln = (left_edge && z + 1 < z1) ? St::ld(other, (z + 1) * plane + edgej - 1) : 0.f;
-        const float ern = (right_edge && z + 1 < z1) ? St::ld(other, (z + 1) * plane + edgej + 4 * kTX) : 0.f;
-        __syncthreads();
-        if (active) {
-            const float* up = &tile[buf][ty][1 + 4 * tx];
-            const float* dn = &tile[buf][ty + 2][1 + 4 * tx];
-            const float* mid = &tile[buf][ty + 1][1 + 4 * tx];
-            const uint32_t p = (c + y + z) & 1u;
-            // x-neighbours of site k: other columns h0+k-1+p and h0+k+p
-            const float e = p == 0 ? mid[-1] : mid[4];
-            float a0, a1, a2, a3;
-            if (p == 0) {
-                a0 = e + bc.x;
-                a1 = bc.x + bc.y;
-                a2 = bc.y + bc.z;
-                a3 = bc.z + bc.w;
-            } else {
-                a0 = bc.x + bc.y;
-                a1 = bc.y + bc.z;
-                a2 = bc.z + bc.w;
-                a3 = bc.w + e;
-            }
-            const uint32_t j0 = z * plane + rowj;
-            const uint4 r = philox4x32_10(j0 >> 2, h, chain, 0u, k0, k1);
-            float4 out;
-            out.x = fmaf(a0 + up[0] + dn[0] + bm.x + bn.x, sixth, heatbath_noise(r.x));
-            out.y = fmaf(a1 + up[1] + dn[1] + bm.y + bn.y, sixth, heatbath_noise(r.y));
-            out.z = fmaf(a2 + up[2] + dn[2] + bm.z + bn.z, sixth, heatbath_noise(r.z));
-            out.w = fmaf(a3 + up[3] + dn[3] + bm.w + bn.w, sixth, heatbath_noise(r.w));
-            St::st4(own, j0, out);
-        }
-        bm = bc;
-        bc = bn;
-        hc = hn;
-        el = eln;
-        er = ern;
+    float4 B0 = z0 > 0 ? k.centre(z0 - 1) : zero;
+    float4 B1 = k.centre(z0), B2 = zero;
+    float4 H0 = k.ty < 2 ? k.halo(z0) : zero, H1 = zero;
+    float E0 = k.edge(z0), E1 = 0.f;
+    const uint32_t z1 = k.z1;
+    for (uint32_t z = z0; z < z1; z += 6) {
+        k.template step<0>(z, B0, B1, B2, H0, H1, E0, E1);
+        if (z + 1 >= z1) break;
+        k.template step<1>(z + 1, B1, B2, B0, H1, H0, E1, E0);
+        if (z + 2 >= z1) break;
+        k.template step<0>(z + 2, B2, B0, B1, H0, H1, E0, E1);
+        if (z + 3 >= z1) break;
+        k.template step<1>(z + 3, B0, B1, B2, H1, H0, E1, E0);
+        if (z + 4 >= z1) break;
+        k.template step<0>(z + 4, B1, B2, B0, H0, H1, E0, E1);
+        if (z + 5 >= z1) break;
+        k.template step<1>(z + 5, B2, B0, B1, H1, H0, E1, E0);
     }
 }
 
@@ -224,12 +278,25 @@ static hipError_t launch_halfsweep_t(const SweepArgs& a, hipStream_t stream) {
     const T* other = field + (size_t)(a.c ^ 1u) * a.vh;
     T* own = const_cast<T*>(field) + (size_t)a.c * a.vh;
     if (a.variant == kVariantZslab) {
-        constexpr int kTX = 32, kTY = 8;
+        if ((uint64_t)a.vh * St::kBytes >= (1ull << 31)) return hipErrorInvalidValue;  // kNoLoad must be out of range
+        const uint32_t zc = a.zc ? a.zc : 16u;
         const uint32_t nq = a.lh >> 2;
-        const uint32_t zc = a.zc ? a.zc : 32u;
-        const uint32_t nb = ((nq + kTX - 1) / kTX) * ((a.ly + kTY - 1) / kTY) * ((a.lz + zc - 1) / zc);
-        hipLaunchKernelGGL((halfsweep_zslab<St, kTX, kTY>), dim3(nb), dim3(kTX, kTY, 1), 0, stream, other, own,
-                           a.lh, a.ly, a.lz, zc, a.c, a.h, a.k0, a.k1, a.chain, a.xcd_order);
+        auto launch = [&](auto kern, int tx, int ty) {
+            const uint32_t nb = ((nq + tx - 1) / tx) * ((a.ly + ty - 1) / ty) * ((a.lz + zc - 1) / zc);
+            hipLaunchKernelGGL(kern, dim3(nb), dim3(tx, ty, 1), 0, stream, other, own, a.lh, a.ly, a.lz, zc, a.c,
+                               a.h, a.k0, a.k1, a.chain, a.xcd_order);
+        };
+        switch (a.tile) {  // tile quads x rows, minimum waves per SIMD
+            case 0: launch(halfsweep_zslab<St, 32, 8, 1>, 32, 8); break;
+            case 1: launch(halfsweep_zslab<St, 32, 8, 5>, 32, 8); break;
+            case 2: launch(halfsweep_zslab<St, 32, 8, 6>, 32, 8); break;
+            case 3: launch(halfsweep_zslab<St, 32, 8, 8>, 32, 8); break;
+            case 4: launch(halfsweep_zslab<St, 16, 8, 6>, 16, 8); break;
+            case 5: launch(halfsweep_zslab<St, 32, 4, 6>, 32, 4); break;
+            case 6: launch(halfsweep_zslab<St, 64, 4, 4>, 64, 4); break;
+            case 7: launch(halfsweep_zslab<St, 16, 16, 4>, 16, 16); break;
+            default: return hipErrorInvalidValue;
+        }
     } else if (a.variant == kVariantQuad) {
         const uint32_t nq = a.lh >> 2;
         const uint32_t tx = nq >= 16 ? 16 : nq;

@@ -67,7 +67,7 @@ def load_library() -> ctypes.CDLL:
         "lattice_last_error": (ctypes.c_char_p, []),
         "lattice_sweep_count": (_int, [_p, _pi64]),
         "lattice_set_variant": (_int, [_p, _int]),
-        "lattice_set_slab": (_int, [_p, _i64, _int]),
+        "lattice_set_tuning": (_int, [_p, _i64, _int, _int]),
         "lattice_get_field": (_int, [_p, _p]),
         "lattice_set_field": (_int, [_p, _p]),
         "lattice_last_measure": (_int, [_p, _pd, _pd]),
@@ -222,8 +222,9 @@ class Lattice:
     def set_variant(self, name: str):
         self._call(self.lib.lattice_set_variant, VARIANT[name])
 
-    def set_slab(self, planes: int = 0, xcd_order: bool = True):
-        self._call(self.lib.lattice_set_slab, int(planes), 1 if xcd_order else 0)
+    def set_tuning(self, planes: int = 16, tile: int = 0, xcd_order: bool = True):
+        """Slab-kernel tuning: planes per workgroup, tile configuration, XCD order."""
+        self._call(self.lib.lattice_set_tuning, int(planes), int(tile), 1 if xcd_order else 0)
 
     def get_field(self) -> np.ndarray:
         lx, ly, lz = self.shape

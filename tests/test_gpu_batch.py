@@ -1,0 +1,137 @@
+"""GPU parity of the batched-chain path (one persistent launch, one workgroup
+per chain) against single lattices and the CPU oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_0711_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lat_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1403_0711_amd import lattice
+
+    lattice.load_library()
+    return lattice
+
+
+EDGES = [(24, 24, 24), (16, 8, 12), (10, 6, 5), (32, 32, 32), (2, 1, 1), (40, 16, 9)]
+
+
+def _charges(shape, n, seed):
+    rng = np.random.default_rng(seed)
+    xyz = workloads.distinct_sites(rng, n, (0, 0, 0), shape)
+    q = rng.standard_normal(n)
+    return xyz, q - q.mean()
+
+
+def test_batch_matches_single_lattices(lat_mod):
+    """Each chain of a batch equals a single lattice with the same seed and
+    chain id: same field after every run, same estimate."""
+    print("[gpu] batch vs single lattices", flush=True)
+    seed = 12345
+    ids = [7, 0, 3, 1000, 5, 2]
+    b = lat_mod.Batch(EDGES, "fp32", seed=seed, chain_ids=ids)
+    singles = []
+    for k, e in enumerate(EDGES):
+        n = min(6, int(np.prod(e)))
+        xyz, q = _charges(e, n, k)
+        b.set_charges(k, xyz, q)
+        s = lat_mod.Lattice(e, "fp32", seed=seed, chain_id=ids[k])
+        s.set_charges(xyz, q)
+        singles.append(s)
+    b.run(5, 20, 5)
+    for s in singles:
+        s.thermalise(5)
+        s.sweep_and_measure(20, 1, 5)
+    for k, s in enumerate(singles):
+        fb, fs = b.get_field(k), s.get_field()
+        assert np.abs(fb - fs).max() <= 1e-6 * max(np.abs(fs).max(), 1e-30), k
+        mb, seb, Mb, nbb = b.energy_estimate(k)
+        ms, ses, Ms, nbs = s.energy_estimate()
+        assert (Mb, nbb) == (Ms, nbs) == (20, 4)
+        assert abs(mb - ms) <= 1e-6 * max(1.0, abs(ms)), k
+    # a second run continues the same streams
+    b.run(0, 10, 5)
+    for s in singles:
+        s.sweep_and_measure(10, 1, 5)
+    for k, s in enumerate(singles):
+        assert np.abs(b.get_field(k) - s.get_field()).max() <= 1e-6 * max(np.abs(s.get_field()).max(), 1e-30)
+        assert b.energy_estimate(k)[2] == 30
+
+
+def test_batch_chain_matches_oracle(lat_mod):
+    print("[gpu] batch chain vs oracle", flush=True)
+    seed = 99
+    edges = [(16, 16, 16), (10, 6, 5)]
+    b = lat_mod.Batch(edges, "fp32", seed=seed, chain_ids=[4, 9])
+    c = workloads.small_neutral(seed=3, L=16, n=10)
+    b.set_charges(0, c.xyz, c.q)
+    ref = oracle.OracleChain(c.shape, seed=seed, chain=4)
+    ref.set_charges(c.xyz, c.q)
+    b.run(10, 40, 1)
+    ref.sweeps(10)
+    s = ref.sweeps(40, 1)
+    phi = b.get_field(0).astype(np.float64)
+    assert np.abs(phi - ref.phi).max() <= 1e-5 * np.abs(ref.phi).max()
+    m, se, M, nb = b.energy_estimate(0)
+    assert M == 40 and nb == 40
+    scale = np.sum(np.abs(c.q)) ** 2 * np.abs(ref.phi).max() ** 2
+    assert abs(m - s[:, 2].mean()) <= 1e-4 * scale
+    ref2 = oracle.OracleChain((10, 6, 5), seed=seed, chain=9)
+    ref2.sweeps(50)
+    assert np.abs(b.get_field(1) - ref2.phi).max() <= 1e-5 * np.abs(ref2.phi).max()
+
+
+def test_batch_charge_reset_is_per_chain(lat_mod):
+    print("[gpu] batch charge reset", flush=True)
+    b = lat_mod.Batch([(8, 8, 8), (8, 8, 8)], seed=1)
+    for k in range(2):
+        b.set_charges(k, [[1, 1, 1], [3, 4, 5]], [1.0, -1.0])
+    b.run(0, 20, 5)
+    b.set_charges(1, [[2, 2, 2], [5, 5, 5]], [1.0, 1.0])
+    b.run(0, 10, 5)
+    assert b.energy_estimate(0)[2] == 30
+    assert b.energy_estimate(1)[2] == 10
+
+
+def test_batch_argument_errors(lat_mod):
+    print("[gpu] batch errors", flush=True)
+    with pytest.raises(lat_mod.LatticeError):
+        lat_mod.Batch([(7, 4, 4)])
+    b = lat_mod.Batch([(8, 4, 4)])
+    with pytest.raises(lat_mod.LatticeError):
+        b.set_charges(1, [[0, 0, 0]], [1.0])
+    with pytest.raises(lat_mod.LatticeError):
+        b.set_charges(0, [[0, 4, 0]], [1.0])
+    b.set_charges(0, [[0, 0, 0], [1, 1, 1]], [1.0, -1.0])
+    b.run(0, 4, 2)
+    with pytest.raises(lat_mod.LatticeError):
+        b.run(0, 4, 3)
+
+
+def test_batched_workload_estimates(lat_mod):
+    """The 512-chain workload (edges 24..64, 16..512 charges of N(0,1)
+    shifted to neutral): one persistent launch, every chain returns finite
+    estimates with the requested bins; chain 0 equals a single lattice."""
+    print("[gpu] batched workload", flush=True)
+    chains = workloads.batched_chains(seed=0)
+    b = lat_mod.Batch([c.shape for c in chains], "fp32", seed=0)
+    for k, c in enumerate(chains):
+        b.set_charges(k, c.xyz, c.q)
+    b.run(20, 200, 20)
+    ests = [b.energy_estimate(k) for k in range(len(chains))]
+    assert all(np.isfinite(m) and np.isfinite(se) and M == 200 and nb == 10 for m, se, M, nb in ests)
+    s = lat_mod.Lattice(chains[0].shape, "fp32", seed=0, chain_id=0)
+    s.set_charges(chains[0].xyz, chains[0].q)
+    s.thermalise(20)
+    s.sweep_and_measure(200, 1, 20)
+    assert np.abs(b.get_field(0) - s.get_field()).max() <= 1e-6 * np.abs(s.get_field()).max()
+    assert abs(ests[0][0] - s.energy_estimate()[0]) <= 1e-6 * max(1.0, abs(ests[0][0]))

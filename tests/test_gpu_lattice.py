@@ -61,7 +61,7 @@ def test_field_parity_per_sweep_fp32(lat_mod, shape, variant):
     lat = lat_mod.Lattice(shape, "fp32", seed=seed, chain_id=3)
     lat.set_variant(variant)
     if variant == "zslab":
-        lat.set_slab(2 if shape[2] > 2 else 1, xcd_order=True)
+        lat.set_tuning(2 if shape[2] > 2 else 1, tile=(shape[0] + shape[1]) % 8, xcd_order=True)
     ref = oracle.OracleChain(shape, "fp32", seed=seed, chain=3)
     for s in range(6):
         lat.thermalise(1)
@@ -85,14 +85,15 @@ def test_variants_agree(lat_mod):
     ref.thermalise(20)
     fr = ref.get_field()
     slab_fields = []
-    for variant, slab, xcd in (("quad", 0, True), ("zslab", 0, True), ("zslab", 1, False),
-                               ("zslab", 7, True), ("zslab", 20, False)):
+    for variant, slab, tile, xcd in (("quad", 0, 0, True), ("zslab", 0, 0, True), ("zslab", 1, 1, False),
+                                     ("zslab", 7, 2, True), ("zslab", 20, 3, False), ("zslab", 5, 4, True),
+                                     ("zslab", 3, 5, True), ("zslab", 9, 6, False), ("zslab", 16, 7, True)):
         a = lat_mod.Lattice(shape, seed=7)
         a.set_variant(variant)
-        a.set_slab(slab, xcd)
+        a.set_tuning(slab, tile, xcd)
         a.thermalise(20)
         fa = a.get_field()
-        assert np.abs(fa - fr).max() <= 1e-6 * np.abs(fr).max(), (variant, slab, xcd)
+        assert np.abs(fa - fr).max() <= 1e-6 * np.abs(fr).max(), (variant, slab, tile, xcd)
         if variant == "zslab":
             slab_fields.append(fa)
     for f in slab_fields[1:]:
