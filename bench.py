@@ -148,7 +148,7 @@ def main():
     fused = args.variant == "fused"
     if fused:
         launch_ms = sweep_ms  # one launch per sweep
-        bytes_per_launch = V * esz  # read colour 1, write colour 1 (colour 0 kept on chip)
+        bytes_per_launch = 3 * (V // 2) * esz  # read colour 1, write colour 0 and colour 1
         kname = "fused_sweep"
     else:
         launch_ms = sweep_ms / 2.0

@@ -82,7 +82,8 @@ enum {
     LAT_SWEEP_QUAD = 1,    /* 4 sites per thread, one pass per half-sweep (lx % 8 == 0) */
     LAT_SWEEP_GENERIC = 2, /* 1 site per thread, any even lx                        */
     LAT_SWEEP_ZSLAB = 3,   /* z-marching slabs, plane staged in LDS (lx % 8 == 0)   */
-    LAT_SWEEP_FUSED = 4    /* both half-sweeps in one pass (lx % 8 == 0)             */
+    LAT_SWEEP_FUSED = 4,   /* both half-sweeps in one pass (lx % 8 == 0)             */
+    LAT_SWEEP_RESIDENT = 5 /* small boxes: one workgroup runs every sweep of a call in one launch */
 };
 
 /* ------------------------------------------------------------------ */

@@ -220,9 +220,24 @@ int batch_run(lattice_batch_t* B, int64_t n_therm, int64_t n_meas, int64_t bin_s
         e = hipMemcpy(B->d_desc, B->desc.data(), sizeof(BatchChainDesc) * (size_t)B->n, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
     if (n_therm + n_meas == 0) return LAT_OK;
-    BatchArgs a{B->field, B->d_desc, B->d_order, (uint32_t)B->n, B->d_site, B->d_Q, B->d_S, B->d_bins,
-                (uint32_t)B->t, (uint32_t)n_therm, (uint32_t)n_meas, (uint32_t)bin_size,
-                (uint32_t)B->seed, (uint32_t)(B->seed >> 32), B->storage, 0u};
+    BatchArgs a{};
+    a.field = B->field;
+    a.desc = B->d_desc;
+    a.order = B->d_order;
+    a.n_chains = (uint32_t)B->n;
+    a.site = B->d_site;
+    a.Q = B->d_Q;
+    a.S = B->d_S;
+    a.bins = B->d_bins;
+    a.t0 = (uint32_t)B->t;
+    a.n_therm = (uint32_t)n_therm;
+    a.n_meas = (uint32_t)n_meas;
+    a.every = 1;
+    a.bin_size = (uint32_t)bin_size;
+    a.k0 = (uint32_t)B->seed;
+    a.k1 = (uint32_t)(B->seed >> 32);
+    a.storage = B->storage;
+    a.single = false;
     e = launch_batch(a, B->stream);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     B->t += n_therm + n_meas;

@@ -14,7 +14,7 @@
 
 namespace latcoul {
 
-constexpr int kBatchThreads = 512;
+constexpr int kBatchThreads = 1024;
 
 // One half-sweep of colour c over a whole chain by one workgroup: 4 compact
 // sites of one row per iteration when lh % 4 == 0, else one site.
@@ -80,16 +80,14 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
     }
 }
 
+// All sweeps of one chain by one workgroup: n_therm unmeasured sweeps, then
+// n_meas sweeps with a sample after every `every`-th one.
 template <class St>
-__global__ __launch_bounds__(kBatchThreads) void batch_chains(typename St::T* __restrict__ fields,
-                                                              const BatchChainDesc* __restrict__ desc,
-                                                              const uint32_t* __restrict__ order,
-                                                              const uint32_t* __restrict__ site,
-                                                              const double* __restrict__ Q,
-                                                              const double* __restrict__ S, double* bins,
-                                                              uint32_t t0, uint32_t n_therm, uint32_t n_meas,
-                                                              uint32_t bin_size, uint32_t k0, uint32_t k1) {
-    const BatchChainDesc d = desc[order[blockIdx.x]];
+__device__ __forceinline__ void run_chain(typename St::T* fields, const BatchChainDesc& d,
+                                          const uint32_t* __restrict__ site, const double* __restrict__ Q,
+                                          const double* __restrict__ S, double* bins, uint32_t t0, uint32_t n_therm,
+                                          uint32_t n_meas, uint32_t every, uint32_t bin_size, uint32_t k0,
+                                          uint32_t k1, double* last_xy) {
     typename St::T* field = fields + d.field_off;
     const typename St::T* cfield = field;
     const uint32_t n_sweeps = n_therm + n_meas;
@@ -99,7 +97,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_chains(typename St::T* __
         __syncthreads();
         chain_halfsweep<St>(field, d, 1u, 2u * t + 1u, k0, k1);
         __syncthreads();
-        if (s >= n_therm) {
+        if (s >= n_therm && (s - n_therm + 1) % every == 0) {
             double x = 0.0, y = 0.0;
             for (uint32_t i = d.site_off + threadIdx.x; i < d.site_off + d.n_sites; i += kBatchThreads) {
                 const double v = (double)St::ld(cfield, site[i]);
@@ -108,7 +106,8 @@ __global__ __launch_bounds__(kBatchThreads) void batch_chains(typename St::T* __
             }
             block_sum2<kBatchThreads>(x, y);  // ends with a barrier
             if (threadIdx.x == 0) {
-                const uint32_t b = d.bin_off + (d.meas0 + (s - n_therm)) / bin_size;
+                const uint32_t m = (s - n_therm + 1) / every - 1;  // sample index within this run
+                const uint32_t b = d.bin_off + (d.meas0 + m) / bin_size;
                 const double O = x * x - y;
                 double sum = bins[2 * b], comp = bins[2 * b + 1];
                 const double yk = O - comp;
@@ -116,16 +115,53 @@ __global__ __launch_bounds__(kBatchThreads) void batch_chains(typename St::T* __
                 comp = (tk - sum) - yk;
                 bins[2 * b] = tk;
                 bins[2 * b + 1] = comp;
+                if (last_xy) {
+                    last_xy[0] = x;
+                    last_xy[1] = y;
+                }
             }
         }
     }
 }
 
 template <class St>
+__global__ __launch_bounds__(kBatchThreads) void batch_chains(typename St::T* __restrict__ fields,
+                                                              const BatchChainDesc* __restrict__ desc,
+                                                              const uint32_t* __restrict__ order,
+                                                              const uint32_t* __restrict__ site,
+                                                              const double* __restrict__ Q,
+                                                              const double* __restrict__ S, double* bins,
+                                                              uint32_t t0, uint32_t n_therm, uint32_t n_meas,
+                                                              uint32_t every, uint32_t bin_size, uint32_t k0,
+                                                              uint32_t k1) {
+    const BatchChainDesc d = desc[order[blockIdx.x]];
+    run_chain<St>(fields, d, site, Q, S, bins, t0, n_therm, n_meas, every, bin_size, k0, k1, nullptr);
+}
+
+// One lattice small enough for one workgroup: the whole run in one launch.
+template <class St>
+__global__ __launch_bounds__(kBatchThreads) void resident_chain(typename St::T* __restrict__ field,
+                                                                BatchChainDesc d,
+                                                                const uint32_t* __restrict__ site,
+                                                                const double* __restrict__ Q,
+                                                                const double* __restrict__ S, double* bins,
+                                                                uint32_t t0, uint32_t n_therm, uint32_t n_meas,
+                                                                uint32_t every, uint32_t bin_size, uint32_t k0,
+                                                                uint32_t k1, double* last_xy) {
+    run_chain<St>(field, d, site, Q, S, bins, t0, n_therm, n_meas, every, bin_size, k0, k1, last_xy);
+}
+
+template <class St>
 static hipError_t launch_batch_t(const BatchArgs& a, hipStream_t stream) {
-    hipLaunchKernelGGL(batch_chains<St>, dim3(a.n_chains), dim3(kBatchThreads), 0, stream,
-                       static_cast<typename St::T*>(a.field), a.desc, a.order, a.site, a.Q, a.S, a.bins, a.t0,
-                       a.n_therm, a.n_meas, a.bin_size, a.k0, a.k1);
+    if (a.single) {
+        hipLaunchKernelGGL(resident_chain<St>, dim3(1), dim3(kBatchThreads), 0, stream,
+                           static_cast<typename St::T*>(a.field), a.single_desc, a.site, a.Q, a.S, a.bins, a.t0,
+                           a.n_therm, a.n_meas, a.every, a.bin_size, a.k0, a.k1, a.last_xy);
+    } else {
+        hipLaunchKernelGGL(batch_chains<St>, dim3(a.n_chains), dim3(kBatchThreads), 0, stream,
+                           static_cast<typename St::T*>(a.field), a.desc, a.order, a.site, a.Q, a.S, a.bins, a.t0,
+                           a.n_therm, a.n_meas, a.every, a.bin_size, a.k0, a.k1);
+    }
     return hipGetLastError();
 }
 

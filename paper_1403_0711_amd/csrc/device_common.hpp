@@ -131,6 +131,8 @@ struct StoreF32 {
     __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<float>(p, i) = v; }
     __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32x4(r, off); }
     __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32(r, off); }
+    // the value a store followed by a load returns
+    __device__ static __forceinline__ float4 round4(float4 v) { return v; }
 };
 
 __device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
@@ -163,6 +165,10 @@ struct StoreBF16 {
     __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
     }
+    __device__ static __forceinline__ float4 round4(float4 v) {
+        return make_float4(bf16_to_f32(bf16_rne_bits(v.x)), bf16_to_f32(bf16_rne_bits(v.y)),
+                           bf16_to_f32(bf16_rne_bits(v.z)), bf16_to_f32(bf16_rne_bits(v.w)));
+    }
 };
 
 struct StoreF16 {
@@ -192,6 +198,9 @@ struct StoreF16 {
     }
     __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+    }
+    __device__ static __forceinline__ float4 round4(float4 v) {
+        return make_float4((float)(_Float16)v.x, (float)(_Float16)v.y, (float)(_Float16)v.z, (float)(_Float16)v.w);
     }
 };
 

@@ -24,14 +24,17 @@ struct SweepArgs {
 constexpr int kZslabTiles = 8;
 hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream);
 
-// Both half-sweeps of sweep t in one pass (z-marching slabs), lh % 4 == 0.
+// Both half-sweeps of sweep t in one pass (temporal blocking), lh % 4 == 0.
 struct FusedArgs {
-    void* field;
+    void* c0;          // colour 0 (written)
+    const void* b_in;  // colour 1 before the sweep
+    void* b_out;       // colour 1 after the sweep (a different array)
     uint32_t lh, ly, lz, vh;
-    uint32_t h0;      // 2t: colour 0 uses h0, colour 1 uses h0 + 1
+    uint32_t h0;       // 2t: colour 0 uses h0, colour 1 uses h0 + 1
     uint32_t k0, k1, chain;
     int storage;
-    uint32_t slab;    // planes per workgroup along z
+    uint32_t slab;     // planes per workgroup along z (0 = default)
+    uint32_t xcd_order;
 };
 hipError_t launch_fused_sweep(const FusedArgs& a, hipStream_t stream);
 
@@ -39,7 +42,9 @@ hipError_t launch_fused_sweep(const FusedArgs& a, hipStream_t stream);
 // X = sum_s Q_s phi_s, Y = sum_s S_s phi_s^2 over the site-aggregated charge
 // list, O = X^2 - Y compensated-added into bins[2*bin], bins[2*bin+1].
 struct MeasureArgs {
-    const void* field;
+    const void* field0;    // colour 0
+    const void* field1;    // colour 1
+    uint32_t vh;
     const uint32_t* site;  // c * vh + j, sorted ascending
     const double* Q;       // sum of q on the site
     const double* S;       // sum of q^2 on the site
@@ -65,18 +70,20 @@ struct BatchChainDesc {
 };
 struct BatchArgs {
     void* field;
-    const BatchChainDesc* desc;
-    const uint32_t* order;  // chains in launch order (largest first)
+    const BatchChainDesc* desc;  // device table (batch) ...
+    const uint32_t* order;       // ... chains in launch order (largest first)
     uint32_t n_chains;
     const uint32_t* site;
     const double* Q;
     const double* S;
     double* bins;
     uint32_t t0;        // sweep counter at the start of this run (same for all chains)
-    uint32_t n_therm, n_meas, bin_size;
+    uint32_t n_therm, n_meas, every, bin_size;
     uint32_t k0, k1;
     int storage;
-    uint32_t threads;   // workgroup size
+    bool single;                 // one lattice: descriptor passed by value
+    BatchChainDesc single_desc;
+    double* last_xy;             // single: X, Y of the last sample (or null)
 };
 hipError_t launch_batch(const BatchArgs& a, hipStream_t stream);
 

@@ -15,6 +15,9 @@
 
 using namespace latcoul;
 
+// largest box that AUTO runs with the one-workgroup resident kernel
+constexpr uint64_t kResidentMaxSites = 32768;
+
 struct lattice {
     int64_t lx = 0, ly = 0, lz = 0;
     uint32_t lh = 0, vh = 0;
@@ -24,7 +27,11 @@ struct lattice {
     uint32_t chain = 0;
     DeviceAllocator mem;
     hipStream_t stream = nullptr;
-    void* field = nullptr;
+    void* field = nullptr;  // colour 0 then colour 1
+    // second colour-1 array for the fused sweep, which reads colour 1 from one
+    // array and writes the other; alt_current: the current colour 1 is there
+    void* c1alt = nullptr;
+    bool alt_current = false;
     // charges, aggregated per site
     int64_t n_raw = 0;
     uint32_t n_sites = 0;
@@ -47,8 +54,13 @@ struct lattice {
     uint32_t tile = 0;       // tile configuration of the slab kernel
 
     double* last_xy() { return reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
+    void* c1main() const { return static_cast<char*>(field) + (size_t)vh * esz; }
+    void* c1cur() const { return alt_current ? c1alt : c1main(); }
     int effective_variant() const {
         if (variant != LAT_SWEEP_AUTO) return variant;
+        // a box one workgroup sweeps in a few microseconds: launch overhead
+        // would dominate, so run the whole call in one launch
+        if ((uint64_t)vh * 2 <= kResidentMaxSites) return LAT_SWEEP_RESIDENT;
         if (lh % 4 != 0) return LAT_SWEEP_GENERIC;
         // boxes that spill out of the 256 MB last-level cache: z-marching slabs
         // (whose colour arrays must stay below 2 GiB)
@@ -68,9 +80,11 @@ static int enqueue_sweep(lattice* L) {
     const int v = L->effective_variant();
     hipError_t e;
     if (v == LAT_SWEEP_FUSED) {
-        FusedArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, h0,
-                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, L->slab};
+        void* out = L->alt_current ? L->c1main() : L->c1alt;
+        FusedArgs a{L->field, L->c1cur(), out, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, h0,
+                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, L->slab, L->xcd_order};
         e = launch_fused_sweep(a, L->stream);
+        if (e == hipSuccess) L->alt_current = !L->alt_current;
     } else {
         const int kv = v == LAT_SWEEP_QUAD ? kVariantQuad : v == LAT_SWEEP_ZSLAB ? kVariantZslab : kVariantGeneric;
         SweepArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, 0u, h0,
@@ -88,13 +102,61 @@ static int enqueue_sweep(lattice* L) {
     return LAT_OK;
 }
 
+// The resident path: n_therm unmeasured sweeps then n_meas sweeps with a
+// sample after every `every`-th, all in one launch.
+static int enqueue_resident(lattice* L, int64_t n_therm, int64_t n_meas, int64_t every) {
+    if (n_therm + n_meas == 0) return LAT_OK;
+    BatchArgs a{};
+    a.field = L->field;
+    a.site = L->d_site;
+    a.Q = L->d_Q;
+    a.S = L->d_S;
+    a.bins = L->d_bins;
+    a.t0 = (uint32_t)L->t;
+    a.n_therm = (uint32_t)n_therm;
+    a.n_meas = (uint32_t)n_meas;
+    a.every = (uint32_t)every;
+    a.bin_size = (uint32_t)(L->bin_size > 0 ? L->bin_size : 1);
+    a.k0 = (uint32_t)L->seed;
+    a.k1 = (uint32_t)(L->seed >> 32);
+    a.storage = L->storage;
+    a.single = true;
+    a.last_xy = L->last_xy();
+    BatchChainDesc& d = a.single_desc;
+    d.field_off = 0;
+    d.lh = L->lh;
+    d.ly = (uint32_t)L->ly;
+    d.lz = (uint32_t)L->lz;
+    d.vh = L->vh;
+    d.chain_id = L->chain;
+    d.site_off = 0;
+    d.n_sites = L->n_sites;
+    d.bin_off = 0;
+    d.meas0 = (uint32_t)L->n_meas;
+    hipError_t e = launch_batch(a, L->stream);
+    if (e != hipSuccess) return hip_fail(e, "resident sweep launch");
+    L->t += n_therm + n_meas;
+    L->n_meas += n_meas / every;
+    return LAT_OK;
+}
+
 static int enqueue_measure(lattice* L) {
-    MeasureArgs a{L->field, L->d_site, L->d_Q, L->d_S, L->n_sites, L->d_partials,
+    MeasureArgs a{L->field, L->c1cur(), L->vh, L->d_site, L->d_Q, L->d_S, L->n_sites, L->d_partials,
                   L->d_bins, (uint32_t)(L->n_meas / L->bin_size), L->last_xy(), L->storage,
                   L->meas_blocks};
     hipError_t e = launch_measure(a, L->stream);
     if (e != hipSuccess) return hip_fail(e, "measure launch");
     L->n_meas += 1;
+    return LAT_OK;
+}
+
+// After fused sweeps colour 1 may sit in the second array: copy it home so
+// that every other path sees colour 0 then colour 1 in `field`.
+static int settle_colour1(lattice* L) {
+    if (!L->alt_current) return LAT_OK;
+    hipError_t e = hipMemcpyAsync(L->c1main(), L->c1alt, (size_t)L->vh * L->esz, hipMemcpyDeviceToDevice, L->stream);
+    if (e != hipSuccess) return hip_fail(e, "colour-1 copy");
+    L->alt_current = false;
     return LAT_OK;
 }
 
@@ -163,6 +225,7 @@ void lattice_destroy(lattice_t* L) {
     if (!L) return;
     (void)hipStreamSynchronize(L->stream);
     L->mem.release(L->field);
+    L->mem.release(L->c1alt);
     L->mem.release(L->d_misc);
     L->mem.release(L->d_site);
     L->mem.release(L->d_Q);
@@ -183,7 +246,8 @@ int lattice_set_variant(lattice_t* L, int variant) {
     if (int r = check_lattice(L)) return r;
     switch (variant) {
         case LAT_SWEEP_AUTO:
-        case LAT_SWEEP_GENERIC: break;
+        case LAT_SWEEP_GENERIC:
+        case LAT_SWEEP_RESIDENT: break;
         case LAT_SWEEP_QUAD:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
             break;
@@ -195,7 +259,11 @@ int lattice_set_variant(lattice_t* L, int variant) {
         case LAT_SWEEP_FUSED:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "fused sweep needs lx % 8 == 0");
             if (!fused_sweep_supported(L->lh, (uint32_t)L->ly))
-                return set_error(LAT_ERR_ARG, "fused sweep not available for this box");
+                return set_error(LAT_ERR_ARG, "fused sweep needs 64 <= lx <= 1024 (full rows staged in LDS)");
+            if (!L->c1alt) {
+                L->c1alt = L->mem.alloc(round_up((size_t)L->vh * L->esz, 256));
+                if (!L->c1alt) return set_error(LAT_ERR_ALLOC, "allocation of the second colour-1 array failed");
+            }
             break;
         default: return set_error(LAT_ERR_ARG, "unknown sweep variant");
     }
@@ -276,9 +344,10 @@ int thermalise(lattice_t* L, int64_t n_sweeps) {
     if (int r = check_lattice(L)) return r;
     if (n_sweeps < 0) return set_error(LAT_ERR_ARG, "n_sweeps < 0");
     if (L->t + n_sweeps > (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_ARG, "sweep counter would exceed 2^31");
+    if (L->effective_variant() == LAT_SWEEP_RESIDENT) return enqueue_resident(L, n_sweeps, 0, 1);
     for (int64_t s = 0; s < n_sweeps; ++s)
         if (int r = enqueue_sweep(L)) return r;
-    return LAT_OK;
+    return settle_colour1(L);
 }
 
 int sweep_and_measure(lattice_t* L, int64_t n_sweeps, int64_t measure_every, int64_t bin_size) {
@@ -299,12 +368,13 @@ int sweep_and_measure(lattice_t* L, int64_t n_sweeps, int64_t measure_every, int
         return set_error(LAT_ERR_ARG, "too many bins");
     if (int r = ensure_bins(L, (total + bin_size - 1) / bin_size)) return r;
     L->bin_size = bin_size;
+    if (L->effective_variant() == LAT_SWEEP_RESIDENT) return enqueue_resident(L, 0, n_sweeps, measure_every);
     for (int64_t s = 0; s < n_sweeps; ++s) {
         if (int r = enqueue_sweep(L)) return r;
         if ((s + 1) % measure_every == 0)
             if (int r = enqueue_measure(L)) return r;
     }
-    return LAT_OK;
+    return settle_colour1(L);
 }
 
 int energy_estimate(lattice_t* L, double* mean, double* stderr_binned, int64_t* n_samples, int64_t* n_bins) {

@@ -28,7 +28,15 @@ uint32_t measure_blocks(uint32_t n) {
 }
 
 template <class St>
-__global__ __launch_bounds__(kMeasureThreads) void gather_partials(const typename St::T* __restrict__ field,
+__device__ __forceinline__ float site_value(const typename St::T* f0, const typename St::T* f1, uint32_t vh,
+                                            uint32_t s) {
+    return s < vh ? St::ld(f0, s) : St::ld(f1, s - vh);
+}
+
+template <class St>
+__global__ __launch_bounds__(kMeasureThreads) void gather_partials(const typename St::T* __restrict__ f0,
+                                                                   const typename St::T* __restrict__ f1,
+                                                                   uint32_t vh,
                                                                    const uint32_t* __restrict__ site,
                                                                    const double* __restrict__ Q,
                                                                    const double* __restrict__ S, uint32_t n,
@@ -40,7 +48,7 @@ __global__ __launch_bounds__(kMeasureThreads) void gather_partials(const typenam
     for (; i + (kGatherUnroll - 1) * stride < n; i += kGatherUnroll * stride) {
         float v[kGatherUnroll];
 #pragma unroll
-        for (int u = 0; u < kGatherUnroll; ++u) v[u] = St::ld(field, site[i + u * stride]);
+        for (int u = 0; u < kGatherUnroll; ++u) v[u] = site_value<St>(f0, f1, vh, site[i + u * stride]);
 #pragma unroll
         for (int u = 0; u < kGatherUnroll; ++u) {
             const double d = (double)v[u];
@@ -49,7 +57,7 @@ __global__ __launch_bounds__(kMeasureThreads) void gather_partials(const typenam
         }
     }
     for (; i < n; i += stride) {
-        const double d = (double)St::ld(field, site[i]);
+        const double d = (double)site_value<St>(f0, f1, vh, site[i]);
         x = fma(Q[i], d, x);
         y = fma(S[i], d * d, y);
     }
@@ -88,7 +96,8 @@ __global__ __launch_bounds__(kMeasureThreads) void finalize_measure(const double
 template <class St>
 static hipError_t launch_measure_t(const MeasureArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL(gather_partials<St>, dim3(a.blocks), dim3(kMeasureThreads), 0, stream,
-                       static_cast<const typename St::T*>(a.field), a.site, a.Q, a.S, a.n, a.partials);
+                       static_cast<const typename St::T*>(a.field0), static_cast<const typename St::T*>(a.field1),
+                       a.vh, a.site, a.Q, a.S, a.n, a.partials);
     hipLaunchKernelGGL(finalize_measure, dim3(1), dim3(kMeasureThreads), 0, stream, a.partials, a.blocks,
                        a.bins, a.bin, a.last_xy);
     return hipGetLastError();

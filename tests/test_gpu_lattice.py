@@ -51,6 +51,13 @@ SHAPES = [
     ((6, 4, 3), "generic"),
     ((2, 1, 1), "generic"),     # smallest box
     ((8, 1, 3), "quad"),        # one-row planes
+    ((64, 16, 16), "fused"),
+    ((80, 21, 13), "fused"),    # 10 quads per row, ragged y rows and z slabs
+    ((64, 1, 3), "fused"),      # one row per plane
+    ((16, 16, 16), "resident"),
+    ((10, 6, 5), "resident"),
+    ((2, 1, 1), "resident"),
+    ((48, 40, 36), "resident"), # 34560 sites: many loop passes per workgroup
 ]
 
 
@@ -62,6 +69,8 @@ def test_field_parity_per_sweep_fp32(lat_mod, shape, variant):
     lat.set_variant(variant)
     if variant == "zslab":
         lat.set_tuning(2 if shape[2] > 2 else 1, tile=(shape[0] + shape[1]) % 8, xcd_order=True)
+    if variant == "fused":
+        lat.set_tuning(3, 0, xcd_order=True)
     ref = oracle.OracleChain(shape, "fp32", seed=seed, chain=3)
     for s in range(6):
         lat.thermalise(1)
@@ -85,7 +94,8 @@ def test_variants_agree(lat_mod):
     ref.thermalise(20)
     fr = ref.get_field()
     slab_fields = []
-    for variant, slab, tile, xcd in (("quad", 0, 0, True), ("zslab", 0, 0, True), ("zslab", 1, 1, False),
+    for variant, slab, tile, xcd in (("quad", 0, 0, True), ("resident", 0, 0, True), ("fused", 0, 0, True),
+                                     ("fused", 5, 0, False), ("zslab", 0, 0, True), ("zslab", 1, 1, False),
                                      ("zslab", 7, 2, True), ("zslab", 20, 3, False), ("zslab", 5, 4, True),
                                      ("zslab", 3, 5, True), ("zslab", 9, 6, False), ("zslab", 16, 7, True)):
         a = lat_mod.Lattice(shape, seed=7)
@@ -94,7 +104,7 @@ def test_variants_agree(lat_mod):
         a.thermalise(20)
         fa = a.get_field()
         assert np.abs(fa - fr).max() <= 1e-6 * np.abs(fr).max(), (variant, slab, tile, xcd)
-        if variant == "zslab":
+        if variant in ("zslab", "fused"):
             slab_fields.append(fa)
     for f in slab_fields[1:]:
         np.testing.assert_array_equal(f, slab_fields[0])
@@ -335,7 +345,7 @@ def _sampled_sweep_parity(lat_mod, shape, variant, n_samples=4096, storage="fp32
     return before, after
 
 
-@pytest.mark.parametrize("variant", ["quad", "zslab"])
+@pytest.mark.parametrize("variant", ["quad", "zslab", "fused"])
 def test_sampled_parity_large(lat_mod, variant):
     print(f"[gpu] sampled parity 256^3 {variant}", flush=True)
     _sampled_sweep_parity(lat_mod, (256, 256, 256), variant)
