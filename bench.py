@@ -10,9 +10,12 @@ Default workload: the largest one-GPU machine, 768^3 sites (FP32 field 1.69 GiB),
 input (the paper's tests use synthetic charge placements only).
 
 Prints one JSON line: whole-job site updates/s, the roofline of the dominant
-kernel (the half-sweep) from HIP events around its own launches on the
-library's stream, and the CPU oracle timed on a bounded sample of the same
-workload.
+kernel (the sweep kernel the autotuner picked) from HIP events around its own
+launches on the library's stream, the time to a 1% statistical error on E_N
+(extrapolated from the measured binned error and the exact lattice energy
+stored in tests/golden/exact_energies.json), the same sweep with FP16 field
+storage and the 512-chain batched workload for comparison, and the CPU oracle
+timed on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -34,6 +37,7 @@ if ROOT not in sys.path:
 METRIC = "site updates/s + HBM GB/s; time to E_N at 1% stat error vs plain FP32 sweep"
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+EXACT_FILE = os.path.join(ROOT, "tests", "golden", "exact_energies.json")
 
 
 def parse():
@@ -45,8 +49,15 @@ def parse():
                    choices=["largest_subdomain_768", "large_neutral_256", "gaussian_blob_384",
                             "small_neutral_16"])
     p.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
-    p.add_argument("--variant", default="auto", choices=["auto", "quad", "generic", "fused"])
-    p.add_argument("--bin-size", type=int, default=100)
+    p.add_argument("--variant", default="tuned",
+                   choices=["tuned", "auto", "quad", "generic", "zslab", "fused", "resident"],
+                   help="tuned: the library's autotuner picks kernel, slab depth and tile")
+    p.add_argument("--bin-size", type=int, default=50)
+    p.add_argument("--no-extras", action="store_true", help="skip the FP16 and batched comparisons")
+    p.add_argument("--planes", type=int, default=None, help="slab kernels: planes per workgroup")
+    p.add_argument("--tile", type=int, default=0, help="zslab: tile configuration 0..7")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run a plain device copy of the workload's colour-array size (counter calibration)")
     p.add_argument("--kernel-reps", type=int, default=50,
                    help="sweeps timed for the per-kernel (half-sweep) duration")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -78,6 +89,97 @@ def stored_traffic(key: str):
     if not e or e.get("sources_hash") != sources_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def exact_energy(workload: str):
+    try:
+        with open(EXACT_FILE) as f:
+            return json.load(f)[workload]["E_lat"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def time_to_1pct(t_run_s: float, stderr: float, e_exact):
+    """t_run (eps_run / 0.01)^2 with eps_run = binned stderr / |E_exact|:
+    samples needed for a 1% relative error, at the measured cost per sample
+    (the binned error already carries the autocorrelation)."""
+    if e_exact is None or not math.isfinite(stderr) or e_exact == 0:
+        return None
+    eps = stderr / abs(e_exact)
+    return {"seconds": t_run_s * (eps / 0.01) ** 2, "eps_run": eps, "E_exact": e_exact,
+            "kind": "extrapolated"}
+
+
+def kernel_roofline(lat, stream, V: int, esz: int, variant: str, reps: int, torch):
+    """Average duration of the dominant sweep kernel, from HIP events around
+    `reps` unmeasured sweeps on the library's stream, and its algorithmic
+    bytes per launch."""
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    lat.thermalise(reps)
+    ev1.record(stream)
+    ev1.synchronize()
+    sweep_ms = ev0.elapsed_time(ev1) / reps
+    if variant == "fused":
+        return sweep_ms, sweep_ms, 3 * (V // 2) * esz, "fused_sweep"  # read colour 1, write both colours
+    if variant == "resident":
+        return sweep_ms, sweep_ms, 2 * (V // 2) * 2 * esz, "resident_chain"
+    return sweep_ms, sweep_ms / 2.0, (V // 2) * 2 * esz, f"halfsweep_{variant}"  # read other colour, write own
+
+
+def kernel_key(kname: str, lat_tuning: dict, workload: str, storage: str) -> str:
+    """Key of the stored counters: kernel, slab planes and tile, workload, storage."""
+    t = lat_tuning or {}
+    return f"{kname}_p{t.get('planes', 0)}_t{t.get('tile', 0)}_{workload}_{storage}"
+
+
+def fp16_comparison(cs, seed, steps, bin_size, torch, lattice):
+    """The same workload with FP16 field storage (FP32 arithmetic): per-step time."""
+    lat = lattice.Lattice(cs.shape, "fp16", seed=seed)
+    tune = lat.autotune(5)
+    lat.set_charges(cs.xyz, cs.q)
+    lat.sweep_and_measure(5, 1, bin_size)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.sweep_and_measure(steps, 1, bin_size)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lat.close()
+    return {"ms_per_step": 1e3 * dt / steps, "site_updates_per_s": int(np.prod(cs.shape)) * steps / dt,
+            "tuning": tune}
+
+
+def batched_comparison(sweeps, torch, lattice, workloads):
+    """512 chains (edges 24..64, 16..512 charges) in one persistent launch."""
+    chains = workloads.batched_chains(seed=0)
+    b = lattice.Batch([c.shape for c in chains], "fp32", seed=0)
+    for k, c in enumerate(chains):
+        b.set_charges(k, c.xyz, c.q)
+    b.run(5, 10, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(0, sweeps, 10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sites = sum(int(np.prod(c.shape)) for c in chains)
+    b.close()
+    return {"chains": len(chains), "sites": sites, "sweeps": sweeps, "seconds": dt,
+            "site_updates_per_s": sites * sweeps / dt}
+
+
+def calibrate_copy(spec, torch):
+    """A plain copy of one colour array of the workload (read n*4 B, write
+    n*4 B, n = V/2 FP32 values), three times: run under rocprofv3 --pmc, its
+    FETCH_SIZE / WRITE_SIZE per dispatch against the known bytes give the
+    counters' scale factors."""
+    cs = spec["make"]()
+    n = int(np.prod(cs.shape)) // 2
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": n * 4, "calibrate_copy_bytes_written": n * 4}), flush=True)
 
 
 def cpu_baseline(cs, storage: str, seed: int):
@@ -113,6 +215,9 @@ def main():
         sys.exit(1)
     lattice.load_library()
     spec = workloads.WORKLOADS[args.workload]
+    if args.calibrate_copy:
+        calibrate_copy(spec, torch)
+        return
     cs = spec["make"]()
     seed = spec["philox_seed"]
     V = int(np.prod(cs.shape))
@@ -121,7 +226,15 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     lat = lattice.Lattice(cs.shape, args.storage, seed=seed, chain_id=0, device=0, stream=stream)
-    lat.set_variant(args.variant)
+    tuning = None
+    if args.variant == "tuned":
+        tuning = lat.autotune(5)
+        variant = tuning["variant"]
+    else:
+        lat.set_variant(args.variant)
+        variant = args.variant
+        if args.planes is not None:
+            lat.set_tuning(args.planes, args.tile, True)
     lat.set_charges(cs.xyz, cs.q)
 
     # warmup: W measured sweeps (untimed)
@@ -136,29 +249,16 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = V * args.steps / elapsed
 
-    # dominant kernel: the half-sweep, timed with HIP events on the library's
-    # stream around `kernel_reps` unmeasured sweeps (2 launches each)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    lat.thermalise(args.kernel_reps)
-    ev1.record(stream)
-    ev1.synchronize()
-    sweep_ms = ev0.elapsed_time(ev1) / args.kernel_reps
     esz = 4 if args.storage == "fp32" else 2
-    fused = args.variant == "fused"
-    if fused:
-        launch_ms = sweep_ms  # one launch per sweep
-        bytes_per_launch = 3 * (V // 2) * esz  # read colour 1, write colour 0 and colour 1
-        kname = "fused_sweep"
-    else:
-        launch_ms = sweep_ms / 2.0
-        bytes_per_launch = (V // 2) * 2 * esz  # read other colour, write own colour
-        kname = "halfsweep"
+    sweep_ms, launch_ms, bytes_per_launch, kname = kernel_roofline(
+        lat, stream, V, esz, variant, args.kernel_reps, torch)
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     measure_ms = max(ms_per_step - sweep_ms, 0.0)
-    traffic = stored_traffic(f"{kname}_{args.workload}_{args.storage}")
+    used = tuning if tuning is not None else {"planes": args.planes or 0, "tile": args.tile}
+    traffic = stored_traffic(kernel_key(kname, used, args.workload, args.storage))
 
     m, se, M, nb = lat.energy_estimate(allow_few_bins=True)
+    e_exact = exact_energy(args.workload)
     out = {
         "metric": METRIC,
         "value": value,
@@ -173,13 +273,15 @@ def main():
         "dtype": "f32" if args.storage == "fp32" else f"f32 arithmetic, {args.storage} storage",
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": list(cs.shape), "charges": cs.n,
-                   "charged_sites": cs.n, "storage": args.storage, "variant": args.variant,
+                   "storage": args.storage, "variant": variant, "tuning": tuning,
                    "measure_every": 1, "bin_size": args.bin_size, "philox_seed": seed},
         "hbm_gbps": achieved,
         "sweep_ms": sweep_ms,
         "measure_ms": measure_ms,
         "samples": M,
-        "estimate": {"mean": m, "stderr": se if math.isfinite(se) else None, "bins": nb},
+        "estimate": {"mean": m, "stderr": se if math.isfinite(se) else None, "bins": nb,
+                     "E_exact": e_exact},
+        "time_to_1pct": time_to_1pct(ms_per_step * 1e-3 * M, se, e_exact),
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms,
@@ -188,6 +290,15 @@ def main():
     lat.close()
     del lat
     torch.cuda.synchronize()
+    if not args.no_extras:
+        try:
+            if args.storage == "fp32":
+                f16 = fp16_comparison(cs, seed, min(args.steps, 200), args.bin_size, torch, lattice)
+                f16["speedup_vs_fp32"] = ms_per_step / f16["ms_per_step"]
+                out["fp16_storage"] = f16
+            out["batched_512"] = batched_comparison(200, torch, lattice, workloads)
+        except Exception as exc:  # comparisons must not hide the headline line
+            out["extras_error"] = repr(exc)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cs, args.storage, seed)
     print(json.dumps(out), flush=True)

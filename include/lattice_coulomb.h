@@ -151,6 +151,24 @@ int lattice_set_variant(lattice_t *lat, int variant);
  * contiguous run of tiles.  Results do not depend on any of them. */
 int lattice_set_tuning(lattice_t *lat, int64_t planes, int tile, int xcd_order);
 
+/* Graph capture of the multi-launch sweep path: runs of sweeps (with their
+ * samples) are recorded once as a hipGraph of K-sweep chunks whose kernels
+ * read the sweep and sample counters from device memory, then replayed.
+ * mode 0: never; 1 (default): boxes of at most 2^24 sites, whose sweeps are
+ * short enough for launch overhead to matter; 2: every box.  Results do not
+ * depend on the mode. */
+int lattice_use_graphs(lattice_t *lat, int mode);
+
+/* Autotuner: time every sweep kernel and tuning that can handle this box
+ * (reps sweeps each, after one warm-up sweep) on scratch memory of the
+ * handle's size, so the chain itself is not advanced; select the fastest on
+ * the handle and cache it per (box, storage) for the process.  Outputs (any
+ * may be NULL): the chosen variant, planes, tile, XCD order and the measured
+ * ms per sweep.  Synchronises the stream.  Errors: LAT_ERR_ARG for reps
+ * outside [1, 1000]; LAT_ERR_ALLOC if the scratch cannot be allocated. */
+int lattice_autotune(lattice_t *lat, int64_t reps, int *variant, int64_t *planes, int *tile,
+                     int *xcd_order, double *ms_per_sweep);
+
 /* ---- test / checkpoint hooks (all synchronise the stream) ---------- */
 
 /* Copy the field to host_out: lx*ly*lz floats, natural order x fastest. */

@@ -53,7 +53,9 @@ __global__ __launch_bounds__(1024) void fused_sweep(typename St::T* __restrict__
                                                     const typename St::T* __restrict__ b_in,
                                                     typename St::T* __restrict__ b_out, uint32_t lh, uint32_t ly,
                                                     uint32_t lz, uint32_t ty_rows, uint32_t zc, uint32_t h0,
-                                                    uint32_t k0, uint32_t k1, uint32_t chain, uint32_t xcd_order) {
+                                                    uint32_t k0, uint32_t k1, uint32_t chain, uint32_t xcd_order,
+                                                    const uint32_t* __restrict__ tdev) {
+    if (tdev) h0 += 2u * tdev[0];  // graph replays: sweep counter kept on the device
     extern __shared__ __align__(16) float lds[];
     const uint32_t TY = ty_rows, nq = lh >> 2;
     const uint32_t rowsB = TY + 4, rowsA = TY + 2;
@@ -181,13 +183,24 @@ static hipError_t launch_fused_t(const FusedArgs& a, hipStream_t stream) {
     const uint32_t zc = a.slab ? a.slab : 32u;
     const uint32_t nb = ((a.ly + ty - 1) / ty) * ((a.lz + zc - 1) / zc);
     const size_t lds = (size_t)3 * ((ty + 4) + (ty + 2)) * a.lh * sizeof(float);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_sweep<St>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fused_sweep<St>, dim3(nb), dim3(nq * kFusedRowLanes), lds, stream,
                        static_cast<T*>(a.c0), static_cast<const T*>(a.b_in), static_cast<T*>(a.b_out), a.lh, a.ly,
-                       a.lz, ty, zc, a.h0, a.k0, a.k1, a.chain, a.xcd_order);
+                       a.lz, ty, zc, a.h0, a.k0, a.k1, a.chain, a.xcd_order, a.tdev);
     return hipGetLastError();
+}
+
+// Allow the fused kernels the whole LDS of a CU (dynamic shared memory);
+// called once before any fused launch, outside stream capture.
+hipError_t prepare_fused_sweep() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_sweep<StoreF32>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_sweep<StoreBF16>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_sweep<StoreF16>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
+    return e;
 }
 
 hipError_t launch_fused_sweep(const FusedArgs& a, hipStream_t stream) {

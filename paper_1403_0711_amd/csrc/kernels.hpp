@@ -20,9 +20,13 @@ struct SweepArgs {
     uint32_t zc;      // zslab: planes per workgroup (0 = default)
     uint32_t xcd_order;  // zslab: XCD-aware block order
     uint32_t tile;    // zslab: tile configuration, 0 .. kZslabTiles - 1
+    const uint32_t* tdev;  // if set, h += 2 * tdev[0] (sweep counter on the device)
 };
 constexpr int kZslabTiles = 8;
 hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream);
+// device-side sweep / sample counters (ctr[0], ctr[1]) for graph replays
+hipError_t launch_set_counters(uint32_t* ctr, uint32_t t, uint32_t m, hipStream_t stream);
+hipError_t launch_advance_counters(uint32_t* ctr, uint32_t dt, uint32_t dm, hipStream_t stream);
 
 // Both half-sweeps of sweep t in one pass (temporal blocking), lh % 4 == 0.
 struct FusedArgs {
@@ -35,8 +39,10 @@ struct FusedArgs {
     int storage;
     uint32_t slab;     // planes per workgroup along z (0 = default)
     uint32_t xcd_order;
+    const uint32_t* tdev;  // if set, h0 += 2 * tdev[0]
 };
 hipError_t launch_fused_sweep(const FusedArgs& a, hipStream_t stream);
+hipError_t prepare_fused_sweep();  // once, before fused launches and outside capture
 
 // Gather of the charge-weighted correlator after a sweep (Eq. nsum2):
 // X = sum_s Q_s phi_s, Y = sum_s S_s phi_s^2 over the site-aggregated charge
@@ -51,7 +57,9 @@ struct MeasureArgs {
     uint32_t n;            // number of charged sites
     double* partials;      // 2 * blocks scratch
     double* bins;
-    uint32_t bin;
+    uint32_t m;            // sample index (relative to *mdev when mdev is set)
+    uint32_t bin_size;
+    const uint32_t* mdev;  // sample counter on the device, or null
     double* last_xy;       // X, Y of this sample
     int storage;
     uint32_t blocks;       // grid size (fixed for a given n: fixes the sum order)

@@ -6,7 +6,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.hpp"
@@ -16,7 +19,7 @@
 using namespace latcoul;
 
 // largest box that AUTO runs with the one-workgroup resident kernel
-constexpr uint64_t kResidentMaxSites = 32768;
+constexpr uint64_t kResidentMaxSites = 16384;
 
 struct lattice {
     int64_t lx = 0, ly = 0, lz = 0;
@@ -48,12 +51,25 @@ struct lattice {
     int64_t bin_size = 0;
     int64_t n_meas = 0;
     int64_t t = 0;
+    // captured chunks of sweeps (hipGraph) for boxes whose sweeps are short
+    struct SweepGraph {
+        hipGraphExec_t exec = nullptr;
+        int64_t K = 0, every = 0, bin_size = 0;
+        int variant = -1;
+        uint32_t slab = 0, tile = 0, xcd = 0;
+        const void* bins = nullptr;
+        const void* site = nullptr;
+    };
+    SweepGraph g_therm, g_meas;
+    hipStream_t cap = nullptr;  // private capture stream
+    int graph_mode = 1;         // 0 never, 1 boxes up to 2^24 sites, 2 always
     int variant = LAT_SWEEP_AUTO;
     uint32_t slab = 16;      // planes per workgroup for the slab kernels (0 = kernel default)
     uint32_t xcd_order = 1;  // XCD-aware workgroup order for the slab kernels
     uint32_t tile = 0;       // tile configuration of the slab kernel
 
     double* last_xy() { return reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
+    uint32_t* counters() { return static_cast<uint32_t*>(d_misc); }  // [0] sweeps, [1] samples
     void* c1main() const { return static_cast<char*>(field) + (size_t)vh * esz; }
     void* c1cur() const { return alt_current ? c1alt : c1main(); }
     int effective_variant() const {
@@ -74,32 +90,39 @@ static int check_lattice(const lattice* L) {
     return LAT_OK;
 }
 
-static int enqueue_sweep(lattice* L) {
-    if (L->t >= (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_STATE, "sweep counter exhausted (2^31 sweeps)");
-    const uint32_t h0 = (uint32_t)(2 * L->t);
+// One sweep on `stream`.  Eager (tdev null): sweep index L->t, which is
+// advanced.  Captured: index tdev[0] + rel, read on the device at run time.
+static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint32_t rel) {
+    const uint32_t h0 = tdev ? 2u * rel : (uint32_t)(2 * L->t);
     const int v = L->effective_variant();
     hipError_t e;
     if (v == LAT_SWEEP_FUSED) {
         void* out = L->alt_current ? L->c1main() : L->c1alt;
         FusedArgs a{L->field, L->c1cur(), out, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, h0,
-                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, L->slab, L->xcd_order};
-        e = launch_fused_sweep(a, L->stream);
+                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, L->slab, L->xcd_order,
+                    tdev};
+        e = launch_fused_sweep(a, stream);
         if (e == hipSuccess) L->alt_current = !L->alt_current;
     } else {
         const int kv = v == LAT_SWEEP_QUAD ? kVariantQuad : v == LAT_SWEEP_ZSLAB ? kVariantZslab : kVariantGeneric;
         SweepArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, 0u, h0,
                     (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, kv, L->slab,
-                    L->xcd_order, L->tile};
-        e = launch_halfsweep(a, L->stream);
+                    L->xcd_order, L->tile, tdev};
+        e = launch_halfsweep(a, stream);
         if (e == hipSuccess) {
             a.c = 1u;
             a.h = h0 + 1u;
-            e = launch_halfsweep(a, L->stream);
+            e = launch_halfsweep(a, stream);
         }
     }
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
-    L->t += 1;
+    if (!tdev) L->t += 1;
     return LAT_OK;
+}
+
+static int enqueue_sweep(lattice* L) {
+    if (L->t >= (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_STATE, "sweep counter exhausted (2^31 sweeps)");
+    return enqueue_sweep_ex(L, L->stream, nullptr, 0);
 }
 
 // The resident path: n_therm unmeasured sweeps then n_meas sweeps with a
@@ -140,15 +163,19 @@ static int enqueue_resident(lattice* L, int64_t n_therm, int64_t n_meas, int64_t
     return LAT_OK;
 }
 
-static int enqueue_measure(lattice* L) {
+// One sample on `stream`.  Eager (mdev null): sample index L->n_meas, which
+// is advanced.  Captured: index mdev[0] + rel on the device.
+static int enqueue_measure_ex(lattice* L, hipStream_t stream, const uint32_t* mdev, uint32_t rel) {
     MeasureArgs a{L->field, L->c1cur(), L->vh, L->d_site, L->d_Q, L->d_S, L->n_sites, L->d_partials,
-                  L->d_bins, (uint32_t)(L->n_meas / L->bin_size), L->last_xy(), L->storage,
-                  L->meas_blocks};
-    hipError_t e = launch_measure(a, L->stream);
+                  L->d_bins, mdev ? rel : (uint32_t)L->n_meas, (uint32_t)L->bin_size, mdev, L->last_xy(),
+                  L->storage, L->meas_blocks};
+    hipError_t e = launch_measure(a, stream);
     if (e != hipSuccess) return hip_fail(e, "measure launch");
-    L->n_meas += 1;
+    if (!mdev) L->n_meas += 1;
     return LAT_OK;
 }
+
+static int enqueue_measure(lattice* L) { return enqueue_measure_ex(L, L->stream, nullptr, 0); }
 
 // After fused sweeps colour 1 may sit in the second array: copy it home so
 // that every other path sees colour 0 then colour 1 in `field`.
@@ -158,6 +185,114 @@ static int settle_colour1(lattice* L) {
     if (e != hipSuccess) return hip_fail(e, "colour-1 copy");
     L->alt_current = false;
     return LAT_OK;
+}
+
+static void graph_reset(lattice::SweepGraph& g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = lattice::SweepGraph();
+}
+
+static void graphs_reset(lattice* L) {
+    graph_reset(L->g_therm);
+    graph_reset(L->g_meas);
+}
+
+// Sweeps per captured chunk, or 0 to run eagerly: a multiple of
+// measure_every (every > 0), even (the fused kernel alternates colour-1
+// arrays, so a chunk must end where it starts).
+static int64_t graph_chunk(const lattice* L, int64_t every) {
+    if (L->graph_mode == 0) return 0;
+    const int v = L->effective_variant();
+    if (v == LAT_SWEEP_RESIDENT) return 0;
+    if (L->graph_mode == 1 && (uint64_t)L->vh * 2 > ((uint64_t)1 << 24)) return 0;
+    int64_t K = 32;
+    if (every > 0) {
+        if (every > 256) return 0;
+        K = (32 + every - 1) / every * every;
+    }
+    if (K % 2) K *= 2;
+    return K;
+}
+
+static bool graph_matches(const lattice* L, const lattice::SweepGraph& g, int64_t K, int64_t every) {
+    return g.exec && g.K == K && g.every == every && g.variant == L->effective_variant() && g.slab == L->slab &&
+           g.tile == L->tile && g.xcd == L->xcd_order && g.site == L->d_site &&
+           (every == 0 || (g.bins == L->d_bins && g.bin_size == L->bin_size));
+}
+
+// Record K sweeps (and their samples) relative to the device counters,
+// followed by a one-thread kernel that advances the counters: the graph is
+// then replayed unchanged.  Kernels only (no memset or copy nodes).
+static int graph_capture(lattice* L, lattice::SweepGraph& g, int64_t K, int64_t every) {
+    graph_reset(g);
+    hipError_t e = hipSuccess;
+    if (!L->cap) e = hipStreamCreateWithFlags(&L->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    const bool alt0 = L->alt_current;
+    e = hipStreamBeginCapture(L->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    int rc = LAT_OK;
+    uint32_t m = 0;
+    for (int64_t s = 0; s < K && rc == LAT_OK; ++s) {
+        rc = enqueue_sweep_ex(L, L->cap, L->counters(), (uint32_t)s);
+        if (rc == LAT_OK && every > 0 && (s + 1) % every == 0)
+            rc = enqueue_measure_ex(L, L->cap, L->counters() + 1, m++);
+    }
+    if (rc == LAT_OK) {
+        e = launch_advance_counters(L->counters(), (uint32_t)K, m, L->cap);
+        if (e != hipSuccess) rc = hip_fail(e, "capture");
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(L->cap, &graph);
+    L->alt_current = alt0;
+    if (rc != LAT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "end capture");
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        g.exec = nullptr;
+        return hip_fail(e, "graph instantiation");
+    }
+    g.K = K;
+    g.every = every;
+    g.bin_size = L->bin_size;
+    g.variant = L->effective_variant();
+    g.slab = L->slab;
+    g.tile = L->tile;
+    g.xcd = L->xcd_order;
+    g.bins = L->d_bins;
+    g.site = L->d_site;
+    return LAT_OK;
+}
+
+static int settle_colour1(lattice* L);
+
+// n sweeps with a sample after every `every`-th (every = 0: no samples):
+// whole chunks as graph replays where that pays, the rest launch by launch.
+static int run_sweeps(lattice* L, int64_t n, int64_t every) {
+    int64_t done = 0;
+    const int64_t K = graph_chunk(L, every);
+    if (K > 0 && n >= K) {
+        lattice::SweepGraph& g = every > 0 ? L->g_meas : L->g_therm;
+        if (!graph_matches(L, g, K, every))
+            if (int r = graph_capture(L, g, K, every)) return r;
+        hipError_t e = launch_set_counters(L->counters(), (uint32_t)L->t, (uint32_t)L->n_meas, L->stream);
+        const int64_t chunks = n / K;
+        for (int64_t r = 0; r < chunks && e == hipSuccess; ++r) e = hipGraphLaunch(g.exec, L->stream);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+        done = chunks * K;
+        L->t += done;
+        if (every > 0) L->n_meas += done / every;
+    }
+    for (int64_t s = done; s < n; ++s) {
+        if (int r = enqueue_sweep(L)) return r;
+        if (every > 0 && (s + 1) % every == 0)
+            if (int r = enqueue_measure(L)) return r;
+    }
+    return settle_colour1(L);
 }
 
 static int ensure_bins(lattice* L, int64_t n_bins_needed) {
@@ -179,7 +314,138 @@ static int ensure_bins(lattice* L, int64_t n_bins_needed) {
     return LAT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: times every sweep kernel and tuning that can handle a box on
+// scratch memory, keeps the fastest; choices are cached per (box, storage).
+// ---------------------------------------------------------------------------
+struct TuneChoice {
+    int variant;
+    uint32_t slab, tile, xcd;
+    double ms;
+};
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int64_t, int64_t, int64_t, int>, TuneChoice> g_tune_cache;
+
+// Candidates in order of preference: the first is the library default for
+// the box; a later one replaces the current best only if it is more than 3%
+// faster, so that choices do not flip on timing noise.
+static std::vector<TuneChoice> tune_candidates(const lattice* L) {
+    std::vector<TuneChoice> c;
+    const uint64_t V = (uint64_t)L->vh * 2;
+    if (V <= kResidentMaxSites) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
+    if (L->lh % 4 != 0) {
+        if (V > kResidentMaxSites && V <= (uint64_t)1 << 18) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
+        c.push_back({LAT_SWEEP_GENERIC, 0, 0, 1, 0});
+        return c;
+    }
+    const bool slab_ok = (size_t)L->vh * L->esz < ((size_t)1 << 31);
+    if (slab_ok && (size_t)2 * L->vh * L->esz > ((size_t)256 << 20)) c.push_back({LAT_SWEEP_ZSLAB, 16, 0, 1, 0});
+    c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
+    if (V > kResidentMaxSites && V <= (uint64_t)1 << 18) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
+    if (slab_ok)
+        for (uint32_t tile : {0u, 1u, 7u})
+            for (uint32_t slab : {8u, 16u, 32u})
+                if (slab <= L->lz && !(tile == 0 && slab == 16)) c.push_back({LAT_SWEEP_ZSLAB, slab, tile, 1, 0});
+    if (fused_sweep_supported(L->lh, (uint32_t)L->ly))
+        for (uint32_t slab : {16u, 32u})
+            if (slab <= L->lz) c.push_back({LAT_SWEEP_FUSED, slab, 0, 1, 0});
+    return c;
+}
+
+static void apply_choice(lattice* L, const TuneChoice& ch) {
+    L->variant = ch.variant;
+    L->slab = ch.slab;
+    L->tile = ch.tile;
+    L->xcd_order = ch.xcd;
+}
+
+static int autotune(lattice* L, int64_t reps, TuneChoice* out) {
+    const auto key = std::make_tuple(L->lx, L->ly, L->lz, L->storage);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            return LAT_OK;
+        }
+    }
+    const std::vector<TuneChoice> cands = tune_candidates(L);
+    if (fused_sweep_supported(L->lh, (uint32_t)L->ly))
+        if (hipError_t e = prepare_fused_sweep()) return hip_fail(e, "fused sweep set-up");
+    const size_t fbytes = round_up(2 * (size_t)L->vh * L->esz, 256);
+    void* scratch = L->mem.alloc(fbytes);
+    void* scratch_alt = L->mem.alloc(round_up((size_t)L->vh * L->esz, 256));
+    if (!scratch || !scratch_alt) {
+        L->mem.release(scratch);
+        L->mem.release(scratch_alt);
+        return set_error(LAT_ERR_ALLOC, "allocation of autotuning scratch failed");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMemsetAsync(scratch, 0, fbytes, L->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    TuneChoice best{LAT_SWEEP_AUTO, 0, 0, 1, 1e30};
+    int rc = LAT_OK;
+    for (size_t i = 0; i < cands.size() && e == hipSuccess && rc == LAT_OK; ++i) {
+        lattice tmp = *L;  // shallow copy: same sizes and streams, scratch field, no charges
+        tmp.field = scratch;
+        tmp.c1alt = scratch_alt;
+        tmp.alt_current = false;
+        tmp.t = 0;
+        tmp.n_meas = 0;
+        apply_choice(&tmp, cands[i]);
+        auto run = [&](int64_t n) {
+            if (tmp.variant == LAT_SWEEP_RESIDENT) return enqueue_resident(&tmp, n, 0, 1);
+            for (int64_t k = 0; k < n; ++k)
+                if (int r = enqueue_sweep(&tmp)) return r;
+            return (int)LAT_OK;
+        };
+        rc = run(1);
+        if (rc == LAT_OK) e = hipEventRecord(e0, L->stream);
+        if (rc == LAT_OK && e == hipSuccess) rc = run(reps);
+        if (rc == LAT_OK && e == hipSuccess) e = hipEventRecord(e1, L->stream);
+        if (rc == LAT_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (rc == LAT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (rc == LAT_OK && e == hipSuccess && ms / reps < 0.97 * best.ms) {
+            best = cands[i];
+            best.ms = ms / reps;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(L->stream);
+    L->mem.release(scratch);
+    L->mem.release(scratch_alt);
+    if (rc != LAT_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotuning");
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    *out = best;
+    return LAT_OK;
+}
+
 extern "C" {
+
+int lattice_autotune(lattice_t* L, int64_t reps, int* variant, int64_t* planes, int* tile, int* xcd_order,
+                     double* ms_per_sweep) {
+    if (int r = check_lattice(L)) return r;
+    if (reps < 1 || reps > 1000) return set_error(LAT_ERR_ARG, "reps must be in [1, 1000]");
+    TuneChoice ch;
+    if (int r = autotune(L, reps, &ch)) return r;
+    if (ch.variant == LAT_SWEEP_FUSED)
+        if (int r = lattice_set_variant(L, LAT_SWEEP_FUSED)) return r;  // allocates the second colour-1 array
+    apply_choice(L, ch);
+    graphs_reset(L);
+    if (variant) *variant = ch.variant;
+    if (planes) *planes = ch.slab;
+    if (tile) *tile = (int)ch.tile;
+    if (xcd_order) *xcd_order = (int)ch.xcd;
+    if (ms_per_sweep) *ms_per_sweep = ch.ms;
+    return LAT_OK;
+}
 
 int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t seed, uint32_t chain_id,
                    const lat_allocator* alloc, void* hip_stream, lattice_t** out) {
@@ -224,6 +490,8 @@ int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t see
 void lattice_destroy(lattice_t* L) {
     if (!L) return;
     (void)hipStreamSynchronize(L->stream);
+    graphs_reset(L);
+    if (L->cap) (void)hipStreamDestroy(L->cap);
     L->mem.release(L->field);
     L->mem.release(L->c1alt);
     L->mem.release(L->d_misc);
@@ -264,10 +532,20 @@ int lattice_set_variant(lattice_t* L, int variant) {
                 L->c1alt = L->mem.alloc(round_up((size_t)L->vh * L->esz, 256));
                 if (!L->c1alt) return set_error(LAT_ERR_ALLOC, "allocation of the second colour-1 array failed");
             }
+            if (hipError_t e = prepare_fused_sweep()) return hip_fail(e, "fused sweep set-up");
             break;
         default: return set_error(LAT_ERR_ARG, "unknown sweep variant");
     }
     L->variant = variant;
+    graphs_reset(L);
+    return LAT_OK;
+}
+
+int lattice_use_graphs(lattice_t* L, int mode) {
+    if (int r = check_lattice(L)) return r;
+    if (mode < 0 || mode > 2) return set_error(LAT_ERR_ARG, "graph mode must be 0, 1 or 2");
+    L->graph_mode = mode;
+    graphs_reset(L);
     return LAT_OK;
 }
 
@@ -278,6 +556,7 @@ int lattice_set_tuning(lattice_t* L, int64_t planes, int tile, int xcd_order) {
     L->slab = (uint32_t)planes;
     L->tile = (uint32_t)tile;
     L->xcd_order = xcd_order ? 1u : 0u;
+    graphs_reset(L);
     return LAT_OK;
 }
 
@@ -323,6 +602,7 @@ int set_charges(lattice_t* L, int64_t n, const int32_t* xyz, const double* q) {
     L->mem.release(L->d_Q);
     L->mem.release(L->d_S);
     L->mem.release(L->d_partials);
+    graphs_reset(L);
     L->d_site = d_site;
     L->d_Q = d_Q;
     L->d_S = d_S;
@@ -345,9 +625,7 @@ int thermalise(lattice_t* L, int64_t n_sweeps) {
     if (n_sweeps < 0) return set_error(LAT_ERR_ARG, "n_sweeps < 0");
     if (L->t + n_sweeps > (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_ARG, "sweep counter would exceed 2^31");
     if (L->effective_variant() == LAT_SWEEP_RESIDENT) return enqueue_resident(L, n_sweeps, 0, 1);
-    for (int64_t s = 0; s < n_sweeps; ++s)
-        if (int r = enqueue_sweep(L)) return r;
-    return settle_colour1(L);
+    return run_sweeps(L, n_sweeps, 0);
 }
 
 int sweep_and_measure(lattice_t* L, int64_t n_sweeps, int64_t measure_every, int64_t bin_size) {
@@ -369,12 +647,7 @@ int sweep_and_measure(lattice_t* L, int64_t n_sweeps, int64_t measure_every, int
     if (int r = ensure_bins(L, (total + bin_size - 1) / bin_size)) return r;
     L->bin_size = bin_size;
     if (L->effective_variant() == LAT_SWEEP_RESIDENT) return enqueue_resident(L, 0, n_sweeps, measure_every);
-    for (int64_t s = 0; s < n_sweeps; ++s) {
-        if (int r = enqueue_sweep(L)) return r;
-        if ((s + 1) % measure_every == 0)
-            if (int r = enqueue_measure(L)) return r;
-    }
-    return settle_colour1(L);
+    return run_sweeps(L, n_sweeps, measure_every);
 }
 
 int energy_estimate(lattice_t* L, double* mean, double* stderr_binned, int64_t* n_samples, int64_t* n_bins) {

@@ -68,9 +68,14 @@ __global__ __launch_bounds__(kMeasureThreads) void gather_partials(const typenam
     }
 }
 
+// Sample m (counted from the device counter mdev when given: graph replays)
+// goes to bin (m [+ *mdev]) / bin_size.
 __global__ __launch_bounds__(kMeasureThreads) void finalize_measure(const double* __restrict__ partials,
-                                                                    uint32_t blocks, double* bins, uint32_t bin,
+                                                                    uint32_t blocks, double* bins, uint32_t m,
+                                                                    uint32_t bin_size,
+                                                                    const uint32_t* __restrict__ mdev,
                                                                     double* last_xy) {
+    const uint32_t bin = (m + (mdev ? mdev[0] : 0u)) / bin_size;
     double X = 0.0, Y = 0.0;
     for (uint32_t b = threadIdx.x; b < blocks; b += kMeasureThreads) {
         X += partials[2 * b];
@@ -99,7 +104,7 @@ static hipError_t launch_measure_t(const MeasureArgs& a, hipStream_t stream) {
                        static_cast<const typename St::T*>(a.field0), static_cast<const typename St::T*>(a.field1),
                        a.vh, a.site, a.Q, a.S, a.n, a.partials);
     hipLaunchKernelGGL(finalize_measure, dim3(1), dim3(kMeasureThreads), 0, stream, a.partials, a.blocks,
-                       a.bins, a.bin, a.last_xy);
+                       a.bins, a.m, a.bin_size, a.mdev, a.last_xy);
     return hipGetLastError();
 }
 

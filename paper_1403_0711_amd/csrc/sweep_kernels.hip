@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void halfsweep_quad(const typename St::T* __re
                                                       typename St::T* __restrict__ own, uint32_t lh,
                                                       uint32_t ly, uint32_t lz, uint32_t c,
                                                       uint32_t h, uint32_t k0, uint32_t k1,
-                                                      uint32_t chain) {
+                                                      uint32_t chain, const uint32_t* __restrict__ tdev) {
+    if (tdev) h += 2u * tdev[0];  // graph replays: sweep counter kept on the device
     const uint32_t nq = lh >> 2;
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -77,7 +78,9 @@ __global__ __launch_bounds__(256) void halfsweep_generic(const typename St::T* _
                                                          typename St::T* __restrict__ own,
                                                          uint32_t lh, uint32_t ly, uint32_t lz,
                                                          uint32_t c, uint32_t h, uint32_t k0,
-                                                         uint32_t k1, uint32_t chain) {
+                                                         uint32_t k1, uint32_t chain,
+                                                         const uint32_t* __restrict__ tdev) {
+    if (tdev) h += 2u * tdev[0];
     const uint32_t vh = lh * ly * lz;
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= vh) return;
@@ -200,7 +203,9 @@ __global__ __launch_bounds__(kTX* kTY) __attribute__((amdgpu_waves_per_eu(kWPE, 
                                                            typename St::T* __restrict__ own, uint32_t lh,
                                                            uint32_t ly, uint32_t lz, uint32_t zc, uint32_t c,
                                                            uint32_t h, uint32_t k0, uint32_t k1,
-                                                           uint32_t chain, uint32_t xcd_order) {
+                                                           uint32_t chain, uint32_t xcd_order,
+                                                           const uint32_t* __restrict__ tdev) {
+    if (tdev) h += 2u * tdev[0];
     using K = Zslab<St, kTX, kTY>;
     __shared__ __align__(16) float tile[2][kTY + 2][K::kW];
 
@@ -284,7 +289,7 @@ static hipError_t launch_halfsweep_t(const SweepArgs& a, hipStream_t stream) {
         auto launch = [&](auto kern, int tx, int ty) {
             const uint32_t nb = ((nq + tx - 1) / tx) * ((a.ly + ty - 1) / ty) * ((a.lz + zc - 1) / zc);
             hipLaunchKernelGGL(kern, dim3(nb), dim3(tx, ty, 1), 0, stream, other, own, a.lh, a.ly, a.lz, zc, a.c,
-                               a.h, a.k0, a.k1, a.chain, a.xcd_order);
+                               a.h, a.k0, a.k1, a.chain, a.xcd_order, a.tdev);
         };
         switch (a.tile) {  // tile quads x rows, minimum waves per SIMD
             case 0: launch(halfsweep_zslab<St, 32, 8, 1>, 32, 8); break;
@@ -304,13 +309,31 @@ static hipError_t launch_halfsweep_t(const SweepArgs& a, hipStream_t stream) {
         dim3 block(tx, ty, 1);
         dim3 grid((nq + tx - 1) / tx, (a.ly + ty - 1) / ty, a.lz);
         hipLaunchKernelGGL(halfsweep_quad<St>, grid, block, 0, stream, other, own, a.lh, a.ly, a.lz,
-                           a.c, a.h, a.k0, a.k1, a.chain);
+                           a.c, a.h, a.k0, a.k1, a.chain, a.tdev);
     } else {
         dim3 block(256, 1, 1);
         dim3 grid((a.vh + 255) / 256, 1, 1);
         hipLaunchKernelGGL(halfsweep_generic<St>, grid, block, 0, stream, other, own, a.lh, a.ly,
-                           a.lz, a.c, a.h, a.k0, a.k1, a.chain);
+                           a.lz, a.c, a.h, a.k0, a.k1, a.chain, a.tdev);
     }
+    return hipGetLastError();
+}
+
+// Sets / advances the device-side sweep and sample counters (graph replays).
+__global__ void set_counters(uint32_t* ctr, uint32_t t, uint32_t m) {
+    ctr[0] = t;
+    ctr[1] = m;
+}
+__global__ void advance_counters(uint32_t* ctr, uint32_t dt, uint32_t dm) {
+    ctr[0] += dt;
+    ctr[1] += dm;
+}
+hipError_t launch_set_counters(uint32_t* ctr, uint32_t t, uint32_t m, hipStream_t stream) {
+    hipLaunchKernelGGL(set_counters, dim3(1), dim3(1), 0, stream, ctr, t, m);
+    return hipGetLastError();
+}
+hipError_t launch_advance_counters(uint32_t* ctr, uint32_t dt, uint32_t dm, hipStream_t stream) {
+    hipLaunchKernelGGL(advance_counters, dim3(1), dim3(1), 0, stream, ctr, dt, dm);
     return hipGetLastError();
 }
 

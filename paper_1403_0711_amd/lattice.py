@@ -68,6 +68,9 @@ def load_library() -> ctypes.CDLL:
         "lattice_sweep_count": (_int, [_p, _pi64]),
         "lattice_set_variant": (_int, [_p, _int]),
         "lattice_set_tuning": (_int, [_p, _i64, _int, _int]),
+        "lattice_use_graphs": (_int, [_p, _int]),
+        "lattice_autotune": (_int, [_p, _i64, ctypes.POINTER(_int), _pi64, ctypes.POINTER(_int),
+                                    ctypes.POINTER(_int), _pd]),
         "lattice_get_field": (_int, [_p, _p]),
         "lattice_set_field": (_int, [_p, _p]),
         "lattice_last_measure": (_int, [_p, _pd, _pd]),
@@ -225,6 +228,20 @@ class Lattice:
     def set_tuning(self, planes: int = 16, tile: int = 0, xcd_order: bool = True):
         """Slab-kernel tuning: planes per workgroup, tile configuration, XCD order."""
         self._call(self.lib.lattice_set_tuning, int(planes), int(tile), 1 if xcd_order else 0)
+
+    def use_graphs(self, mode: int = 1):
+        """0: launch by launch; 1: hipGraph chunks for boxes up to 2^24 sites; 2: always."""
+        self._call(self.lib.lattice_use_graphs, int(mode))
+
+    def autotune(self, reps: int = 5) -> dict:
+        """Time the sweep kernels on scratch memory and keep the fastest."""
+        v, t, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        pl, ms = ctypes.c_int64(), ctypes.c_double()
+        self._call(self.lib.lattice_autotune, int(reps), ctypes.byref(v), ctypes.byref(pl), ctypes.byref(t),
+                   ctypes.byref(x), ctypes.byref(ms))
+        names = {val: key for key, val in VARIANT.items()}
+        return {"variant": names.get(v.value, v.value), "planes": pl.value, "tile": t.value,
+                "xcd_order": bool(x.value), "ms_per_sweep": ms.value}
 
     def get_field(self) -> np.ndarray:
         lx, ly, lz = self.shape

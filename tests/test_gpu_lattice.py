@@ -57,7 +57,7 @@ SHAPES = [
     ((16, 16, 16), "resident"),
     ((10, 6, 5), "resident"),
     ((2, 1, 1), "resident"),
-    ((48, 40, 36), "resident"), # 34560 sites: many loop passes per workgroup
+    ((48, 40, 36), "resident"), # 69120 sites: many loop passes per workgroup
 ]
 
 
@@ -356,3 +356,56 @@ def test_sampled_parity_largest_box(lat_mod):
     configuration the benchmark times (library default)."""
     print("[gpu] sampled parity 768^3", flush=True)
     _sampled_sweep_parity(lat_mod, (768, 768, 768), "auto", n_samples=2048)
+
+
+def test_autotune_does_not_advance_the_chain(lat_mod):
+    """The autotuner times kernels on scratch memory: the chain's field and
+    sweep counter are untouched, and the chosen kernel gives the same chain."""
+    print("[gpu] autotune", flush=True)
+    shape = (64, 24, 20)
+    lat = lat_mod.Lattice(shape, seed=3)
+    lat.thermalise(3)
+    before = lat.get_field()
+    choice = lat.autotune(reps=2)
+    assert choice["variant"] in ("quad", "zslab", "fused", "resident")
+    assert lat.sweeps == 3
+    np.testing.assert_array_equal(lat.get_field(), before)
+    lat.thermalise(10)
+    ref = lat_mod.Lattice(shape, seed=3)
+    ref.set_variant("generic")
+    ref.thermalise(13)
+    assert np.abs(lat.get_field() - ref.get_field()).max() <= 1e-6 * np.abs(ref.get_field()).max()
+    # cached: a second lattice of the same box gets the same choice
+    again = lat_mod.Lattice(shape, seed=4).autotune(reps=2)
+    assert again["variant"] == choice["variant"] and again["planes"] == choice["planes"]
+
+
+@pytest.mark.parametrize("variant", ["quad", "zslab", "fused", "generic"])
+def test_graph_replays_match_eager(lat_mod, variant):
+    """Chunks of sweeps recorded as a hipGraph and replayed (kernels reading the
+    sweep and sample counters on the device) give bit-identical fields, bins
+    and estimates to launch-by-launch runs, replay after replay, with eager
+    work and host synchronisations in between."""
+    print(f"[gpu] graphs {variant}", flush=True)
+    shape = (64, 24, 20) if variant != "generic" else (66, 10, 9)
+    c = workloads.small_neutral(seed=5, L=min(shape), n=12)
+    lats = []
+    for mode in (0, 2):
+        lat = lat_mod.Lattice(shape, seed=21, chain_id=2)
+        lat.set_variant(variant)
+        lat.use_graphs(mode)
+        lat.set_charges(c.xyz, c.q)
+        lats.append(lat)
+    for step in range(4):
+        for lat in lats:
+            lat.thermalise(70)            # 2 graph chunks + 6 eager sweeps
+            lat.sweep_and_measure(96, 3, 8)  # one 66-sweep chunk (22 samples) + 30 eager sweeps
+        f0, f1 = lats[0].get_field(), lats[1].get_field()
+        np.testing.assert_array_equal(f0, f1)
+        s0, s1 = lats[0].get_state(), lats[1].get_state()
+        assert s0[0] == s1[0] == 166 * (step + 1) and s0[1] == s1[1] == 32 * (step + 1)
+        np.testing.assert_array_equal(s0[2], s1[2])
+        assert lats[0].last_measure() == lats[1].last_measure()
+    ref = oracle.OracleChain(shape, seed=21, chain=2)
+    ref.sweeps(4 * 166)
+    assert np.abs(lats[1].get_field() - ref.phi).max() <= 1e-5 * np.abs(ref.phi).max()
