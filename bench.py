@@ -50,7 +50,7 @@ def parse():
                             "small_neutral_16"])
     p.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
     p.add_argument("--variant", default="tuned",
-                   choices=["tuned", "auto", "quad", "generic", "zslab", "fused", "resident"],
+                   choices=["tuned", "auto", "quad", "generic", "zslab", "stream", "fused", "resident"],
                    help="tuned: the library's autotuner picks kernel, slab depth and tile")
     p.add_argument("--bin-size", type=int, default=50)
     p.add_argument("--no-extras", action="store_true", help="skip the FP16 and batched comparisons")

@@ -83,7 +83,9 @@ enum {
     LAT_SWEEP_GENERIC = 2, /* 1 site per thread, any even lx                        */
     LAT_SWEEP_ZSLAB = 3,   /* z-marching slabs, plane staged in LDS (lx % 8 == 0)   */
     LAT_SWEEP_FUSED = 4,   /* both half-sweeps in one pass (lx % 8 == 0)             */
-    LAT_SWEEP_RESIDENT = 5 /* small boxes: one workgroup runs every sweep of a call in one launch */
+    LAT_SWEEP_RESIDENT = 5, /* small boxes: one workgroup runs every sweep of a call in one launch */
+    LAT_SWEEP_STREAM = 6    /* z-marching slabs fed by a producer wave through an LDS ring
+                               (lx % 8 == 0, each colour array below 2 GiB)         */
 };
 
 /* ------------------------------------------------------------------ */
@@ -144,11 +146,16 @@ int lattice_sweep_count(const lattice_t *lat, int64_t *sweeps);
  * cannot handle this box. */
 int lattice_set_variant(lattice_t *lat, int variant);
 
-/* Tuning of the slab kernel (LAT_SWEEP_ZSLAB): planes of the box one
- * workgroup walks along z (0 = library default, at most lz); tile
- * configuration 0..7 (workgroup tile width x rows and register budget);
- * whether workgroups are ordered so that each of the chip's 8 XCDs gets a
- * contiguous run of tiles.  Results do not depend on any of them. */
+/* Tuning of the slab kernels (LAT_SWEEP_ZSLAB, LAT_SWEEP_STREAM, and the
+ * planes of LAT_SWEEP_FUSED): planes of the box one workgroup walks along z
+ * (0 = library default, at most lz); tile configuration: 0..7 for
+ * LAT_SWEEP_ZSLAB (workgroup tile width x rows and register budget), 0..9
+ * for LAT_SWEEP_STREAM (tile width 128..512 sites, rows, depth of the LDS
+ * plane ring, non-temporal stores); whether workgroups are ordered so that
+ * each of the chip's 8 XCDs gets a contiguous run of tiles.  LAT_ERR_ARG for
+ * a tile the selected variant does not have (and lattice_set_variant(
+ * LAT_SWEEP_STREAM) with a tile above 9).  Results do not depend on any of
+ * them. */
 int lattice_set_tuning(lattice_t *lat, int64_t planes, int tile, int xcd_order);
 
 /* Graph capture of the multi-launch sweep path: runs of sweeps (with their

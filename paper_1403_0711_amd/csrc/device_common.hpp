@@ -83,6 +83,38 @@ __device__ __forceinline__ float heatbath_noise(uint32_t u) {
     return p * s;
 }
 
+// Heat-bath update of the 4 consecutive same-colour sites j0 .. j0+3 of one
+// row (j0 % 4 == 0): bm/bn are the quads at planes z-1/z+1, up/dn at rows
+// y-1/y+1, bc the other-colour quad at the same columns, e the other-colour
+// value beyond the quad on the side p selects (p = (c + y + z) & 1: the
+// x-neighbours of site k are other-colour columns k-1+p and k+p).  One
+// Philox4x32-10 call with counter (j0/4, h, chain, 0) gives the 4 words.
+__device__ __forceinline__ float4 heatbath_quad(const float4& bm, const float4& bc, const float4& bn,
+                                                const float4& up, const float4& dn, float e, uint32_t p,
+                                                uint32_t j0, uint32_t h, uint32_t chain, uint32_t k0,
+                                                uint32_t k1) {
+    float a0, a1, a2, a3;
+    if (p == 0) {
+        a0 = e + bc.x;
+        a1 = bc.x + bc.y;
+        a2 = bc.y + bc.z;
+        a3 = bc.z + bc.w;
+    } else {
+        a0 = bc.x + bc.y;
+        a1 = bc.y + bc.z;
+        a2 = bc.z + bc.w;
+        a3 = bc.w + e;
+    }
+    const uint4 r = philox4x32_10(j0 >> 2, h, chain, 0u, k0, k1);
+    const float sixth = 1.0f / 6.0f;
+    float4 out;
+    out.x = fmaf(a0 + up.x + dn.x + bm.x + bn.x, sixth, heatbath_noise(r.x));
+    out.y = fmaf(a1 + up.y + dn.y + bm.y + bn.y, sixth, heatbath_noise(r.y));
+    out.z = fmaf(a2 + up.z + dn.z + bm.z + bn.z, sixth, heatbath_noise(r.z));
+    out.w = fmaf(a3 + up.w + dn.w + bm.w + bn.w, sixth, heatbath_noise(r.w));
+    return out;
+}
+
 // ---------------------------------------------------------------------------
 // Raw buffer loads.  A buffer resource carries the array's size; a load at a
 // byte offset >= that size returns 0 and fetches nothing (gfx9-family range
@@ -128,6 +160,10 @@ struct StoreF32 {
     __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return at<float>(p, i); }
     __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) { return at<float4>(p, i); }
     __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) { at<float4>(p, i) = v; }
+    __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(f4{v.x, v.y, v.z, v.w}, &at<f4>(p, i));
+    }
     __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<float>(p, i) = v; }
     __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32x4(r, off); }
     __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32(r, off); }
@@ -155,6 +191,11 @@ struct StoreBF16 {
         w.x = bf16_rne_bits(v.x) | (bf16_rne_bits(v.y) << 16);
         w.y = bf16_rne_bits(v.z) | (bf16_rne_bits(v.w) << 16);
         at<uint2>(p, i) = w;
+    }
+    __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v) {
+        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+        const u2 w = {bf16_rne_bits(v.x) | (bf16_rne_bits(v.y) << 16), bf16_rne_bits(v.z) | (bf16_rne_bits(v.w) << 16)};
+        __builtin_nontemporal_store(w, &at<u2>(p, i));
     }
     __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<uint16_t>(p, i) = (T)bf16_rne_bits(v); }
     __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
@@ -188,6 +229,11 @@ struct StoreF16 {
         w[2] = (_Float16)v.z;
         w[3] = (_Float16)v.w;
         at<h4>(p, i) = w;
+    }
+    __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        const h4 w = {(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
+        __builtin_nontemporal_store(w, &at<h4>(p, i));
     }
     __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<_Float16>(p, i) = (_Float16)v; }
     __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {

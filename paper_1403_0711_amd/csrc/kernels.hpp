@@ -6,7 +6,7 @@
 
 namespace latcoul {
 
-enum : int { kVariantQuad = 1, kVariantGeneric = 2, kVariantZslab = 3, kVariantFused = 4 };
+enum : int { kVariantQuad = 1, kVariantGeneric = 2, kVariantZslab = 3, kVariantFused = 4, kVariantStream = 6 };
 
 // One half-sweep of colour c = h & 1 on one lattice.
 struct SweepArgs {
@@ -16,14 +16,16 @@ struct SweepArgs {
     uint32_t k0, k1;  // Philox key
     uint32_t chain;   // Philox counter word 2
     int storage;      // 0 FP32, 1 BF16, 2 FP16
-    int variant;      // kVariantQuad / kVariantGeneric / kVariantZslab
-    uint32_t zc;      // zslab: planes per workgroup (0 = default)
-    uint32_t xcd_order;  // zslab: XCD-aware block order
-    uint32_t tile;    // zslab: tile configuration, 0 .. kZslabTiles - 1
+    int variant;      // kVariantQuad / kVariantGeneric / kVariantZslab / kVariantStream
+    uint32_t zc;      // slab kernels: planes per workgroup (0 = 16)
+    uint32_t xcd_order;  // slab kernels: XCD-aware block order
+    uint32_t tile;    // slab kernels: tile configuration (kZslabTiles / kStreamTiles of them)
     const uint32_t* tdev;  // if set, h += 2 * tdev[0] (sweep counter on the device)
 };
 constexpr int kZslabTiles = 8;
+constexpr int kStreamTiles = 10;  // tile configurations of the streaming slab kernel
 hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream);
+hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream);  // tile 0 .. kStreamTiles-1
 // device-side sweep / sample counters (ctr[0], ctr[1]) for graph replays
 hipError_t launch_set_counters(uint32_t* ctr, uint32_t t, uint32_t m, hipStream_t stream);
 hipError_t launch_advance_counters(uint32_t* ctr, uint32_t dt, uint32_t dm, hipStream_t stream);

@@ -64,7 +64,7 @@ struct lattice {
     hipStream_t cap = nullptr;  // private capture stream
     int graph_mode = 1;         // 0 never, 1 boxes up to 2^24 sites, 2 always
     int variant = LAT_SWEEP_AUTO;
-    uint32_t slab = 16;      // planes per workgroup for the slab kernels (0 = kernel default)
+    uint32_t slab = 16;      // planes per workgroup for the slab kernels (set per storage at creation)
     uint32_t xcd_order = 1;  // XCD-aware workgroup order for the slab kernels
     uint32_t tile = 0;       // tile configuration of the slab kernel
 
@@ -79,11 +79,17 @@ struct lattice {
         if ((uint64_t)vh * 2 <= kResidentMaxSites) return LAT_SWEEP_RESIDENT;
         if (lh % 4 != 0) return LAT_SWEEP_GENERIC;
         // boxes that spill out of the 256 MB last-level cache: z-marching slabs
-        // (whose colour arrays must stay below 2 GiB)
+        // fed through LDS by a producer wave (colour arrays below 2 GiB)
         const size_t bytes = (size_t)vh * esz;
-        return (2 * bytes > ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) ? LAT_SWEEP_ZSLAB : LAT_SWEEP_QUAD;
+        return (2 * bytes > ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) ? LAT_SWEEP_STREAM : LAT_SWEEP_QUAD;
     }
 };
+
+// Planes per workgroup the slab kernels default to: 16 at FP32, where the
+// sweep is bound by memory traffic and short slabs balance the chip best; 48
+// at 16-bit storage, where arithmetic binds and longer slabs amortise each
+// workgroup's start-up.
+static uint32_t default_slab(size_t esz) { return esz == 4 ? 16u : 48u; }
 
 static int check_lattice(const lattice* L) {
     if (!L) return set_error(LAT_ERR_ARG, "null lattice handle");
@@ -104,7 +110,10 @@ static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev
         e = launch_fused_sweep(a, stream);
         if (e == hipSuccess) L->alt_current = !L->alt_current;
     } else {
-        const int kv = v == LAT_SWEEP_QUAD ? kVariantQuad : v == LAT_SWEEP_ZSLAB ? kVariantZslab : kVariantGeneric;
+        const int kv = v == LAT_SWEEP_QUAD     ? kVariantQuad
+                       : v == LAT_SWEEP_ZSLAB  ? kVariantZslab
+                       : v == LAT_SWEEP_STREAM ? kVariantStream
+                                               : kVariantGeneric;
         SweepArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, 0u, h0,
                     (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, kv, L->slab,
                     L->xcd_order, L->tile, tdev};
@@ -339,13 +348,20 @@ static std::vector<TuneChoice> tune_candidates(const lattice* L) {
         return c;
     }
     const bool slab_ok = (size_t)L->vh * L->esz < ((size_t)1 << 31);
-    if (slab_ok && (size_t)2 * L->vh * L->esz > ((size_t)256 << 20)) c.push_back({LAT_SWEEP_ZSLAB, 16, 0, 1, 0});
+    if (slab_ok && (size_t)2 * L->vh * L->esz > ((size_t)256 << 20))
+        c.push_back({LAT_SWEEP_STREAM, default_slab(L->esz), 0, 1, 0});
     c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
     if (V > kResidentMaxSites && V <= (uint64_t)1 << 18) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
     if (slab_ok)
+        for (uint32_t tile = 0; tile < (uint32_t)kStreamTiles; ++tile)
+            for (uint32_t slab : {16u, 32u, 48u})
+                for (uint32_t xcd : {1u, 0u})
+                    if (slab <= L->lz && (xcd == 1 || tile == 0 || tile == 9))
+                        c.push_back({LAT_SWEEP_STREAM, slab, tile, xcd, 0});
+    if (slab_ok)
         for (uint32_t tile : {0u, 1u, 7u})
             for (uint32_t slab : {8u, 16u, 32u})
-                if (slab <= L->lz && !(tile == 0 && slab == 16)) c.push_back({LAT_SWEEP_ZSLAB, slab, tile, 1, 0});
+                if (slab <= L->lz) c.push_back({LAT_SWEEP_ZSLAB, slab, tile, 1, 0});
     if (fused_sweep_supported(L->lh, (uint32_t)L->ly))
         for (uint32_t slab : {16u, 32u})
             if (slab <= L->lz) c.push_back({LAT_SWEEP_FUSED, slab, 0, 1, 0});
@@ -466,6 +482,7 @@ int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t see
     L->vh = (uint32_t)(lx / 2 * ly * lz);
     L->storage = storage;
     L->esz = storage == LAT_FP32 ? 4 : 2;
+    L->slab = default_slab(L->esz);
     L->seed = seed;
     L->chain = chain_id;
     L->mem = DeviceAllocator(alloc);
@@ -503,6 +520,14 @@ void lattice_destroy(lattice_t* L) {
     delete L;
 }
 
+// Tile configurations the variant's kernel has; for the other variants (the
+// library's choice among them included) a tile every slab kernel has.
+static uint32_t tiles_of(int variant) {
+    if (variant == LAT_SWEEP_ZSLAB) return kZslabTiles;
+    if (variant == LAT_SWEEP_STREAM) return kStreamTiles;
+    return (uint32_t)std::min(kZslabTiles, kStreamTiles);
+}
+
 int lattice_sweep_count(const lattice_t* L, int64_t* sweeps) {
     if (int r = check_lattice(L)) return r;
     if (!sweeps) return set_error(LAT_ERR_ARG, "sweeps is NULL");
@@ -513,16 +538,22 @@ int lattice_sweep_count(const lattice_t* L, int64_t* sweeps) {
 int lattice_set_variant(lattice_t* L, int variant) {
     if (int r = check_lattice(L)) return r;
     switch (variant) {
-        case LAT_SWEEP_AUTO:
+        case LAT_SWEEP_AUTO:  // may pick a slab kernel, which uses the tile
+            if (L->tile >= tiles_of(variant))
+                return set_error(LAT_ERR_ARG, "the selected tile configuration does not exist for every slab kernel");
+            break;
         case LAT_SWEEP_GENERIC:
         case LAT_SWEEP_RESIDENT: break;
         case LAT_SWEEP_QUAD:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
             break;
         case LAT_SWEEP_ZSLAB:
+        case LAT_SWEEP_STREAM:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
             if ((size_t)L->vh * L->esz >= ((size_t)1 << 31))
                 return set_error(LAT_ERR_ARG, "slab kernel needs each colour array below 2 GiB");
+            if (L->tile >= tiles_of(variant))
+                return set_error(LAT_ERR_ARG, "the selected tile configuration does not exist for this kernel");
             break;
         case LAT_SWEEP_FUSED:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "fused sweep needs lx % 8 == 0");
@@ -552,7 +583,8 @@ int lattice_use_graphs(lattice_t* L, int mode) {
 int lattice_set_tuning(lattice_t* L, int64_t planes, int tile, int xcd_order) {
     if (int r = check_lattice(L)) return r;
     if (planes < 0 || planes > L->lz) return set_error(LAT_ERR_ARG, "planes must be in [0, lz]");
-    if (tile < 0 || tile >= kZslabTiles) return set_error(LAT_ERR_ARG, "unknown tile configuration");
+    if (tile < 0 || (uint32_t)tile >= tiles_of(L->variant))
+        return set_error(LAT_ERR_ARG, "unknown tile configuration for the selected sweep kernel");
     L->slab = (uint32_t)planes;
     L->tile = (uint32_t)tile;
     L->xcd_order = xcd_order ? 1u : 0u;

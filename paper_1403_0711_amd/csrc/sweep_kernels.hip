@@ -149,66 +149,55 @@ struct Zslab {
     __device__ __forceinline__ float4 halo(uint32_t z) const { return St::bld4(src, z * plane_b + halob); }
     __device__ __forceinline__ float edge(uint32_t z) const { return St::bld(src, z * plane_b + edgeb); }
 
+    // stage plane z (centre row, halo rows, x-edges) in LDS buffer `buf`
+    __device__ __forceinline__ void stage(int buf, const float4& bc, const float4& hc, float ec) const {
+        *reinterpret_cast<float4*>(&tile[buf][row + 1][4 + 4 * tx]) = bc;
+        if (ty < 2) *reinterpret_cast<float4*>(&tile[buf][ty == 0 ? 0 : kTY + 1][4 + 4 * tx]) = hc;
+        if (tx == 0) tile[buf][row + 1][3] = ec;
+        if (tx == kTX - 1) tile[buf][row + 1][kW - 4] = ec;
+    }
+
+    // update own colour at plane z from planes z-1, z, z+1 (registers) and
+    // the y/x-neighbours of plane z (LDS buffer `buf`)
+    __device__ __forceinline__ void update(uint32_t z, int buf, const float4& bm, const float4& bc,
+                                           const float4& bn) const {
+        if (!active) return;
+        const float4 up = *reinterpret_cast<const float4*>(&tile[buf][row][4 + 4 * tx]);
+        const float4 dn = *reinterpret_cast<const float4*>(&tile[buf][row + 2][4 + 4 * tx]);
+        // uniform per wave (both rows of a wave have the same parity): say so,
+        // so the branch below is a scalar branch
+        const uint32_t p = __builtin_amdgcn_readfirstlane((c + y + z) & 1u);
+        const float e = p == 0 ? tile[buf][row + 1][3 + 4 * tx] : tile[buf][row + 1][8 + 4 * tx];
+        const uint32_t j0 = z * plane + rowj;
+        St::st4(own, j0, heatbath_quad(bm, bc, bn, up, dn, e, p, j0, h, chain, k0, k1));
+    }
+
     // one plane: stage bc (+ halo, edges) in LDS buffer kBuf, prefetch plane
     // z+1 into bn/hn/en, update own colour at plane z
     template <int kBuf>
     __device__ __forceinline__ void step(uint32_t z, const float4& bm, const float4& bc, float4& bn,
                                          const float4& hc, float4& hn, float ec, float& en) const {
-        *reinterpret_cast<float4*>(&tile[kBuf][row + 1][4 + 4 * tx]) = bc;
-        if (ty < 2) *reinterpret_cast<float4*>(&tile[kBuf][ty == 0 ? 0 : kTY + 1][4 + 4 * tx]) = hc;
-        if (tx == 0) tile[kBuf][row + 1][3] = ec;
-        if (tx == kTX - 1) tile[kBuf][row + 1][kW - 4] = ec;
+        stage(kBuf, bc, hc, ec);
         bn = centre(z + 1);
         if (z + 1 < z1) {  // block-uniform
             if (ty < 2) hn = halo(z + 1);  // wave-uniform: the first wave loads the halo rows
             en = edge(z + 1);
         }
         __syncthreads();
-        if (!active) return;
-        const float4 up = *reinterpret_cast<const float4*>(&tile[kBuf][row][4 + 4 * tx]);
-        const float4 dn = *reinterpret_cast<const float4*>(&tile[kBuf][row + 2][4 + 4 * tx]);
-        // uniform per wave (both rows of a wave have the same parity): say so,
-        // so the branch below is a scalar branch
-        const uint32_t p = __builtin_amdgcn_readfirstlane((c + y + z) & 1u);
-        float a0, a1, a2, a3;  // x-neighbours of site k: other columns h0+k-1+p and h0+k+p
-        if (p == 0) {
-            const float e = tile[kBuf][row + 1][3 + 4 * tx];
-            a0 = e + bc.x;
-            a1 = bc.x + bc.y;
-            a2 = bc.y + bc.z;
-            a3 = bc.z + bc.w;
-        } else {
-            const float e = tile[kBuf][row + 1][8 + 4 * tx];
-            a0 = bc.x + bc.y;
-            a1 = bc.y + bc.z;
-            a2 = bc.z + bc.w;
-            a3 = bc.w + e;
-        }
-        const uint32_t j0 = z * plane + rowj;
-        const uint4 r = philox4x32_10(j0 >> 2, h, chain, 0u, k0, k1);
-        const float sixth = 1.0f / 6.0f;
-        float4 out;
-        out.x = fmaf(a0 + up.x + dn.x + bm.x + bn.x, sixth, heatbath_noise(r.x));
-        out.y = fmaf(a1 + up.y + dn.y + bm.y + bn.y, sixth, heatbath_noise(r.y));
-        out.z = fmaf(a2 + up.z + dn.z + bm.z + bn.z, sixth, heatbath_noise(r.z));
-        out.w = fmaf(a3 + up.w + dn.w + bm.w + bn.w, sixth, heatbath_noise(r.w));
-        St::st4(own, j0, out);
+        update(z, kBuf, bm, bc, bn);
     }
 };
 
-// Requires vh * sizeof(storage) < 2^31 (kNoLoad must lie past the array).
-// kWPE: minimum waves per SIMD the register allocation must allow.
-template <class St, int kTX, int kTY, int kWPE>
-__global__ __launch_bounds__(kTX* kTY) __attribute__((amdgpu_waves_per_eu(kWPE, 8))) void halfsweep_zslab(const typename St::T* __restrict__ other,
-                                                           typename St::T* __restrict__ own, uint32_t lh,
-                                                           uint32_t ly, uint32_t lz, uint32_t zc, uint32_t c,
-                                                           uint32_t h, uint32_t k0, uint32_t k1,
-                                                           uint32_t chain, uint32_t xcd_order,
-                                                           const uint32_t* __restrict__ tdev) {
-    if (tdev) h += 2u * tdev[0];
+// Tile set-up shared by the slab kernels: block -> tile (optionally
+// XCD-ordered), per-thread byte offsets of the centre, halo and edge loads.
+// Returns the first plane of the block's slab.
+template <class St, int kTX, int kTY>
+__device__ __forceinline__ uint32_t zslab_setup(Zslab<St, kTX, kTY>& k, const typename St::T* other,
+                                                typename St::T* own, uint32_t lh, uint32_t ly, uint32_t lz,
+                                                uint32_t zc, uint32_t c, uint32_t h, uint32_t k0, uint32_t k1,
+                                                uint32_t chain, uint32_t xcd_order,
+                                                float (*tile)[kTY + 2][Zslab<St, kTX, kTY>::kW]) {
     using K = Zslab<St, kTX, kTY>;
-    __shared__ __align__(16) float tile[2][kTY + 2][K::kW];
-
     const uint32_t nq = lh >> 2;
     const uint32_t nbx = (nq + kTX - 1) / kTX, nby = (ly + kTY - 1) / kTY;
     const uint32_t nb = gridDim.x;
@@ -219,7 +208,6 @@ __global__ __launch_bounds__(kTX* kTY) __attribute__((amdgpu_waves_per_eu(kWPE, 
     }
     const uint32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     constexpr uint32_t E = K::kEsz;
-    K k;
     k.plane = ly * lh;
     k.plane_b = k.plane * E;
     k.src = make_rsrc(other, k.plane_b * lz);
@@ -254,6 +242,23 @@ __global__ __launch_bounds__(kTX* kTY) __attribute__((amdgpu_waves_per_eu(kWPE, 
         k.edgeb = (edge_row + 4u * kTX) * E;
     else
         k.edgeb = kNoLoad;
+    return z0;
+}
+
+// Requires vh * sizeof(storage) < 2^31 (kNoLoad must lie past the array).
+// kWPE: minimum waves per SIMD the register allocation must allow.
+template <class St, int kTX, int kTY, int kWPE>
+__global__ __launch_bounds__(kTX* kTY) __attribute__((amdgpu_waves_per_eu(kWPE, 8))) void halfsweep_zslab(const typename St::T* __restrict__ other,
+                                                           typename St::T* __restrict__ own, uint32_t lh,
+                                                           uint32_t ly, uint32_t lz, uint32_t zc, uint32_t c,
+                                                           uint32_t h, uint32_t k0, uint32_t k1,
+                                                           uint32_t chain, uint32_t xcd_order,
+                                                           const uint32_t* __restrict__ tdev) {
+    if (tdev) h += 2u * tdev[0];
+    using K = Zslab<St, kTX, kTY>;
+    __shared__ __align__(16) float tile[2][kTY + 2][K::kW];
+    K k;
+    const uint32_t z0 = zslab_setup<St, kTX, kTY>(k, other, own, lh, ly, lz, zc, c, h, k0, k1, chain, xcd_order, tile);
 
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     float4 B0 = z0 > 0 ? k.centre(z0 - 1) : zero;
@@ -338,6 +343,7 @@ hipError_t launch_advance_counters(uint32_t* ctr, uint32_t dt, uint32_t dm, hipS
 }
 
 hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream) {
+    if (a.variant == kVariantStream) return launch_halfsweep_stream(a, stream);
     switch (a.storage) {
         case 0: return launch_halfsweep_t<StoreF32>(a, stream);
         case 1: return launch_halfsweep_t<StoreBF16>(a, stream);

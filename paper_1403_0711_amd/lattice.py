@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "liblatcoul.so")
 
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
-VARIANT = {"auto": 0, "quad": 1, "generic": 2, "zslab": 3, "fused": 4, "resident": 5}
+VARIANT = {"auto": 0, "quad": 1, "generic": 2, "zslab": 3, "fused": 4, "resident": 5, "stream": 6}
 ERR_NAMES = {1: "LAT_ERR_ARG", 2: "LAT_ERR_STATE", 3: "LAT_ERR_ALLOC", 4: "LAT_ERR_DEVICE"}
 
 _i64 = ctypes.c_int64

@@ -43,6 +43,11 @@ SHAPES = [
     ((40, 24, 9), "zslab"),     # ragged y tile and z slab
     ((264, 10, 7), "zslab"),    # 33 quads per row: a partial x tile
     ((8, 1, 3), "zslab"),       # one row per plane: a tile with a single active row
+    ((16, 16, 16), "stream"),
+    ((40, 24, 9), "stream"),    # ragged y tile and z slab
+    ((264, 10, 7), "stream"),   # 33 quads per row: a partial x tile
+    ((8, 1, 3), "stream"),      # one row per plane
+    ((520, 12, 5), "stream"),   # 16-row tiles over 12 rows, 65 quads per row
     ((16, 16, 16), "quad"),
     ((24, 16, 8), "quad"),
     ((40, 24, 9), "quad"),      # several tiles + ragged y and z
@@ -71,6 +76,8 @@ def test_field_parity_per_sweep_fp32(lat_mod, shape, variant):
         lat.set_tuning(2 if shape[2] > 2 else 1, tile=(shape[0] + shape[1]) % 8, xcd_order=True)
     if variant == "fused":
         lat.set_tuning(3, 0, xcd_order=True)
+    if variant == "stream":
+        lat.set_tuning(2 if shape[2] > 2 else 1, tile=sum(shape) % 10, xcd_order=True)
     ref = oracle.OracleChain(shape, "fp32", seed=seed, chain=3)
     for s in range(6):
         lat.thermalise(1)
@@ -97,14 +104,18 @@ def test_variants_agree(lat_mod):
     for variant, slab, tile, xcd in (("quad", 0, 0, True), ("resident", 0, 0, True), ("fused", 0, 0, True),
                                      ("fused", 5, 0, False), ("zslab", 0, 0, True), ("zslab", 1, 1, False),
                                      ("zslab", 7, 2, True), ("zslab", 20, 3, False), ("zslab", 5, 4, True),
-                                     ("zslab", 3, 5, True), ("zslab", 9, 6, False), ("zslab", 16, 7, True)):
+                                     ("zslab", 3, 5, True), ("zslab", 9, 6, False), ("zslab", 16, 7, True),
+                                     ("stream", 0, 0, True), ("stream", 1, 1, False), ("stream", 7, 2, True),
+                                     ("stream", 20, 3, False), ("stream", 3, 4, True), ("stream", 2, 5, True),
+                                     ("stream", 9, 6, True), ("stream", 6, 7, True), ("stream", 5, 8, False),
+                                     ("stream", 4, 9, True), ("stream", 11, 4, True)):
         a = lat_mod.Lattice(shape, seed=7)
         a.set_variant(variant)
         a.set_tuning(slab, tile, xcd)
         a.thermalise(20)
         fa = a.get_field()
         assert np.abs(fa - fr).max() <= 1e-6 * np.abs(fr).max(), (variant, slab, tile, xcd)
-        if variant in ("zslab", "fused"):
+        if variant in ("zslab", "fused", "stream"):
             slab_fields.append(fa)
     for f in slab_fields[1:]:
         np.testing.assert_array_equal(f, slab_fields[0])
@@ -183,8 +194,9 @@ def _ulp(v, storage):
     return np.ldexp(1.0, e - p + 1)
 
 
+@pytest.mark.parametrize("variant", ["auto", "zslab", "stream"])
 @pytest.mark.parametrize("storage", ["bf16", "fp16"])
-def test_reduced_precision_parity(lat_mod, storage):
+def test_reduced_precision_parity(lat_mod, storage, variant):
     """16-bit storage, one sweep from a common field, checked half-sweep by
     half-sweep: each colour's new values equal the oracle's heat-bath values
     (FP64, rounded to the storage format) computed from the field the GPU
@@ -192,10 +204,13 @@ def test_reduced_precision_parity(lat_mod, storage):
     lands on the other side of a rounding boundary: there by one storage ulp.
     After 30 more sweeps the field stays within a few ulps of the oracle's
     chain (the map contracts)."""
-    print(f"[gpu] reduced precision {storage}", flush=True)
+    print(f"[gpu] reduced precision {storage} {variant}", flush=True)
     shape = (24, 16, 12)
     lx, ly, lz = shape
     lat = lat_mod.Lattice(shape, storage, seed=5)
+    lat.set_variant(variant)
+    if variant != "auto":
+        lat.set_tuning(5, 0, xcd_order=True)
     ref = oracle.OracleChain(shape, storage, seed=5)
     rng = np.random.default_rng(0)
     start = rng.standard_normal(shape[::-1]).astype(np.float32) * 0.5
@@ -288,6 +303,14 @@ def test_argument_errors(lat_mod):
     lat.set_variant("quad")  # lx = 8: lh = 4, accepted
     with pytest.raises(lat_mod.LatticeError):
         lat_mod.Lattice((6, 6, 6)).set_variant("quad")  # lh = 3: rejected
+    lat.set_variant("stream")
+    with pytest.raises(lat_mod.LatticeError):
+        lat.set_tuning(4, 10, True)  # the streaming kernel has tiles 0 .. 9
+    lat.set_variant("zslab")
+    lat.set_tuning(4, 7, True)
+    lat.set_variant("stream")  # tile 7 exists for both slab kernels
+    lat.set_variant("zslab")
+    lat.set_tuning(0, 0, True)
     # a state with a failed call is unchanged
     assert lat.sweeps == 4
 
@@ -345,7 +368,7 @@ def _sampled_sweep_parity(lat_mod, shape, variant, n_samples=4096, storage="fp32
     return before, after
 
 
-@pytest.mark.parametrize("variant", ["quad", "zslab", "fused"])
+@pytest.mark.parametrize("variant", ["quad", "zslab", "fused", "stream"])
 def test_sampled_parity_large(lat_mod, variant):
     print(f"[gpu] sampled parity 256^3 {variant}", flush=True)
     _sampled_sweep_parity(lat_mod, (256, 256, 256), variant)
@@ -367,7 +390,7 @@ def test_autotune_does_not_advance_the_chain(lat_mod):
     lat.thermalise(3)
     before = lat.get_field()
     choice = lat.autotune(reps=2)
-    assert choice["variant"] in ("quad", "zslab", "fused", "resident")
+    assert choice["variant"] in ("quad", "zslab", "stream", "fused", "resident")
     assert lat.sweeps == 3
     np.testing.assert_array_equal(lat.get_field(), before)
     lat.thermalise(10)
@@ -380,7 +403,7 @@ def test_autotune_does_not_advance_the_chain(lat_mod):
     assert again["variant"] == choice["variant"] and again["planes"] == choice["planes"]
 
 
-@pytest.mark.parametrize("variant", ["quad", "zslab", "fused", "generic"])
+@pytest.mark.parametrize("variant", ["quad", "zslab", "fused", "generic", "stream"])
 def test_graph_replays_match_eager(lat_mod, variant):
     """Chunks of sweeps recorded as a hipGraph and replayed (kernels reading the
     sweep and sample counters on the device) give bit-identical fields, bins
