@@ -10,8 +10,9 @@ Default workload: the largest one-GPU machine, 768^3 sites (FP32 field 1.69 GiB),
 input (the paper's tests use synthetic charge placements only).
 
 Prints one JSON line: whole-job site updates/s, the roofline of the dominant
-kernel (the sweep kernel the autotuner picked) from HIP events around its own
-launches on the library's stream, the time to a 1% statistical error on E_N
+kernel (the library's default sweep kernel for the box, or the autotuner's
+pick with --variant tuned) from HIP events around its own launches on the
+library's stream, the time to a 1% statistical error on E_N
 (extrapolated from the measured binned error and the exact lattice energy
 stored in tests/golden/exact_energies.json), the same sweep with FP16 field
 storage and the 512-chain batched workload for comparison, and the CPU oracle
@@ -49,13 +50,14 @@ def parse():
                    choices=["largest_subdomain_768", "large_neutral_256", "gaussian_blob_384",
                             "small_neutral_16"])
     p.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
-    p.add_argument("--variant", default="tuned",
-                   choices=["tuned", "auto", "quad", "generic", "zslab", "stream", "fused", "resident"],
-                   help="tuned: the library's autotuner picks kernel, slab depth and tile")
+    p.add_argument("--variant", default="auto",
+                   choices=["auto", "tuned", "quad", "generic", "zslab", "stream", "fused", "resident"],
+                   help="auto: the library's default kernel and tuning for the box; "
+                        "tuned: the library's autotuner picks kernel, slab depth and tile")
     p.add_argument("--bin-size", type=int, default=50)
     p.add_argument("--no-extras", action="store_true", help="skip the FP16 and batched comparisons")
     p.add_argument("--planes", type=int, default=None, help="slab kernels: planes per workgroup")
-    p.add_argument("--tile", type=int, default=0, help="zslab: tile configuration 0..7")
+    p.add_argument("--tile", type=int, default=-1, help="slab kernels: tile configuration (-1: library default)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain device copy of the workload's colour-array size (counter calibration)")
     p.add_argument("--kernel-reps", type=int, default=50,
@@ -64,29 +66,42 @@ def parse():
     return p.parse_args()
 
 
-def sources_hash() -> str:
-    """Hash of the HIP sources, to tell whether stored counters are stale."""
+# Sources of each timed kernel: stored counters are valid while these are
+# unchanged.
+_COMMON_SOURCES = ["device_common.hpp", "erfinv_coeffs.h", "kernels.hpp"]
+KERNEL_SOURCES = {
+    "halfsweep_stream": ["stream_sweep.hip"],
+    "halfsweep_zslab": ["sweep_kernels.hip"],
+    "halfsweep_quad": ["sweep_kernels.hip"],
+    "halfsweep_generic": ["sweep_kernels.hip"],
+    "fused_sweep": ["fused_sweep.hip"],
+    "resident_chain": ["batch_kernels.hip"],
+}
+
+
+def sources_hash(kname: str) -> str:
+    """Hash of the HIP sources a kernel is built from, to tell whether stored
+    counters are stale."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1403_0711_amd", "csrc")
-    for n in sorted(os.listdir(csrc)):
-        if n.endswith((".hip", ".hpp", ".h")):
-            with open(os.path.join(csrc, n), "rb") as f:
-                h.update(n.encode())
-                h.update(f.read())
+    for n in KERNEL_SOURCES.get(kname, []) + _COMMON_SOURCES:
+        with open(os.path.join(csrc, n), "rb") as f:
+            h.update(n.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(key: str):
+def stored_traffic(kname: str, key: str):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE and
     WRITE_SIZE, scaled by a copy kernel of known size), if taken on the
-    current sources."""
+    kernel's current sources."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
     e = d.get(key)
-    if not e or e.get("sources_hash") != sources_hash():
+    if not e or e.get("sources_hash") != sources_hash(kname):
         return None
     return e.get("bytes_per_launch")
 
@@ -133,10 +148,12 @@ def kernel_key(kname: str, lat_tuning: dict, workload: str, storage: str) -> str
     return f"{kname}_p{t.get('planes', 0)}_t{t.get('tile', 0)}_{workload}_{storage}"
 
 
-def fp16_comparison(cs, seed, steps, bin_size, torch, lattice):
+def fp16_comparison(cs, seed, steps, bin_size, torch, lattice, tuned: bool):
     """The same workload with FP16 field storage (FP32 arithmetic): per-step time."""
     lat = lattice.Lattice(cs.shape, "fp16", seed=seed)
-    tune = lat.autotune(5)
+    if tuned:
+        lat.autotune(5)
+    tune = lat.tuning()
     lat.set_charges(cs.xyz, cs.q)
     lat.sweep_and_measure(5, 1, bin_size)
     torch.cuda.synchronize()
@@ -180,6 +197,24 @@ def calibrate_copy(spec, torch):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"calibrate_copy_bytes_read": n * 4, "calibrate_copy_bytes_written": n * 4}), flush=True)
+
+
+def copy_reference(n_bytes: int, torch, reps: int = 10):
+    """A device-to-device copy of n_bytes (read n_bytes, write n_bytes), timed
+    with HIP events: the practical ceiling for a kernel that streams one array
+    into another."""
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, b
+    return {"bytes_read": n_bytes, "bytes_written": n_bytes, "ms": ms, "GBps": 2 * n_bytes / (ms * 1e-3) / 1e9}
 
 
 def cpu_baseline(cs, storage: str, seed: int):
@@ -226,15 +261,14 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     lat = lattice.Lattice(cs.shape, args.storage, seed=seed, chain_id=0, device=0, stream=stream)
-    tuning = None
     if args.variant == "tuned":
-        tuning = lat.autotune(5)
-        variant = tuning["variant"]
+        lat.autotune(5)
     else:
         lat.set_variant(args.variant)
-        variant = args.variant
-        if args.planes is not None:
-            lat.set_tuning(args.planes, args.tile, True)
+        if args.planes is not None or args.tile != -1:
+            lat.set_tuning(args.planes or 0, args.tile, True)
+    tuning = lat.tuning()  # what runs: library defaults or the autotuner's choice, resolved
+    variant = tuning["variant"]
     lat.set_charges(cs.xyz, cs.q)
 
     # warmup: W measured sweeps (untimed)
@@ -254,8 +288,7 @@ def main():
         lat, stream, V, esz, variant, args.kernel_reps, torch)
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     measure_ms = max(ms_per_step - sweep_ms, 0.0)
-    used = tuning if tuning is not None else {"planes": args.planes or 0, "tile": args.tile}
-    traffic = stored_traffic(kernel_key(kname, used, args.workload, args.storage))
+    traffic = stored_traffic(kname, kernel_key(kname, tuning, args.workload, args.storage))
 
     m, se, M, nb = lat.energy_estimate(allow_few_bins=True)
     e_exact = exact_energy(args.workload)
@@ -292,8 +325,11 @@ def main():
     torch.cuda.synchronize()
     if not args.no_extras:
         try:
+            out["copy_same_bytes"] = copy_reference(bytes_per_launch // 2, torch)
+            out["copy_same_bytes"]["kernel_vs_copy"] = out["copy_same_bytes"]["ms"] / launch_ms
             if args.storage == "fp32":
-                f16 = fp16_comparison(cs, seed, min(args.steps, 200), args.bin_size, torch, lattice)
+                f16 = fp16_comparison(cs, seed, min(args.steps, 200), args.bin_size, torch, lattice,
+                                      args.variant == "tuned")
                 f16["speedup_vs_fp32"] = ms_per_step / f16["ms_per_step"]
                 out["fp16_storage"] = f16
             out["batched_512"] = batched_comparison(200, torch, lattice, workloads)

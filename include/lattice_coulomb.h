@@ -148,7 +148,9 @@ int lattice_set_variant(lattice_t *lat, int variant);
 
 /* Tuning of the slab kernels (LAT_SWEEP_ZSLAB, LAT_SWEEP_STREAM, and the
  * planes of LAT_SWEEP_FUSED): planes of the box one workgroup walks along z
- * (0 = library default, at most lz); tile configuration: 0..7 for
+ * (0 = library default: 16 at FP32, 48 at 16-bit storage; at most lz); tile
+ * configuration (-1 = library default: for LAT_SWEEP_STREAM at FP32 tile 9
+ * where 96-quad tiles divide the rows, else tile 0): 0..7 for
  * LAT_SWEEP_ZSLAB (workgroup tile width x rows and register budget), 0..9
  * for LAT_SWEEP_STREAM (tile width 128..512 sites, rows, depth of the LDS
  * plane ring, non-temporal stores); whether workgroups are ordered so that
@@ -157,6 +159,12 @@ int lattice_set_variant(lattice_t *lat, int variant);
  * LAT_SWEEP_STREAM) with a tile above 9).  Results do not depend on any of
  * them. */
 int lattice_set_tuning(lattice_t *lat, int64_t planes, int tile, int xcd_order);
+
+/* The configuration the next sweep runs (any output may be NULL): the
+ * variant (LAT_SWEEP_AUTO resolved to the library's choice for the box), the
+ * planes per workgroup, the tile (the library default resolved) and the XCD
+ * order. */
+int lattice_get_tuning(const lattice_t *lat, int *variant, int64_t *planes, int *tile, int *xcd_order);
 
 /* Graph capture of the multi-launch sweep path: runs of sweeps (with their
  * samples) are recorded once as a hipGraph of K-sweep chunks whose kernels

@@ -20,6 +20,8 @@ using namespace latcoul;
 
 // largest box that AUTO runs with the one-workgroup resident kernel
 constexpr uint64_t kResidentMaxSites = 16384;
+constexpr uint32_t kTileDefault = 0xFFFFFFFFu;  // lattice_set_tuning(tile = -1): library default
+constexpr uint32_t kStreamTileFullRow96 = 9;    // streaming kernel: 96-quad tiles, non-temporal stores
 
 struct lattice {
     int64_t lx = 0, ly = 0, lz = 0;
@@ -66,8 +68,17 @@ struct lattice {
     int variant = LAT_SWEEP_AUTO;
     uint32_t slab = 16;      // planes per workgroup for the slab kernels (set per storage at creation)
     uint32_t xcd_order = 1;  // XCD-aware workgroup order for the slab kernels
-    uint32_t tile = 0;       // tile configuration of the slab kernel
+    uint32_t tile = kTileDefault;  // tile configuration of the slab kernels
 
+    // the tile the slab kernel `v` runs: the set one, else the library's
+    // default -- for the streaming kernel at FP32 (bound by memory traffic) a
+    // full-row tile of 96 quads where it divides the row (every plane of a
+    // tile is then one contiguous run of memory), else 32-quad tiles
+    uint32_t resolved_tile(int v) const {
+        if (tile != kTileDefault) return tile;
+        if (v == LAT_SWEEP_STREAM && esz == 4 && (lh / 4) % 96 == 0) return kStreamTileFullRow96;
+        return 0u;
+    }
     double* last_xy() { return reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
     uint32_t* counters() { return static_cast<uint32_t*>(d_misc); }  // [0] sweeps, [1] samples
     void* c1main() const { return static_cast<char*>(field) + (size_t)vh * esz; }
@@ -116,7 +127,7 @@ static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev
                                                : kVariantGeneric;
         SweepArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, 0u, h0,
                     (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, kv, L->slab,
-                    L->xcd_order, L->tile, tdev};
+                    L->xcd_order, L->resolved_tile(v), tdev};
         e = launch_halfsweep(a, stream);
         if (e == hipSuccess) {
             a.c = 1u;
@@ -349,7 +360,7 @@ static std::vector<TuneChoice> tune_candidates(const lattice* L) {
     }
     const bool slab_ok = (size_t)L->vh * L->esz < ((size_t)1 << 31);
     if (slab_ok && (size_t)2 * L->vh * L->esz > ((size_t)256 << 20))
-        c.push_back({LAT_SWEEP_STREAM, default_slab(L->esz), 0, 1, 0});
+        c.push_back({LAT_SWEEP_STREAM, default_slab(L->esz), L->resolved_tile(LAT_SWEEP_STREAM), 1, 0});
     c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
     if (V > kResidentMaxSites && V <= (uint64_t)1 << 18) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
     if (slab_ok)
@@ -539,7 +550,7 @@ int lattice_set_variant(lattice_t* L, int variant) {
     if (int r = check_lattice(L)) return r;
     switch (variant) {
         case LAT_SWEEP_AUTO:  // may pick a slab kernel, which uses the tile
-            if (L->tile >= tiles_of(variant))
+            if (L->tile != kTileDefault && L->tile >= tiles_of(variant))
                 return set_error(LAT_ERR_ARG, "the selected tile configuration does not exist for every slab kernel");
             break;
         case LAT_SWEEP_GENERIC:
@@ -552,7 +563,7 @@ int lattice_set_variant(lattice_t* L, int variant) {
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
             if ((size_t)L->vh * L->esz >= ((size_t)1 << 31))
                 return set_error(LAT_ERR_ARG, "slab kernel needs each colour array below 2 GiB");
-            if (L->tile >= tiles_of(variant))
+            if (L->tile != kTileDefault && L->tile >= tiles_of(variant))
                 return set_error(LAT_ERR_ARG, "the selected tile configuration does not exist for this kernel");
             break;
         case LAT_SWEEP_FUSED:
@@ -572,6 +583,16 @@ int lattice_set_variant(lattice_t* L, int variant) {
     return LAT_OK;
 }
 
+int lattice_get_tuning(const lattice_t* L, int* variant, int64_t* planes, int* tile, int* xcd_order) {
+    if (int r = check_lattice(L)) return r;
+    const int v = L->effective_variant();
+    if (variant) *variant = v;
+    if (planes) *planes = L->slab;
+    if (tile) *tile = (int)L->resolved_tile(v);
+    if (xcd_order) *xcd_order = (int)L->xcd_order;
+    return LAT_OK;
+}
+
 int lattice_use_graphs(lattice_t* L, int mode) {
     if (int r = check_lattice(L)) return r;
     if (mode < 0 || mode > 2) return set_error(LAT_ERR_ARG, "graph mode must be 0, 1 or 2");
@@ -583,10 +604,10 @@ int lattice_use_graphs(lattice_t* L, int mode) {
 int lattice_set_tuning(lattice_t* L, int64_t planes, int tile, int xcd_order) {
     if (int r = check_lattice(L)) return r;
     if (planes < 0 || planes > L->lz) return set_error(LAT_ERR_ARG, "planes must be in [0, lz]");
-    if (tile < 0 || (uint32_t)tile >= tiles_of(L->variant))
+    if (tile < -1 || (tile >= 0 && (uint32_t)tile >= tiles_of(L->variant)))
         return set_error(LAT_ERR_ARG, "unknown tile configuration for the selected sweep kernel");
-    L->slab = (uint32_t)planes;
-    L->tile = (uint32_t)tile;
+    L->slab = planes ? (uint32_t)planes : default_slab(L->esz);
+    L->tile = tile < 0 ? kTileDefault : (uint32_t)tile;
     L->xcd_order = xcd_order ? 1u : 0u;
     graphs_reset(L);
     return LAT_OK;

@@ -69,6 +69,7 @@ def load_library() -> ctypes.CDLL:
         "lattice_set_variant": (_int, [_p, _int]),
         "lattice_set_tuning": (_int, [_p, _i64, _int, _int]),
         "lattice_use_graphs": (_int, [_p, _int]),
+        "lattice_get_tuning": (_int, [_p, ctypes.POINTER(_int), _pi64, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
         "lattice_autotune": (_int, [_p, _i64, ctypes.POINTER(_int), _pi64, ctypes.POINTER(_int),
                                     ctypes.POINTER(_int), _pd]),
         "lattice_get_field": (_int, [_p, _p]),
@@ -225,13 +226,23 @@ class Lattice:
     def set_variant(self, name: str):
         self._call(self.lib.lattice_set_variant, VARIANT[name])
 
-    def set_tuning(self, planes: int = 16, tile: int = 0, xcd_order: bool = True):
-        """Slab-kernel tuning: planes per workgroup, tile configuration, XCD order."""
+    def set_tuning(self, planes: int = 0, tile: int = -1, xcd_order: bool = True):
+        """Slab-kernel tuning: planes per workgroup, tile configuration, XCD
+        order (0 / -1: library defaults)."""
         self._call(self.lib.lattice_set_tuning, int(planes), int(tile), 1 if xcd_order else 0)
 
     def use_graphs(self, mode: int = 1):
         """0: launch by launch; 1: hipGraph chunks for boxes up to 2^24 sites; 2: always."""
         self._call(self.lib.lattice_use_graphs, int(mode))
+
+    def tuning(self) -> dict:
+        """The configuration the next sweep runs (library choices resolved)."""
+        v, t, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        pl = ctypes.c_int64()
+        self._call(self.lib.lattice_get_tuning, ctypes.byref(v), ctypes.byref(pl), ctypes.byref(t), ctypes.byref(x))
+        names = {val: key for key, val in VARIANT.items()}
+        return {"variant": names.get(v.value, v.value), "planes": pl.value, "tile": t.value,
+                "xcd_order": bool(x.value)}
 
     def autotune(self, reps: int = 5) -> dict:
         """Time the sweep kernels on scratch memory and keep the fastest."""

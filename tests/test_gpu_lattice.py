@@ -381,6 +381,31 @@ def test_sampled_parity_largest_box(lat_mod):
     _sampled_sweep_parity(lat_mod, (768, 768, 768), "auto", n_samples=2048)
 
 
+def test_default_tuning_resolution(lat_mod):
+    """Library defaults: large boxes run the streaming slab kernel, at FP32
+    with 96-quad tiles where they divide the rows and 32-quad tiles elsewhere;
+    16 planes per workgroup at FP32, 48 at 16-bit storage; explicit settings
+    win."""
+    print("[gpu] default tuning", flush=True)
+    lat = lat_mod.Lattice((768, 768, 128), "fp32")
+    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 9, "xcd_order": True}
+    lat.set_tuning(32, 3, False)
+    assert lat.tuning() == {"variant": "stream", "planes": 32, "tile": 3, "xcd_order": False}
+    lat.set_tuning(0, -1, True)
+    assert lat.tuning()["tile"] == 9 and lat.tuning()["planes"] == 16
+    lat.close()
+    lat = lat_mod.Lattice((640, 640, 192), "fp32")  # 2 x 157 MB: past the 256 MiB cache
+    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 0, "xcd_order": True}
+    lat.close()
+    lat = lat_mod.Lattice((768, 768, 256), "fp16")
+    assert lat.tuning() == {"variant": "stream", "planes": 48, "tile": 0, "xcd_order": True}
+    lat.set_variant("zslab")
+    assert lat.tuning()["tile"] == 0
+    lat.close()
+    assert lat_mod.Lattice((64, 64, 64)).tuning()["variant"] == "quad"
+    assert lat_mod.Lattice((16, 16, 16)).tuning()["variant"] == "resident"
+
+
 def test_autotune_does_not_advance_the_chain(lat_mod):
     """The autotuner times kernels on scratch memory: the chain's field and
     sweep counter are untouched, and the chosen kernel gives the same chain."""
