@@ -16,7 +16,9 @@ library's stream, the time to a 1% statistical error on E_N
 (extrapolated from the measured binned error and the exact lattice energy
 stored in tests/golden/exact_energies.json), the same sweep with FP16 field
 storage and the 512-chain batched workload for comparison, and the CPU oracle
-timed on a bounded sample of the same workload.
+timed on a bounded sample of the same workload; with extras, also a coupled
+FP32 / BF16 / FP16 comparison on the 384^3 Gaussian blob (bias of the 16-bit
+chains and their cost per sweep).
 """
 
 from __future__ import annotations
@@ -199,6 +201,42 @@ def calibrate_copy(spec, torch):
     print(json.dumps({"calibrate_copy_bytes_read": n * 4, "calibrate_copy_bytes_written": n * 4}), flush=True)
 
 
+def precision_coupled(sweeps, torch, lattice, workloads):
+    """Reduced-precision storage at equal accuracy, on the 384^3 Gaussian blob
+    (2e5 charges of +1): FP32, BF16 and FP16 chains on one Philox stream (same
+    seed and chain id, no thermalisation), one sample per sweep.  The chains
+    move together, so the per-sweep difference of a 16-bit chain's sample from
+    the FP32 chain's measures its bias with an error far below the chains' own
+    statistical error; with equal statistics, time to a given error scales as
+    the cost per sweep."""
+    name = "gaussian_blob_384"
+    spec = workloads.WORKLOADS[name]
+    cs = spec["make"]()
+    out, series = {"workload": name, "sweeps": sweeps, "E_exact": exact_energy(name)}, {}
+    for st in ("fp32", "bf16", "fp16"):
+        lat = lattice.Lattice(cs.shape, st, seed=spec["philox_seed"])
+        lat.set_charges(cs.xyz, cs.q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.sweep_and_measure(sweeps, 1, 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, n, bins = lat.get_state()
+        series[st] = bins[:, 0] - bins[:, 1]  # one sample per bin
+        out[st] = {"ms_per_sweep": 1e3 * dt / sweeps, "mean_O": float(series[st].mean())}
+        lat.close()
+    out["sd_O"] = float(series["fp32"].std())
+    nblk = 10
+    for st in ("bf16", "fp16"):
+        d = series[st] - series["fp32"]
+        blocks = d[: len(d) // nblk * nblk].reshape(nblk, -1).mean(axis=1)
+        out[st].update({"bias_vs_fp32": float(d.mean()),
+                        "bias_stderr": float(blocks.std(ddof=1) / math.sqrt(nblk)),
+                        "sd_of_difference": float(d.std()),
+                        "cost_vs_fp32": out[st]["ms_per_sweep"] / out["fp32"]["ms_per_sweep"]})
+    return out
+
+
 def copy_reference(n_bytes: int, torch, reps: int = 10):
     """A device-to-device copy of n_bytes (read n_bytes, write n_bytes), timed
     with HIP events: the practical ceiling for a kernel that streams one array
@@ -333,6 +371,7 @@ def main():
                 f16["speedup_vs_fp32"] = ms_per_step / f16["ms_per_step"]
                 out["fp16_storage"] = f16
             out["batched_512"] = batched_comparison(200, torch, lattice, workloads)
+            out["precision_coupled"] = precision_coupled(10000, torch, lattice, workloads)
         except Exception as exc:  # comparisons must not hide the headline line
             out["extras_error"] = repr(exc)
     if not args.no_cpu_baseline:

@@ -148,9 +148,11 @@ int lattice_set_variant(lattice_t *lat, int variant);
 
 /* Tuning of the slab kernels (LAT_SWEEP_ZSLAB, LAT_SWEEP_STREAM, and the
  * planes of LAT_SWEEP_FUSED): planes of the box one workgroup walks along z
- * (0 = library default: 16 at FP32, 48 at 16-bit storage; at most lz); tile
- * configuration (-1 = library default: for LAT_SWEEP_STREAM at FP32 tile 9
- * where 96-quad tiles divide the rows, else tile 0): 0..7 for
+ * (0 = library default: 16 at FP32, 32 at 16-bit storage; at most lz); tile
+ * configuration (-1 = library default: for LAT_SWEEP_STREAM 96-quad tiles
+ * at FP32 where they divide the rows, else 32-quad tiles, with non-temporal
+ * stores where a colour array is at least 256 MiB: tiles 9 / 6 / 0 / 3;
+ * tile 0 for the other kernels): 0..7 for
  * LAT_SWEEP_ZSLAB (workgroup tile width x rows and register budget), 0..9
  * for LAT_SWEEP_STREAM (tile width 128..512 sites, rows, depth of the LDS
  * plane ring, non-temporal stores); whether workgroups are ordered so that

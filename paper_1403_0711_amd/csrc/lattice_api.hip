@@ -21,7 +21,9 @@ using namespace latcoul;
 // largest box that AUTO runs with the one-workgroup resident kernel
 constexpr uint64_t kResidentMaxSites = 16384;
 constexpr uint32_t kTileDefault = 0xFFFFFFFFu;  // lattice_set_tuning(tile = -1): library default
-constexpr uint32_t kStreamTileFullRow96 = 9;    // streaming kernel: 96-quad tiles, non-temporal stores
+constexpr uint32_t kStreamTileFullRow96 = 9;        // streaming kernel: 96-quad tiles, non-temporal stores
+constexpr uint32_t kStreamTileFullRow96Cached = 6;  // 96-quad tiles, ordinary stores
+constexpr uint32_t kStreamTileCached = 3;           // 32 quads x 8 rows, 6-slot ring, ordinary stores
 
 struct lattice {
     int64_t lx = 0, ly = 0, lz = 0;
@@ -71,13 +73,18 @@ struct lattice {
     uint32_t tile = kTileDefault;  // tile configuration of the slab kernels
 
     // the tile the slab kernel `v` runs: the set one, else the library's
-    // default -- for the streaming kernel at FP32 (bound by memory traffic) a
+    // default.  Streaming kernel: at FP32 (bound by memory traffic) a
     // full-row tile of 96 quads where it divides the row (every plane of a
-    // tile is then one contiguous run of memory), else 32-quad tiles
+    // tile is then one contiguous run of memory), else 32 quads x 8 rows with
+    // a 6-slot ring; non-temporal stores only where one colour array alone
+    // fills the 256 MiB last-level cache (smaller ones keep part of the
+    // written colour there for the next half-sweep).
     uint32_t resolved_tile(int v) const {
         if (tile != kTileDefault) return tile;
-        if (v == LAT_SWEEP_STREAM && esz == 4 && (lh / 4) % 96 == 0) return kStreamTileFullRow96;
-        return 0u;
+        if (v != LAT_SWEEP_STREAM) return 0u;
+        const bool wide = esz == 4 && (lh / 4) % 96 == 0;
+        const bool nt = (size_t)vh * esz >= ((size_t)256 << 20);
+        return wide ? (nt ? kStreamTileFullRow96 : kStreamTileFullRow96Cached) : (nt ? 0u : kStreamTileCached);
     }
     double* last_xy() { return reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
     uint32_t* counters() { return static_cast<uint32_t*>(d_misc); }  // [0] sweeps, [1] samples
@@ -92,15 +99,15 @@ struct lattice {
         // boxes that spill out of the 256 MB last-level cache: z-marching slabs
         // fed through LDS by a producer wave (colour arrays below 2 GiB)
         const size_t bytes = (size_t)vh * esz;
-        return (2 * bytes > ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) ? LAT_SWEEP_STREAM : LAT_SWEEP_QUAD;
+        return (2 * bytes >= ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) ? LAT_SWEEP_STREAM : LAT_SWEEP_QUAD;
     }
 };
 
 // Planes per workgroup the slab kernels default to: 16 at FP32, where the
-// sweep is bound by memory traffic and short slabs balance the chip best; 48
+// sweep is bound by memory traffic and short slabs balance the chip best; 32
 // at 16-bit storage, where arithmetic binds and longer slabs amortise each
 // workgroup's start-up.
-static uint32_t default_slab(size_t esz) { return esz == 4 ? 16u : 48u; }
+static uint32_t default_slab(size_t esz) { return esz == 4 ? 16u : 32u; }
 
 static int check_lattice(const lattice* L) {
     if (!L) return set_error(LAT_ERR_ARG, "null lattice handle");
@@ -359,7 +366,7 @@ static std::vector<TuneChoice> tune_candidates(const lattice* L) {
         return c;
     }
     const bool slab_ok = (size_t)L->vh * L->esz < ((size_t)1 << 31);
-    if (slab_ok && (size_t)2 * L->vh * L->esz > ((size_t)256 << 20))
+    if (slab_ok && (size_t)2 * L->vh * L->esz >= ((size_t)256 << 20))
         c.push_back({LAT_SWEEP_STREAM, default_slab(L->esz), L->resolved_tile(LAT_SWEEP_STREAM), 1, 0});
     c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
     if (V > kResidentMaxSites && V <= (uint64_t)1 << 18) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});

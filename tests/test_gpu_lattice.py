@@ -382,26 +382,37 @@ def test_sampled_parity_largest_box(lat_mod):
 
 
 def test_default_tuning_resolution(lat_mod):
-    """Library defaults: large boxes run the streaming slab kernel, at FP32
-    with 96-quad tiles where they divide the rows and 32-quad tiles elsewhere;
-    16 planes per workgroup at FP32, 48 at 16-bit storage; explicit settings
-    win."""
+    """Library defaults: boxes whose field does not fit the 256 MiB last-level
+    cache run the streaming slab kernel, at FP32 with 96-quad tiles where they
+    divide the rows, else 32-quad tiles, and non-temporal stores only where a
+    colour array is at least 256 MiB; 16 planes per workgroup at FP32, 32 at
+    16-bit storage; explicit settings win."""
     print("[gpu] default tuning", flush=True)
-    lat = lat_mod.Lattice((768, 768, 128), "fp32")
-    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 9, "xcd_order": True}
+    lat = lat_mod.Lattice((768, 768, 128), "fp32")  # 2 x 151 MB
+    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 6, "xcd_order": True}
     lat.set_tuning(32, 3, False)
     assert lat.tuning() == {"variant": "stream", "planes": 32, "tile": 3, "xcd_order": False}
     lat.set_tuning(0, -1, True)
-    assert lat.tuning()["tile"] == 9 and lat.tuning()["planes"] == 16
+    assert lat.tuning()["tile"] == 6 and lat.tuning()["planes"] == 16
     lat.close()
-    lat = lat_mod.Lattice((640, 640, 192), "fp32")  # 2 x 157 MB: past the 256 MiB cache
-    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 0, "xcd_order": True}
+    lat = lat_mod.Lattice((768, 768, 384), "fp32")  # 2 x 453 MB
+    assert lat.tuning()["tile"] == 9
     lat.close()
-    lat = lat_mod.Lattice((768, 768, 256), "fp16")
-    assert lat.tuning() == {"variant": "stream", "planes": 48, "tile": 0, "xcd_order": True}
+    lat = lat_mod.Lattice((768, 768, 768), "fp16")  # 2 x 453 MB, 16-bit: 32-quad tiles
+    assert lat.tuning() == {"variant": "stream", "planes": 32, "tile": 0, "xcd_order": True}
+    lat.close()
+    lat = lat_mod.Lattice((768, 768, 512), "fp32")  # 2 x 604 MB
+    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 9, "xcd_order": True}
+    lat.close()
+    lat = lat_mod.Lattice((640, 640, 192), "fp32")  # 2 x 157 MB, 80 quads per row
+    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 3, "xcd_order": True}
+    lat.close()
+    lat = lat_mod.Lattice((512, 512, 512), "fp16")  # 2 x 128 MiB: exactly the cache
+    assert lat.tuning() == {"variant": "stream", "planes": 32, "tile": 3, "xcd_order": True}
     lat.set_variant("zslab")
     assert lat.tuning()["tile"] == 0
     lat.close()
+    assert lat_mod.Lattice((384, 384, 384)).tuning()["variant"] == "quad"  # 2 x 113 MB
     assert lat_mod.Lattice((64, 64, 64)).tuning()["variant"] == "quad"
     assert lat_mod.Lattice((16, 16, 16)).tuning()["variant"] == "resident"
 
