@@ -112,6 +112,20 @@ int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t see
  * do not depend on the charges, as the paper notes). */
 int set_charges(lattice_t *lat, int64_t n, const int32_t *xyz, const double *q);
 
+/* Several charge sets measured on one field chain: every measured sweep
+ * takes one sample per set, each into its own bins.  The paper notes that a
+ * stored set of field samples can serve any charge configuration; here the
+ * sets share the sweeps as they are made, so the sweep cost is paid once for
+ * all of them.  n_sets in [1, 65535]; counts = n_sets int64 (charges per
+ * set); xyz (3 int32 per charge) and q (one double per charge) hold the sets
+ * one after the other.  Each set is aggregated per site as in set_charges.
+ * Resets the bins of every set; the field and sweep counter are kept.
+ * set_charges is the case n_sets = 1.  Errors as set_charges; LAT_ERR_ARG
+ * also for n_sets out of range, a negative count, or n_sets > 1 with the
+ * variant LAT_SWEEP_RESIDENT (which measures one set). */
+int lattice_set_charge_sets(lattice_t *lat, int64_t n_sets, const int64_t *counts,
+                            const int32_t *xyz, const double *q);
+
 /* Enqueue n_sweeps sweeps without measurement (thermalisation). n_sweeps >= 0. */
 int thermalise(lattice_t *lat, int64_t n_sweeps);
 
@@ -131,6 +145,11 @@ int sweep_and_measure(lattice_t *lat, int64_t n_sweeps, int64_t measure_every,
  * non-finite sample is found. */
 int energy_estimate(lattice_t *lat, double *mean, double *stderr_binned, int64_t *n_samples,
                     int64_t *n_bins);
+
+/* The estimate of charge set `set` (as energy_estimate; energy_estimate is
+ * set 0).  LAT_ERR_ARG for a set that does not exist. */
+int lattice_energy_estimate_set(lattice_t *lat, int64_t set, double *mean, double *stderr_binned,
+                                int64_t *n_samples, int64_t *n_bins);
 
 /* Release all device memory of the handle (NULL is ignored). */
 void lattice_destroy(lattice_t *lat);
@@ -195,17 +214,20 @@ int lattice_get_field(lattice_t *lat, float *host_out);
  * format.  Errors: LAT_ERR_ARG for non-finite values. */
 int lattice_set_field(lattice_t *lat, const float *host_in);
 
-/* The (X, Y) of the most recent sample. */
+/* The (X, Y) of the most recent sample (charge set 0). */
 int lattice_last_measure(lattice_t *lat, double *X, double *Y);
 
-/* Checkpoint: sweep counter, number of samples and the bins
- * (2 doubles per bin: compensated sum, compensation; at most cap bins
- * copied to bins_host, which may be NULL); *n_bins = bins in use. */
+/* Checkpoint: sweep counter, number of samples and the bins (2 doubles per
+ * bin: compensated sum, compensation); *n_bins = bins in use per charge set.
+ * bins_host (may be NULL) receives the n_bins bins of set 0, then those of
+ * set 1, ...: at most cap bins in all. */
 int lattice_get_state(lattice_t *lat, int64_t *sweep_counter, int64_t *n_samples,
                       double *bins_host, int64_t cap, int64_t *n_bins);
 
 /* Restore a checkpoint taken by lattice_get_state (field restored separately
- * with lattice_set_field).  bin_size as used when it was taken. */
+ * with lattice_set_field; the charge sets placed first): bins_host holds
+ * n_bins bins per charge set, set after set.  bin_size as used when it was
+ * taken. */
 int lattice_set_state(lattice_t *lat, int64_t sweep_counter, int64_t n_samples, int64_t bin_size,
                       const double *bins_host, int64_t n_bins);
 

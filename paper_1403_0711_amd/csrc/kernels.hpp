@@ -48,7 +48,9 @@ hipError_t prepare_fused_sweep();  // once, before fused launches and outside ca
 
 // Gather of the charge-weighted correlator after a sweep (Eq. nsum2):
 // X = sum_s Q_s phi_s, Y = sum_s S_s phi_s^2 over the site-aggregated charge
-// list, O = X^2 - Y compensated-added into bins[2*bin], bins[2*bin+1].
+// list, O = X^2 - Y compensated-added into bins[2*bin], bins[2*bin+1]; for
+// several charge sets, per set (entries set_off[k] .. set_off[k+1]-1, bins at
+// bins + 2 * k * bin_stride, X and Y at last_xy[2k], last_xy[2k+1]).
 struct MeasureArgs {
     const void* field0;    // colour 0
     const void* field1;    // colour 1
@@ -57,14 +59,17 @@ struct MeasureArgs {
     const double* Q;       // sum of q on the site
     const double* S;       // sum of q^2 on the site
     uint32_t n;            // number of charged sites
-    double* partials;      // 2 * blocks scratch
+    double* partials;      // 2 * blocks * n_sets scratch
     double* bins;
     uint32_t m;            // sample index (relative to *mdev when mdev is set)
     uint32_t bin_size;
     const uint32_t* mdev;  // sample counter on the device, or null
-    double* last_xy;       // X, Y of this sample
+    double* last_xy;       // X, Y of this sample, per set
     int storage;
-    uint32_t blocks;       // grid size (fixed for a given n: fixes the sum order)
+    uint32_t blocks;       // blocks per set (fixed for given sets: fixes the sum order)
+    const uint32_t* set_off;  // n_sets + 1 offsets into the list (null: one set of n entries)
+    uint32_t n_sets;
+    uint32_t bin_stride;   // bins per set in `bins`
 };
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream);
 uint32_t measure_blocks(uint32_t n);

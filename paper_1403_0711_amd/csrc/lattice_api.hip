@@ -20,6 +20,7 @@ using namespace latcoul;
 
 // largest box that AUTO runs with the one-workgroup resident kernel
 constexpr uint64_t kResidentMaxSites = 16384;
+constexpr int64_t kMaxChargeSets = 65535;  // charge sets per lattice (a grid dimension of the gather)
 constexpr uint32_t kTileDefault = 0xFFFFFFFFu;  // lattice_set_tuning(tile = -1): library default
 constexpr uint32_t kStreamTileFullRow96 = 9;        // streaming kernel: 96-quad tiles, non-temporal stores
 constexpr uint32_t kStreamTileFullRow96Cached = 6;  // 96-quad tiles, ordinary stores
@@ -47,6 +48,11 @@ struct lattice {
     double* d_S = nullptr;
     double* d_partials = nullptr;
     uint32_t meas_blocks = 1;
+    // charge sets sharing the chain: set k is list entries set_off[k] ..
+    // set_off[k+1]-1; bins of set k at d_bins + 2 * k * bin_cap
+    uint32_t n_sets = 1;
+    uint32_t* d_set_off = nullptr;
+    double* d_lastxy = nullptr;  // X, Y of the last sample, per set
     // misc block: last X, Y (doubles at 64)
     void* d_misc = nullptr;
     // samples
@@ -86,7 +92,7 @@ struct lattice {
         const bool nt = (size_t)vh * esz >= ((size_t)256 << 20);
         return wide ? (nt ? kStreamTileFullRow96 : kStreamTileFullRow96Cached) : (nt ? 0u : kStreamTileCached);
     }
-    double* last_xy() { return reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
+    double* last_xy() { return d_lastxy ? d_lastxy : reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
     uint32_t* counters() { return static_cast<uint32_t*>(d_misc); }  // [0] sweeps, [1] samples
     void* c1main() const { return static_cast<char*>(field) + (size_t)vh * esz; }
     void* c1cur() const { return alt_current ? c1alt : c1main(); }
@@ -94,7 +100,7 @@ struct lattice {
         if (variant != LAT_SWEEP_AUTO) return variant;
         // a box one workgroup sweeps in a few microseconds: launch overhead
         // would dominate, so run the whole call in one launch
-        if ((uint64_t)vh * 2 <= kResidentMaxSites) return LAT_SWEEP_RESIDENT;
+        if ((uint64_t)vh * 2 <= kResidentMaxSites && n_sets == 1) return LAT_SWEEP_RESIDENT;
         if (lh % 4 != 0) return LAT_SWEEP_GENERIC;
         // boxes that spill out of the 256 MB last-level cache: z-marching slabs
         // fed through LDS by a producer wave (colour arrays below 2 GiB)
@@ -195,7 +201,7 @@ static int enqueue_resident(lattice* L, int64_t n_therm, int64_t n_meas, int64_t
 static int enqueue_measure_ex(lattice* L, hipStream_t stream, const uint32_t* mdev, uint32_t rel) {
     MeasureArgs a{L->field, L->c1cur(), L->vh, L->d_site, L->d_Q, L->d_S, L->n_sites, L->d_partials,
                   L->d_bins, mdev ? rel : (uint32_t)L->n_meas, (uint32_t)L->bin_size, mdev, L->last_xy(),
-                  L->storage, L->meas_blocks};
+                  L->storage, L->meas_blocks, L->d_set_off, L->n_sets, (uint32_t)L->bin_cap};
     hipError_t e = launch_measure(a, stream);
     if (e != hipSuccess) return hip_fail(e, "measure launch");
     if (!mdev) L->n_meas += 1;
@@ -322,15 +328,20 @@ static int run_sweeps(lattice* L, int64_t n, int64_t every) {
     return settle_colour1(L);
 }
 
+// Bin arrays of every charge set, each with room for n_bins_needed bins
+// (grown geometrically; each set's bins keep their place in its array).
 static int ensure_bins(lattice* L, int64_t n_bins_needed) {
     if (n_bins_needed <= L->bin_cap) return LAT_OK;
     int64_t cap = std::max<int64_t>({n_bins_needed, 2 * L->bin_cap, 64});
-    double* nb = static_cast<double*>(L->mem.alloc(sizeof(double) * 2 * (size_t)cap));
+    const size_t pitch = sizeof(double) * 2 * (size_t)cap;
+    double* nb = static_cast<double*>(L->mem.alloc(pitch * L->n_sets));
     if (!nb) return set_error(LAT_ERR_ALLOC, "allocation of sample bins failed");
-    hipError_t e = hipMemsetAsync(nb, 0, sizeof(double) * 2 * (size_t)cap, L->stream);
-    if (e == hipSuccess && L->d_bins && L->bin_cap > 0)
-        e = hipMemcpyAsync(nb, L->d_bins, sizeof(double) * 2 * (size_t)L->bin_cap, hipMemcpyDeviceToDevice,
-                           L->stream);
+    hipError_t e = hipMemsetAsync(nb, 0, pitch * L->n_sets, L->stream);
+    if (e == hipSuccess && L->d_bins && L->bin_cap > 0) {
+        const size_t old_pitch = sizeof(double) * 2 * (size_t)L->bin_cap;
+        e = hipMemcpy2DAsync(nb, pitch, L->d_bins, old_pitch, old_pitch, L->n_sets, hipMemcpyDeviceToDevice,
+                             L->stream);
+    }
     if (e != hipSuccess) {
         L->mem.release(nb);
         return hip_fail(e, "bin resize");
@@ -359,9 +370,11 @@ static std::map<std::tuple<int64_t, int64_t, int64_t, int>, TuneChoice> g_tune_c
 static std::vector<TuneChoice> tune_candidates(const lattice* L) {
     std::vector<TuneChoice> c;
     const uint64_t V = (uint64_t)L->vh * 2;
-    if (V <= kResidentMaxSites) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
+    const bool resident_ok = L->n_sets == 1;  // the resident kernel measures one charge set
+    if (V <= kResidentMaxSites && resident_ok) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
     if (L->lh % 4 != 0) {
-        if (V > kResidentMaxSites && V <= (uint64_t)1 << 18) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
+        if (V > kResidentMaxSites && V <= (uint64_t)1 << 18 && resident_ok)
+            c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
         c.push_back({LAT_SWEEP_GENERIC, 0, 0, 1, 0});
         return c;
     }
@@ -369,7 +382,8 @@ static std::vector<TuneChoice> tune_candidates(const lattice* L) {
     if (slab_ok && (size_t)2 * L->vh * L->esz >= ((size_t)256 << 20))
         c.push_back({LAT_SWEEP_STREAM, default_slab(L->esz), L->resolved_tile(LAT_SWEEP_STREAM), 1, 0});
     c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
-    if (V > kResidentMaxSites && V <= (uint64_t)1 << 18) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
+    if (V > kResidentMaxSites && V <= (uint64_t)1 << 18 && resident_ok)
+        c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
     if (slab_ok)
         for (uint32_t tile = 0; tile < (uint32_t)kStreamTiles; ++tile)
             for (uint32_t slab : {16u, 32u, 48u})
@@ -534,6 +548,8 @@ void lattice_destroy(lattice_t* L) {
     L->mem.release(L->d_Q);
     L->mem.release(L->d_S);
     L->mem.release(L->d_partials);
+    L->mem.release(L->d_set_off);
+    L->mem.release(L->d_lastxy);
     L->mem.release(L->d_bins);
     delete L;
 }
@@ -560,8 +576,10 @@ int lattice_set_variant(lattice_t* L, int variant) {
             if (L->tile != kTileDefault && L->tile >= tiles_of(variant))
                 return set_error(LAT_ERR_ARG, "the selected tile configuration does not exist for every slab kernel");
             break;
-        case LAT_SWEEP_GENERIC:
-        case LAT_SWEEP_RESIDENT: break;
+        case LAT_SWEEP_GENERIC: break;
+        case LAT_SWEEP_RESIDENT:
+            if (L->n_sets > 1) return set_error(LAT_ERR_ARG, "the resident kernel measures one charge set");
+            break;
         case LAT_SWEEP_QUAD:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
             break;
@@ -620,64 +638,109 @@ int lattice_set_tuning(lattice_t* L, int64_t planes, int tile, int xcd_order) {
     return LAT_OK;
 }
 
-int set_charges(lattice_t* L, int64_t n, const int32_t* xyz, const double* q) {
+int lattice_set_charge_sets(lattice_t* L, int64_t n_sets, const int64_t* counts, const int32_t* xyz,
+                            const double* q) {
     if (int r = check_lattice(L)) return r;
-    if (n < 0) return set_error(LAT_ERR_ARG, "negative charge count");
+    if (n_sets < 1 || n_sets > kMaxChargeSets) return set_error(LAT_ERR_ARG, "n_sets must be in [1, 65535]");
+    if (!counts) return set_error(LAT_ERR_ARG, "counts is NULL");
+    if (n_sets > 1 && L->variant == LAT_SWEEP_RESIDENT)
+        return set_error(LAT_ERR_ARG, "the resident kernel measures one charge set");
+    int64_t n = 0;
+    for (int64_t k = 0; k < n_sets; ++k) {
+        if (counts[k] < 0) return set_error(LAT_ERR_ARG, "negative charge count");
+        n += counts[k];
+    }
     if (n > 0 && (!xyz || !q)) return set_error(LAT_ERR_ARG, "xyz or q is NULL");
-    AggregatedCharges agg;
-    if (int r = aggregate_charges(n, xyz, q, L->lx, L->ly, L->lz, L->vh, &agg)) return r;
-    const uint32_t ns = (uint32_t)agg.site.size();
-    const uint32_t blocks = measure_blocks(ns);
-    uint32_t* d_site = nullptr;
-    double *d_Q = nullptr, *d_S = nullptr, *d_part = nullptr;
+    // aggregate each set, concatenate
+    AggregatedCharges all;
+    std::vector<uint32_t> off(1, 0u);
+    uint32_t max_ns = 0;
+    int64_t first = 0;
+    for (int64_t k = 0; k < n_sets; ++k) {
+        AggregatedCharges agg;
+        if (int r = aggregate_charges(counts[k], xyz ? xyz + 3 * first : nullptr, q ? q + first : nullptr, L->lx,
+                                      L->ly, L->lz, L->vh, &agg))
+            return r;
+        first += counts[k];
+        if (all.site.size() + agg.site.size() >= (size_t)0xFFFFFFFFu)
+            return set_error(LAT_ERR_ARG, "too many charged sites");
+        all.site.insert(all.site.end(), agg.site.begin(), agg.site.end());
+        all.Q.insert(all.Q.end(), agg.Q.begin(), agg.Q.end());
+        all.S.insert(all.S.end(), agg.S.begin(), agg.S.end());
+        off.push_back((uint32_t)all.site.size());
+        max_ns = std::max(max_ns, (uint32_t)agg.site.size());
+    }
+    const uint32_t ns = (uint32_t)all.site.size();
+    const uint32_t blocks = measure_blocks(max_ns);
     const size_t cap = std::max<size_t>(ns, 1);
-    d_site = static_cast<uint32_t*>(L->mem.alloc(cap * 4));
-    d_Q = static_cast<double*>(L->mem.alloc(cap * 8));
-    d_S = static_cast<double*>(L->mem.alloc(cap * 8));
-    d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * 16));
-    if (!d_site || !d_Q || !d_S || !d_part) {
+    uint32_t* d_site = static_cast<uint32_t*>(L->mem.alloc(cap * 4));
+    double* d_Q = static_cast<double*>(L->mem.alloc(cap * 8));
+    double* d_S = static_cast<double*>(L->mem.alloc(cap * 8));
+    double* d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * n_sets * 16));
+    uint32_t* d_off = static_cast<uint32_t*>(L->mem.alloc(off.size() * 4));
+    double* d_xy = static_cast<double*>(L->mem.alloc((size_t)n_sets * 16));
+    auto release_new = [&] {
         L->mem.release(d_site);
         L->mem.release(d_Q);
         L->mem.release(d_S);
         L->mem.release(d_part);
+        L->mem.release(d_off);
+        L->mem.release(d_xy);
+    };
+    if (!d_site || !d_Q || !d_S || !d_part || !d_off || !d_xy) {
+        release_new();
         return set_error(LAT_ERR_ALLOC, "allocation of the charge list failed");
     }
     hipError_t e = hipSuccess;
     if (ns > 0) {
-        e = hipMemcpyAsync(d_site, agg.site.data(), (size_t)ns * 4, hipMemcpyHostToDevice, L->stream);
+        e = hipMemcpyAsync(d_site, all.site.data(), (size_t)ns * 4, hipMemcpyHostToDevice, L->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(d_Q, agg.Q.data(), (size_t)ns * 8, hipMemcpyHostToDevice, L->stream);
+            e = hipMemcpyAsync(d_Q, all.Q.data(), (size_t)ns * 8, hipMemcpyHostToDevice, L->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(d_S, agg.S.data(), (size_t)ns * 8, hipMemcpyHostToDevice, L->stream);
+            e = hipMemcpyAsync(d_S, all.S.data(), (size_t)ns * 8, hipMemcpyHostToDevice, L->stream);
     }
+    if (e == hipSuccess) e = hipMemcpyAsync(d_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d_xy, 0, (size_t)n_sets * 16, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) {
-        L->mem.release(d_site);
-        L->mem.release(d_Q);
-        L->mem.release(d_S);
-        L->mem.release(d_part);
+        release_new();
         return hip_fail(e, "charge upload");
     }
     L->mem.release(L->d_site);
     L->mem.release(L->d_Q);
     L->mem.release(L->d_S);
     L->mem.release(L->d_partials);
+    L->mem.release(L->d_set_off);
+    L->mem.release(L->d_lastxy);
     graphs_reset(L);
     L->d_site = d_site;
     L->d_Q = d_Q;
     L->d_S = d_S;
     L->d_partials = d_part;
+    L->d_set_off = d_off;
+    L->d_lastxy = d_xy;
     L->n_sites = ns;
     L->n_raw = n;
     L->meas_blocks = blocks;
-    // new observable: start a new sample series
+    // new observables: start new sample series (bin arrays sized per set)
     L->n_meas = 0;
     L->bin_size = 0;
-    if (L->d_bins) {
-        e = hipMemsetAsync(L->d_bins, 0, sizeof(double) * 2 * (size_t)L->bin_cap, L->stream);
+    if (L->n_sets != (uint32_t)n_sets) {
+        L->mem.release(L->d_bins);
+        L->d_bins = nullptr;
+        L->bin_cap = 0;
+        L->n_sets = (uint32_t)n_sets;
+    } else if (L->d_bins) {
+        e = hipMemsetAsync(L->d_bins, 0, sizeof(double) * 2 * (size_t)L->bin_cap * L->n_sets, L->stream);
         if (e != hipSuccess) return hip_fail(e, "bin reset");
     }
     return LAT_OK;
+}
+
+int set_charges(lattice_t* L, int64_t n, const int32_t* xyz, const double* q) {
+    if (int r = check_lattice(L)) return r;
+    if (n < 0) return set_error(LAT_ERR_ARG, "negative charge count");
+    return lattice_set_charge_sets(L, 1, &n, xyz, q);
 }
 
 int thermalise(lattice_t* L, int64_t n_sweeps) {
@@ -710,15 +773,18 @@ int sweep_and_measure(lattice_t* L, int64_t n_sweeps, int64_t measure_every, int
     return run_sweeps(L, n_sweeps, measure_every);
 }
 
-int energy_estimate(lattice_t* L, double* mean, double* stderr_binned, int64_t* n_samples, int64_t* n_bins) {
+int lattice_energy_estimate_set(lattice_t* L, int64_t set, double* mean, double* stderr_binned,
+                                int64_t* n_samples, int64_t* n_bins) {
     if (int r = check_lattice(L)) return r;
+    if (set < 0 || set >= (int64_t)L->n_sets) return set_error(LAT_ERR_ARG, "no such charge set");
     const int64_t M = L->n_meas;
     const int64_t B = L->bin_size > 0 ? L->bin_size : 1;
-    const int64_t used = (M + B - 1) / B;
+    const int64_t used = std::min<int64_t>((M + B - 1) / B, L->bin_cap);
     std::vector<double> h((size_t)std::max<int64_t>(used, 1) * 2, 0.0);
     hipError_t e = hipStreamSynchronize(L->stream);
     if (e == hipSuccess && used > 0)
-        e = hipMemcpy(h.data(), L->d_bins, sizeof(double) * 2 * (size_t)used, hipMemcpyDeviceToHost);
+        e = hipMemcpy(h.data(), L->d_bins + 2 * (size_t)set * L->bin_cap, sizeof(double) * 2 * (size_t)used,
+                      hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "bin readback");
     EstimateResult res = estimate_from_bins(h.data(), used, M, B);
     if (mean) *mean = res.mean;
@@ -728,6 +794,10 @@ int energy_estimate(lattice_t* L, double* mean, double* stderr_binned, int64_t* 
     if (!res.finite) return set_error(LAT_ERR_STATE, "non-finite sample found (field or charges not finite)");
     if (res.full_bins < 2) return set_error(LAT_ERR_STATE, "fewer than 2 full bins: no error estimate");
     return LAT_OK;
+}
+
+int energy_estimate(lattice_t* L, double* mean, double* stderr_binned, int64_t* n_samples, int64_t* n_bins) {
+    return lattice_energy_estimate_set(L, 0, mean, stderr_binned, n_samples, n_bins);
 }
 
 int lattice_get_field(lattice_t* L, float* host_out) {
@@ -775,9 +845,13 @@ int lattice_get_state(lattice_t* L, int64_t* sweep_counter, int64_t* n_samples, 
     if (n_samples) *n_samples = L->n_meas;
     if (n_bins) *n_bins = used;
     hipError_t e = hipStreamSynchronize(L->stream);
-    const int64_t k = std::min(cap, used);
-    if (e == hipSuccess && bins_host && k > 0)
-        e = hipMemcpy(bins_host, L->d_bins, sizeof(double) * 2 * (size_t)k, hipMemcpyDeviceToHost);
+    // set-major: the `used` bins of set 0, then of set 1, ...; at most cap pairs
+    for (int64_t k = 0; k < (int64_t)L->n_sets && e == hipSuccess && bins_host; ++k) {
+        const int64_t room = std::min(used, cap - k * used);
+        if (room <= 0) break;
+        e = hipMemcpy(bins_host + 2 * k * used, L->d_bins + 2 * (size_t)k * L->bin_cap,
+                      sizeof(double) * 2 * (size_t)room, hipMemcpyDeviceToHost);
+    }
     if (e != hipSuccess) return hip_fail(e, "state readback");
     return LAT_OK;
 }
@@ -793,10 +867,12 @@ int lattice_set_state(lattice_t* L, int64_t sweep_counter, int64_t n_samples, in
     if (!L->d_partials)
         if (int r = set_charges(L, 0, nullptr, nullptr)) return r;
     if (int r = ensure_bins(L, std::max<int64_t>(used, 1))) return r;
-    hipError_t e = hipMemsetAsync(L->d_bins, 0, sizeof(double) * 2 * (size_t)L->bin_cap, L->stream);
+    hipError_t e = hipMemsetAsync(L->d_bins, 0, sizeof(double) * 2 * (size_t)L->bin_cap * L->n_sets, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-    if (e == hipSuccess && used > 0)
-        e = hipMemcpy(L->d_bins, bins_host, sizeof(double) * 2 * (size_t)used, hipMemcpyHostToDevice);
+    // set-major, as lattice_get_state writes them
+    for (int64_t k = 0; k < (int64_t)L->n_sets && e == hipSuccess && used > 0; ++k)
+        e = hipMemcpy(L->d_bins + 2 * (size_t)k * L->bin_cap, bins_host + 2 * k * used,
+                      sizeof(double) * 2 * (size_t)used, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "state upload");
     L->t = sweep_counter;
     L->n_meas = n_samples;

@@ -10,6 +10,12 @@
 // (Kahan) FP64 sum; this replaces the paper's global reduce.  The kernel
 // boundary orders the two phases, so no device-scope fence or atomic is
 // needed (a device-scope release on this multi-XCD chip writes back L2).
+//
+// Several charge sets can share one field chain (the paper's reuse of one set
+// of samples for many charge configurations): their lists are concatenated,
+// set k holding entries set_off[k] .. set_off[k+1]-1; grid row k gathers set
+// k, and block k of the second launch forms set k's sample and bins it in its
+// own bin array (stride bin_stride bins).
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -40,10 +46,14 @@ __global__ __launch_bounds__(kMeasureThreads) void gather_partials(const typenam
                                                                    const uint32_t* __restrict__ site,
                                                                    const double* __restrict__ Q,
                                                                    const double* __restrict__ S, uint32_t n,
+                                                                   const uint32_t* __restrict__ set_off,
                                                                    double* __restrict__ partials) {
     double x = 0.0, y = 0.0;
+    const uint32_t set = blockIdx.y;
+    const uint32_t lo = set_off ? set_off[set] : 0u;
+    n = set_off ? set_off[set + 1] : n;  // one past the set's last entry
     const uint32_t stride = gridDim.x * kMeasureThreads;
-    uint32_t i = blockIdx.x * kMeasureThreads + threadIdx.x;
+    uint32_t i = lo + blockIdx.x * kMeasureThreads + threadIdx.x;
     // kGatherUnroll independent loads in flight per thread
     for (; i + (kGatherUnroll - 1) * stride < n; i += kGatherUnroll * stride) {
         float v[kGatherUnroll];
@@ -63,19 +73,23 @@ __global__ __launch_bounds__(kMeasureThreads) void gather_partials(const typenam
     }
     block_sum2<kMeasureThreads>(x, y);
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = x;
-        partials[2 * blockIdx.x + 1] = y;
+        const uint32_t b = set * gridDim.x + blockIdx.x;
+        partials[2 * b] = x;
+        partials[2 * b + 1] = y;
     }
 }
 
 // Sample m (counted from the device counter mdev when given: graph replays)
-// goes to bin (m [+ *mdev]) / bin_size.
+// goes to bin (m [+ *mdev]) / bin_size of the block's charge set.
 __global__ __launch_bounds__(kMeasureThreads) void finalize_measure(const double* __restrict__ partials,
                                                                     uint32_t blocks, double* bins, uint32_t m,
                                                                     uint32_t bin_size,
                                                                     const uint32_t* __restrict__ mdev,
-                                                                    double* last_xy) {
+                                                                    double* last_xy, uint32_t bin_stride) {
     const uint32_t bin = (m + (mdev ? mdev[0] : 0u)) / bin_size;
+    const uint32_t set = blockIdx.x;
+    partials += 2 * (size_t)set * blocks;
+    bins += 2 * (size_t)set * bin_stride;
     double X = 0.0, Y = 0.0;
     for (uint32_t b = threadIdx.x; b < blocks; b += kMeasureThreads) {
         X += partials[2 * b];
@@ -93,18 +107,19 @@ __global__ __launch_bounds__(kMeasureThreads) void finalize_measure(const double
         sum = tk;
         bins[2 * bin] = sum;
         bins[2 * bin + 1] = comp;
-        last_xy[0] = X;
-        last_xy[1] = Y;
+        last_xy[2 * set] = X;
+        last_xy[2 * set + 1] = Y;
     }
 }
 
 template <class St>
 static hipError_t launch_measure_t(const MeasureArgs& a, hipStream_t stream) {
-    hipLaunchKernelGGL(gather_partials<St>, dim3(a.blocks), dim3(kMeasureThreads), 0, stream,
+    if (a.n_sets < 1 || (a.n_sets > 1 && !a.set_off)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gather_partials<St>, dim3(a.blocks, a.n_sets), dim3(kMeasureThreads), 0, stream,
                        static_cast<const typename St::T*>(a.field0), static_cast<const typename St::T*>(a.field1),
-                       a.vh, a.site, a.Q, a.S, a.n, a.partials);
-    hipLaunchKernelGGL(finalize_measure, dim3(1), dim3(kMeasureThreads), 0, stream, a.partials, a.blocks,
-                       a.bins, a.m, a.bin_size, a.mdev, a.last_xy);
+                       a.vh, a.site, a.Q, a.S, a.n, a.set_off, a.partials);
+    hipLaunchKernelGGL(finalize_measure, dim3(a.n_sets), dim3(kMeasureThreads), 0, stream, a.partials, a.blocks,
+                       a.bins, a.m, a.bin_size, a.mdev, a.last_xy, a.bin_stride);
     return hipGetLastError();
 }
 

@@ -63,6 +63,8 @@ def load_library() -> ctypes.CDLL:
         "thermalise": (_int, [_p, _i64]),
         "sweep_and_measure": (_int, [_p, _i64, _i64, _i64]),
         "energy_estimate": (_int, [_p, _pd, _pd, _pi64, _pi64]),
+        "lattice_set_charge_sets": (_int, [_p, _i64, _p, _p, _p]),
+        "lattice_energy_estimate_set": (_int, [_p, _i64, _pd, _pd, _pi64, _pi64]),
         "lattice_destroy": (None, [_p]),
         "lattice_last_error": (ctypes.c_char_p, []),
         "lattice_sweep_count": (_int, [_p, _pi64]),
@@ -161,6 +163,7 @@ class Lattice:
                                            alloc_ptr, ctypes.c_void_p(self.stream.cuda_stream),
                                            ctypes.byref(h)))
         self.h = h
+        self.n_sets = 1  # charge sets measured per sweep
 
     # -- lifetime --------------------------------------------------------
     def close(self):
@@ -196,22 +199,39 @@ class Lattice:
         if xyz.shape[0] != q.shape[0]:
             raise ValueError("xyz and q differ in length")
         self._call(self.lib.set_charges, q.shape[0], _ptr(xyz), _ptr(q))
+        self.n_sets = 1
 
+    def set_charge_sets(self, sets):
+        """Several charge sets ``[(xyz, q), ...]`` measured on one field
+        chain: every measured sweep takes one sample per set."""
+        xs, qs = [], []
+        for xyz, q in sets:
+            xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+            q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+            if xyz.shape[0] != q.shape[0]:
+                raise ValueError("xyz and q differ in length")
+            xs.append(xyz)
+            qs.append(q)
+        counts = np.array([q.shape[0] for q in qs], dtype=np.int64)
+        xyz = np.ascontiguousarray(np.concatenate(xs) if xs else np.zeros((0, 3), np.int32), dtype=np.int32)
+        q = np.ascontiguousarray(np.concatenate(qs) if qs else np.zeros(0), dtype=np.float64)
+        self._call(self.lib.lattice_set_charge_sets, len(counts), _ptr(counts), _ptr(xyz), _ptr(q))
+        self.n_sets = len(counts)
     def thermalise(self, n_sweeps: int):
         self._call(self.lib.thermalise, int(n_sweeps))
 
     def sweep_and_measure(self, n_sweeps: int, measure_every: int = 1, bin_size: int = 100):
         self._call(self.lib.sweep_and_measure, int(n_sweeps), int(measure_every), int(bin_size))
 
-    def energy_estimate(self, allow_few_bins: bool = False):
-        """Returns ``(mean, stderr, n_samples, n_bins)``."""
+    def energy_estimate(self, allow_few_bins: bool = False, charge_set: int = 0):
+        """Returns ``(mean, stderr, n_samples, n_bins)`` of one charge set."""
         import torch
 
         m, s = ctypes.c_double(), ctypes.c_double()
         n, nb = ctypes.c_int64(), ctypes.c_int64()
         with torch.cuda.device(self.device):
-            rc = self.lib.energy_estimate(self.h, ctypes.byref(m), ctypes.byref(s), ctypes.byref(n),
-                                          ctypes.byref(nb))
+            rc = self.lib.lattice_energy_estimate_set(self.h, int(charge_set), ctypes.byref(m), ctypes.byref(s),
+                                                      ctypes.byref(n), ctypes.byref(nb))
         if rc != 0 and not (allow_few_bins and rc == 2 and nb.value < 2):
             _check(rc)
         return m.value, s.value, n.value, nb.value
@@ -271,18 +291,22 @@ class Lattice:
         return X.value, Y.value
 
     def get_state(self):
-        """Returns ``(sweep_counter, n_samples, bins)`` with bins (n, 2)."""
+        """Returns ``(sweep_counter, n_samples, bins)``: bins (n, 2) for one
+        charge set, (n_sets, n, 2) for several."""
         t, n, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         self._call(self.lib.lattice_get_state, ctypes.byref(t), ctypes.byref(n), None, 0, ctypes.byref(nb))
-        bins = np.zeros((max(nb.value, 1), 2), dtype=np.float64)
-        self._call(self.lib.lattice_get_state, ctypes.byref(t), ctypes.byref(n), _ptr(bins), nb.value,
+        k = self.n_sets
+        bins = np.zeros((k, max(nb.value, 1), 2), dtype=np.float64)
+        self._call(self.lib.lattice_get_state, ctypes.byref(t), ctypes.byref(n), _ptr(bins), k * nb.value,
                    ctypes.byref(nb))
-        return t.value, n.value, bins[:nb.value]
+        bins = np.ascontiguousarray(bins[:, :nb.value])
+        return t.value, n.value, (bins[0] if k == 1 else bins)
 
     def set_state(self, sweep_counter: int, n_samples: int, bin_size: int, bins):
-        b = np.ascontiguousarray(bins, dtype=np.float64).reshape(-1, 2)
+        """Restore a checkpoint of ``get_state`` (charge sets placed first)."""
+        b = np.ascontiguousarray(bins, dtype=np.float64).reshape(self.n_sets, -1, 2)
         self._call(self.lib.lattice_set_state, int(sweep_counter), int(n_samples), int(bin_size),
-                   _ptr(b), b.shape[0])
+                   _ptr(b), b.shape[1])
 
 
 class Batch:

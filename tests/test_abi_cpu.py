@@ -57,4 +57,6 @@ def test_null_handles_are_rejected(lib):
     assert lib.thermalise(None, 1) == 1
     assert lib.sweep_and_measure(None, 1, 1, 1) == 1
     assert lib.energy_estimate(None, None, None, None, None) == 1
+    assert lib.lattice_set_charge_sets(None, 1, None, None, None) == 1
+    assert lib.lattice_energy_estimate_set(None, 0, None, None, None, None) == 1
     lib.lattice_destroy(None)
