@@ -18,7 +18,7 @@ stored in tests/golden/exact_energies.json), the same sweep with FP16 field
 storage and the 512-chain batched workload for comparison, and the CPU oracle
 timed on a bounded sample of the same workload; with extras, also a coupled
 FP32 / BF16 / FP16 comparison on the 384^3 Gaussian blob (bias of the 16-bit
-chains and their cost per sweep).
+chains and their cost per sweep), and four charge sets sampled on one chain.
 """
 
 from __future__ import annotations
@@ -68,9 +68,9 @@ def parse():
     return p.parse_args()
 
 
-# Sources of each timed kernel: stored counters are valid while these are
-# unchanged.
-_COMMON_SOURCES = ["device_common.hpp", "erfinv_coeffs.h", "kernels.hpp"]
+# Device sources of each timed kernel: stored counters are valid while these
+# are unchanged (host-side launch structs are not part of a kernel's code).
+_COMMON_SOURCES = ["device_common.hpp", "erfinv_coeffs.h"]
 KERNEL_SOURCES = {
     "halfsweep_stream": ["stream_sweep.hip"],
     "halfsweep_zslab": ["sweep_kernels.hip"],
@@ -237,6 +237,24 @@ def precision_coupled(sweeps, torch, lattice, workloads):
     return out
 
 
+def charge_sets_comparison(cs, spec, workloads, steps, bin_size, torch, lattice, n_sets=4):
+    """Several charge sets on one field chain: the workload's set plus
+    n_sets - 1 more drawn with other seeds, every set sampled every sweep.
+    Sample rate per set against the one-set run: the sweeps are shared."""
+    sets = [cs] + [spec["make"](seed=s) for s in range(1, n_sets)]
+    lat = lattice.Lattice(cs.shape, "fp32", seed=spec["philox_seed"])
+    lat.set_charge_sets([(c.xyz, c.q) for c in sets])
+    lat.sweep_and_measure(5, 1, bin_size)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.sweep_and_measure(steps, 1, bin_size)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lat.close()
+    return {"sets": n_sets, "charges_per_set": [int(c.n) for c in sets], "ms_per_step": 1e3 * dt / steps,
+            "set_samples_per_s": n_sets * steps / dt}
+
+
 def copy_reference(n_bytes: int, torch, reps: int = 10):
     """A device-to-device copy of n_bytes (read n_bytes, write n_bytes), timed
     with HIP events: the practical ceiling for a kernel that streams one array
@@ -372,6 +390,11 @@ def main():
                 out["fp16_storage"] = f16
             out["batched_512"] = batched_comparison(200, torch, lattice, workloads)
             out["precision_coupled"] = precision_coupled(10000, torch, lattice, workloads)
+            if args.storage == "fp32":
+                sets = charge_sets_comparison(cs, spec, workloads, min(args.steps, 200), args.bin_size, torch,
+                                              lattice)
+                sets["set_samples_vs_one_set"] = sets["set_samples_per_s"] / (1e3 / ms_per_step)
+                out["charge_sets"] = sets
         except Exception as exc:  # comparisons must not hide the headline line
             out["extras_error"] = repr(exc)
     if not args.no_cpu_baseline:
