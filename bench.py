@@ -18,7 +18,8 @@ stored in tests/golden/exact_energies.json), the same sweep with FP16 field
 storage and the 512-chain batched workload for comparison, and the CPU oracle
 timed on a bounded sample of the same workload; with extras, also a coupled
 FP32 / BF16 / FP16 comparison on the 384^3 Gaussian blob (bias of the 16-bit
-chains and their cost per sweep), and four charge sets sampled on one chain.
+chains and their cost per sweep), four charge sets sampled on one chain, and
+the paper's two accuracy figures (132 charge sets on one 128^3 chain).
 """
 
 from __future__ import annotations
@@ -255,6 +256,33 @@ def charge_sets_comparison(cs, spec, workloads, steps, bin_size, torch, lattice,
             "set_samples_per_s": n_sets * steps / dt}
 
 
+def figures_comparison(sweeps: int = 200000):
+    """The paper's accuracy figures on the 128^3 box, all 132 charge sets
+    (two-body scan, solid cubes N = 8 .. 32768) sampled on one chain: for the
+    cubes, delta = |estimate - E| / |E| against the exact lattice energy and
+    against the continuum energy of Eq. (s1) (the paper's reference, which
+    the open box misses for large cubes) at each checkpoint M; for the pairs,
+    the largest |estimate - E_lat| / stderr."""
+    from paper_1403_0711_amd import figures
+
+    with open(EXACT_FILE) as f:
+        ex = json.load(f)
+    res = figures.run(L=128, therm=5000, sweeps=sweeps, bin_size=2000)
+    n_pair = len(ex["fig1_pair_scan_128"]["E_lat"])
+    e_lat = np.array(ex["fig1_pair_scan_128"]["E_lat"] + ex["fig2_cubes_128"]["E_lat"])
+    e_s1 = np.array(ex["fig1_pair_scan_128"]["E_continuum"] + ex["fig2_cubes_128"]["E_continuum"])
+    out = {"sweeps": sweeps, "sets": len(res["sets"]), "ms_per_sweep": res["ms_per_sweep"],
+           "cube_N": ex["fig2_cubes_128"]["N"], "checkpoints": []}
+    for row in res["checkpoints"]:
+        mean, se = np.array(row["mean"]), np.array(row["stderr"])
+        out["checkpoints"].append({
+            "M": row["M"],
+            "cube_delta_lattice": [float(v) for v in np.abs(mean[n_pair:] - e_lat[n_pair:]) / np.abs(e_lat[n_pair:])],
+            "cube_delta_eq_s1": [float(v) for v in np.abs(mean[n_pair:] - e_s1[n_pair:]) / np.abs(e_s1[n_pair:])],
+            "pair_max_abs_z": float(np.max(np.abs(mean[:n_pair] - e_lat[:n_pair]) / se[:n_pair]))})
+    return out
+
+
 def copy_reference(n_bytes: int, torch, reps: int = 10):
     """A device-to-device copy of n_bytes (read n_bytes, write n_bytes), timed
     with HIP events: the practical ceiling for a kernel that streams one array
@@ -390,6 +418,7 @@ def main():
                 out["fp16_storage"] = f16
             out["batched_512"] = batched_comparison(200, torch, lattice, workloads)
             out["precision_coupled"] = precision_coupled(10000, torch, lattice, workloads)
+            out["figures_128"] = figures_comparison()
             if args.storage == "fp32":
                 sets = charge_sets_comparison(cs, spec, workloads, min(args.steps, 200), args.bin_size, torch,
                                               lattice)
