@@ -27,7 +27,7 @@ import os
 import numpy as np
 
 __all__ = ["OracleChain", "load", "philox4x32_10", "inv_norm_cdf", "round_storage",
-           "site_uniform", "estimate", "STORAGE"]
+           "site_uniform", "estimate", "gather_offlattice", "force_sample", "STORAGE"]
 
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
 
@@ -66,6 +66,8 @@ def load() -> ctypes.CDLL:
     lib.orc_halfsweep.restype = None
     lib.orc_gather.argtypes = [_p, _i64, _i64, _i64, _i64, _p, _p, _p]
     lib.orc_gather.restype = None
+    lib.orc_gather_offlattice.argtypes = [_p, _i64, _i64, _i64, _i64, _p, _p, _p, _p, _p]
+    lib.orc_gather_offlattice.restype = None
     lib.orc_run.argtypes = [_p, _i64, _i64, _i64, ctypes.c_int, _u64, _u32, _i64, _i64, _i64,
                             _i64, _p, _p, _p]
     lib.orc_run.restype = _i64
@@ -163,6 +165,33 @@ class OracleChain:
         self.lib.orc_gather(_ptr(self.phi), lx, ly, lz, self.q.shape[0], _ptr(self.xyz),
                             _ptr(self.q), _ptr(out))
         return float(out[0]), float(out[1])
+
+
+def gather_offlattice(phi: np.ndarray, r, q):
+    """Off-lattice charges on a field ``phi[z, y, x]`` (FP64): trilinear
+    interpolation from the 8 corners of each charge's cell.  Returns
+    ``(X, Y, phit, grad)``: X = sum q phi~, Y = sum (q phi~)^2, phi~ at each
+    charge and its gradient (n x 3)."""
+    lz, ly, lx = phi.shape
+    f = np.ascontiguousarray(phi, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    out = np.zeros(2)
+    phit = np.zeros(q.shape[0])
+    grad = np.zeros((q.shape[0], 3))
+    load().orc_gather_offlattice(_ptr(f), lx, ly, lz, q.shape[0], _ptr(r), _ptr(q), _ptr(out), _ptr(phit),
+                                 _ptr(grad))
+    return float(out[0]), float(out[1]), phit, grad
+
+
+def force_sample(X: float, phit: np.ndarray, grad: np.ndarray, q) -> np.ndarray:
+    """One sample of dE/dr_i for off-lattice charges (n x 3): E is the mean of
+    O = X^2 - Y with X = sum q_j phi~_j and Y = sum (q_j phi~_j)^2, so
+    dO/dr_i = 2 q_i grad phi~_i (X - q_i phi~_i).  E sums ordered pairs (the
+    paper's Eq. s1), twice the physical pair energy: the physical force on
+    charge i is -(1/2) dE/dr_i."""
+    q = np.asarray(q, dtype=np.float64).reshape(-1)
+    return 2.0 * (q * (X - q * phit))[:, None] * grad
 
 
 def site_values_f32(phi32: np.ndarray, sites: np.ndarray, seed: int, chain: int, h: int) -> np.ndarray:

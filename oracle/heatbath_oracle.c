@@ -196,6 +196,57 @@ void orc_gather(const double *phi, int64_t lx, int64_t ly, int64_t lz, int64_t n
 }
 
 /*
+ * Off-lattice charges (the paper's closing remark: an arbitrary position can
+ * be modelled by its nearest eight lattice sites, and forces evaluated by
+ * interpolation in the same way).  Site (x, y, z) sits at position (x, y, z)
+ * (lattice units).  A charge at r with 0 <= r_d <= L_d - 1 (L_d >= 2) lies in
+ * the cell with origin b_d = min(floor(r_d), L_d - 2) and fraction
+ * f_d = r_d - b_d in [0, 1]; corner b + e (e in {0, 1}^3) carries the
+ * trilinear weight w = prod_d (e_d ? f_d : 1 - f_d).  The field at the charge
+ * is the interpolant phi~(r) = sum over corners of w phi(corner); its
+ * gradient in r within the cell is, for x, sum over corners of
+ * (e_x ? 1 : -1) * (y and z weight factors) * phi(corner), and likewise for y
+ * and z.  Samples: X = sum_i q_i phi~(r_i), Y = sum_i (q_i phi~(r_i))^2.
+ * phit (n values) and grad (3n values) receive phi~ and its gradient when
+ * not NULL.
+ */
+void orc_gather_offlattice(const double *phi, int64_t lx, int64_t ly, int64_t lz, int64_t n,
+                           const double *r, const double *q, double out[2], double *phit, double *grad) {
+    const int64_t L[3] = {lx, ly, lz};
+    double X = 0.0, Y = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t b[3];
+        double f[3];
+        for (int d = 0; d < 3; ++d) {
+            double fl = floor(r[3 * i + d]);
+            if (fl > (double)(L[d] - 2)) fl = (double)(L[d] - 2);
+            b[d] = (int64_t)fl;
+            f[d] = r[3 * i + d] - fl;
+        }
+        double v = 0.0, g[3] = {0.0, 0.0, 0.0};
+        for (int ez = 0; ez < 2; ++ez)
+            for (int ey = 0; ey < 2; ++ey)
+                for (int ex = 0; ex < 2; ++ex) {
+                    const double wx = ex ? f[0] : 1.0 - f[0];
+                    const double wy = ey ? f[1] : 1.0 - f[1];
+                    const double wz = ez ? f[2] : 1.0 - f[2];
+                    const double p = phi[(b[0] + ex) + lx * ((b[1] + ey) + ly * (b[2] + ez))];
+                    v += wx * wy * wz * p;
+                    g[0] += (ex ? 1.0 : -1.0) * wy * wz * p;
+                    g[1] += wx * (ey ? 1.0 : -1.0) * wz * p;
+                    g[2] += wx * wy * (ez ? 1.0 : -1.0) * p;
+                }
+        X += q[i] * v;
+        Y += (q[i] * v) * (q[i] * v);
+        if (phit) phit[i] = v;
+        if (grad)
+            for (int d = 0; d < 3; ++d) grad[3 * i + d] = g[d];
+    }
+    out[0] = X;
+    out[1] = Y;
+}
+
+/*
  * n_sweeps full sweeps starting at sweep counter t0 (sweep t = half-sweeps
  * 2t then 2t+1).  After every sweep whose 1-based position in this call is a
  * multiple of measure_every (0 = never), one sample is written:
