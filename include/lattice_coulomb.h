@@ -126,6 +126,36 @@ int set_charges(lattice_t *lat, int64_t n, const int32_t *xyz, const double *q);
 int lattice_set_charge_sets(lattice_t *lat, int64_t n_sets, const int64_t *counts,
                             const int32_t *xyz, const double *q);
 
+/* Charges at arbitrary positions (the paper's closing remark: model each
+ * position by its nearest eight lattice sites, and evaluate forces by
+ * interpolation the same way).  Site (x, y, z) sits at position (x, y, z)
+ * in lattice units; r = 3n doubles (host), each coordinate in
+ * [0, L_d - 1]; q = n doubles (host).  A charge at r lies in the cell with
+ * origin b_d = min(floor(r_d), L_d - 2) and spreads over its 8 corners with
+ * trilinear weights w; the field at the charge is phi~ = sum w phi.  A
+ * sample is O = X^2 - Y with X = sum_i q_i phi~_i and Y = sum_i
+ * (q_i phi~_i)^2, whose mean is sum_{i != j} q_i q_j w_i^T G w_j (equal to
+ * the on-lattice energy at integer positions).  forces != 0 also
+ * accumulates, at every sample, dO/dr_i = 2 q_i grad phi~_i (X - q_i phi~_i)
+ * (the gradient of the interpolant within the cell), whose mean is dE/dr_i
+ * (read with lattice_force_estimate; E sums ordered pairs, so the physical
+ * force on charge i is -(1/2) dE/dr_i).  Replaces all charge sets; resets
+ * the bins and force sums; the field and sweep counter are kept.  Errors:
+ * LAT_ERR_ARG for a position outside the box, a box edge below 2, a
+ * non-finite q or the variant LAT_SWEEP_RESIDENT (on-lattice charges only);
+ * LAT_ERR_ALLOC. */
+int lattice_set_offlattice_charges(lattice_t *lat, int64_t n, const double *r, const double *q,
+                                   int forces);
+
+/* Synchronise and read the force estimate of off-lattice charges set with
+ * forces: dE_dr (3n doubles, x y z per charge) = mean of the samples of
+ * dE/dr_i since the charges were set (or since lattice_set_state); stderr
+ * (3n, may be NULL) = their standard error computed as if the samples were
+ * independent (the chain's samples are correlated: bin the energy samples
+ * to see by how much).  LAT_ERR_STATE without such charges or with fewer
+ * than 2 samples. */
+int lattice_force_estimate(lattice_t *lat, double *dE_dr, double *stderr_naive, int64_t *n_samples);
+
 /* Enqueue n_sweeps sweeps without measurement (thermalisation). n_sweeps >= 0. */
 int thermalise(lattice_t *lat, int64_t n_sweeps);
 
@@ -227,7 +257,8 @@ int lattice_get_state(lattice_t *lat, int64_t *sweep_counter, int64_t *n_samples
 /* Restore a checkpoint taken by lattice_get_state (field restored separately
  * with lattice_set_field; the charge sets placed first): bins_host holds
  * n_bins bins per charge set, set after set.  bin_size as used when it was
- * taken. */
+ * taken.  Force sums of off-lattice charges are not part of a checkpoint:
+ * they restart from zero. */
 int lattice_set_state(lattice_t *lat, int64_t sweep_counter, int64_t n_samples, int64_t bin_size,
                       const double *bins_host, int64_t n_bins);
 

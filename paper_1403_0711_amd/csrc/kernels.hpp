@@ -73,6 +73,35 @@ struct MeasureArgs {
 };
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream);
 uint32_t measure_blocks(uint32_t n);
+// the second phase alone: per set, sum the partials, form O, bin it
+hipError_t launch_finalize_measure(const double* partials, uint32_t blocks, uint32_t n_sets, double* bins,
+                                   uint32_t m, uint32_t bin_size, const uint32_t* mdev, double* last_xy,
+                                   uint32_t bin_stride, hipStream_t stream);
+
+// Off-lattice charges (trilinear over the 8 corners of each charge's cell):
+// one sample O = X^2 - Y into bins[2*bin], and with fsum set, the force
+// sample 2 q_i grad phi~_i (X - q_i phi~_i) added to fsum / fsq (3 per charge).
+struct OffLatticeArgs {
+    const void* field0;
+    const void* field1;
+    uint32_t lx, ly, lz;
+    const double* r;       // 3n positions, lattice units
+    const double* q;       // n charges
+    uint32_t n;
+    double* partials;      // 2 * blocks scratch
+    double* bins;
+    uint32_t m;            // sample index (relative to *mdev when mdev is set)
+    uint32_t bin_size;
+    const uint32_t* mdev;
+    double* last_xy;
+    int storage;
+    uint32_t blocks;
+    uint32_t bin_stride;
+    double* phit;          // 4n scratch: phi~ and its gradient per charge (forces only)
+    double* fsum;          // 3n force sums, or null: no forces
+    double* fsq;           // 3n sums of squares
+};
+hipError_t launch_measure_offlattice(const OffLatticeArgs& a, hipStream_t stream);
 
 // Batched chains: one workgroup owns one chain and runs all its sweeps.
 struct BatchChainDesc {

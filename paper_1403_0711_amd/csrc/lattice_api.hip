@@ -53,6 +53,15 @@ struct lattice {
     uint32_t n_sets = 1;
     uint32_t* d_set_off = nullptr;
     double* d_lastxy = nullptr;  // X, Y of the last sample, per set
+    // off-lattice charges (trilinear over the 8 corners of each cell)
+    bool offl = false;
+    uint32_t n_off = 0;
+    double* d_r = nullptr;     // 3 n_off positions
+    double* d_qo = nullptr;    // n_off charges
+    double* d_phit = nullptr;  // 4 n_off scratch (forces only)
+    double* d_fsum = nullptr;  // 3 n_off force sums (null: forces off)
+    double* d_fsq = nullptr;
+    int64_t force_base = 0;    // n_meas when the force sums were last cleared
     // misc block: last X, Y (doubles at 64)
     void* d_misc = nullptr;
     // samples
@@ -100,7 +109,7 @@ struct lattice {
         if (variant != LAT_SWEEP_AUTO) return variant;
         // a box one workgroup sweeps in a few microseconds: launch overhead
         // would dominate, so run the whole call in one launch
-        if ((uint64_t)vh * 2 <= kResidentMaxSites && n_sets == 1) return LAT_SWEEP_RESIDENT;
+        if ((uint64_t)vh * 2 <= kResidentMaxSites && n_sets == 1 && !offl) return LAT_SWEEP_RESIDENT;
         if (lh % 4 != 0) return LAT_SWEEP_GENERIC;
         // boxes that spill out of the 256 MB last-level cache: z-marching slabs
         // fed through LDS by a producer wave (colour arrays below 2 GiB)
@@ -199,6 +208,16 @@ static int enqueue_resident(lattice* L, int64_t n_therm, int64_t n_meas, int64_t
 // One sample on `stream`.  Eager (mdev null): sample index L->n_meas, which
 // is advanced.  Captured: index mdev[0] + rel on the device.
 static int enqueue_measure_ex(lattice* L, hipStream_t stream, const uint32_t* mdev, uint32_t rel) {
+    if (L->offl) {
+        OffLatticeArgs o{L->field, L->c1cur(), (uint32_t)L->lx, (uint32_t)L->ly, (uint32_t)L->lz, L->d_r, L->d_qo,
+                         L->n_off, L->d_partials, L->d_bins, mdev ? rel : (uint32_t)L->n_meas,
+                         (uint32_t)L->bin_size, mdev, L->last_xy(), L->storage, L->meas_blocks,
+                         (uint32_t)L->bin_cap, L->d_phit, L->d_fsum, L->d_fsq};
+        hipError_t e = launch_measure_offlattice(o, stream);
+        if (e != hipSuccess) return hip_fail(e, "off-lattice measure launch");
+        if (!mdev) L->n_meas += 1;
+        return LAT_OK;
+    }
     MeasureArgs a{L->field, L->c1cur(), L->vh, L->d_site, L->d_Q, L->d_S, L->n_sites, L->d_partials,
                   L->d_bins, mdev ? rel : (uint32_t)L->n_meas, (uint32_t)L->bin_size, mdev, L->last_xy(),
                   L->storage, L->meas_blocks, L->d_set_off, L->n_sets, (uint32_t)L->bin_cap};
@@ -370,7 +389,7 @@ static std::map<std::tuple<int64_t, int64_t, int64_t, int>, TuneChoice> g_tune_c
 static std::vector<TuneChoice> tune_candidates(const lattice* L) {
     std::vector<TuneChoice> c;
     const uint64_t V = (uint64_t)L->vh * 2;
-    const bool resident_ok = L->n_sets == 1;  // the resident kernel measures one charge set
+    const bool resident_ok = L->n_sets == 1 && !L->offl;  // the resident kernel measures one on-lattice set
     if (V <= kResidentMaxSites && resident_ok) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
     if (L->lh % 4 != 0) {
         if (V > kResidentMaxSites && V <= (uint64_t)1 << 18 && resident_ok)
@@ -550,6 +569,11 @@ void lattice_destroy(lattice_t* L) {
     L->mem.release(L->d_partials);
     L->mem.release(L->d_set_off);
     L->mem.release(L->d_lastxy);
+    L->mem.release(L->d_r);
+    L->mem.release(L->d_qo);
+    L->mem.release(L->d_phit);
+    L->mem.release(L->d_fsum);
+    L->mem.release(L->d_fsq);
     L->mem.release(L->d_bins);
     delete L;
 }
@@ -579,6 +603,7 @@ int lattice_set_variant(lattice_t* L, int variant) {
         case LAT_SWEEP_GENERIC: break;
         case LAT_SWEEP_RESIDENT:
             if (L->n_sets > 1) return set_error(LAT_ERR_ARG, "the resident kernel measures one charge set");
+            if (L->offl) return set_error(LAT_ERR_ARG, "the resident kernel measures on-lattice charges only");
             break;
         case LAT_SWEEP_QUAD:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
@@ -636,6 +661,18 @@ int lattice_set_tuning(lattice_t* L, int64_t planes, int tile, int xcd_order) {
     L->xcd_order = xcd_order ? 1u : 0u;
     graphs_reset(L);
     return LAT_OK;
+}
+
+static void release_offlattice(lattice* L) {
+    L->mem.release(L->d_r);
+    L->mem.release(L->d_qo);
+    L->mem.release(L->d_phit);
+    L->mem.release(L->d_fsum);
+    L->mem.release(L->d_fsq);
+    L->d_r = L->d_qo = L->d_phit = L->d_fsum = L->d_fsq = nullptr;
+    L->offl = false;
+    L->n_off = 0;
+    L->force_base = 0;
 }
 
 int lattice_set_charge_sets(lattice_t* L, int64_t n_sets, const int64_t* counts, const int32_t* xyz,
@@ -719,6 +756,7 @@ int lattice_set_charge_sets(lattice_t* L, int64_t n_sets, const int64_t* counts,
     L->d_partials = d_part;
     L->d_set_off = d_off;
     L->d_lastxy = d_xy;
+    release_offlattice(L);
     L->n_sites = ns;
     L->n_raw = n;
     L->meas_blocks = blocks;
@@ -800,6 +838,123 @@ int energy_estimate(lattice_t* L, double* mean, double* stderr_binned, int64_t* 
     return lattice_energy_estimate_set(L, 0, mean, stderr_binned, n_samples, n_bins);
 }
 
+int lattice_set_offlattice_charges(lattice_t* L, int64_t n, const double* r, const double* q, int forces) {
+    if (int r_ = check_lattice(L)) return r_;
+    if (n < 0 || n >= (int64_t)0xFFFFFFFF) return set_error(LAT_ERR_ARG, "bad charge count");
+    if (n > 0 && (!r || !q)) return set_error(LAT_ERR_ARG, "r or q is NULL");
+    if (L->lx < 2 || L->ly < 2 || L->lz < 2)
+        return set_error(LAT_ERR_ARG, "off-lattice charges need every box edge >= 2");
+    if (L->variant == LAT_SWEEP_RESIDENT)
+        return set_error(LAT_ERR_ARG, "the resident kernel measures on-lattice charges only");
+    const double hi[3] = {(double)(L->lx - 1), (double)(L->ly - 1), (double)(L->lz - 1)};
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(q[i])) return set_error(LAT_ERR_ARG, "non-finite charge");
+        for (int d = 0; d < 3; ++d) {
+            const double v = r[3 * i + d];
+            if (!std::isfinite(v) || v < 0.0 || v > hi[d])
+                return set_error(LAT_ERR_ARG, "position outside [0, L - 1] on some axis");
+        }
+    }
+    const size_t cap = (size_t)std::max<int64_t>(n, 1);
+    const uint32_t blocks = measure_blocks((uint32_t)n);
+    double* d_r = static_cast<double*>(L->mem.alloc(cap * 24));
+    double* d_q = static_cast<double*>(L->mem.alloc(cap * 8));
+    double* d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * 16));
+    double* d_xy = static_cast<double*>(L->mem.alloc(16));
+    double *d_phit = nullptr, *d_fsum = nullptr, *d_fsq = nullptr;
+    if (forces) {
+        d_phit = static_cast<double*>(L->mem.alloc(cap * 32));
+        d_fsum = static_cast<double*>(L->mem.alloc(cap * 24));
+        d_fsq = static_cast<double*>(L->mem.alloc(cap * 24));
+    }
+    auto release_new = [&] {
+        L->mem.release(d_r);
+        L->mem.release(d_q);
+        L->mem.release(d_part);
+        L->mem.release(d_xy);
+        L->mem.release(d_phit);
+        L->mem.release(d_fsum);
+        L->mem.release(d_fsq);
+    };
+    if (!d_r || !d_q || !d_part || !d_xy || (forces && (!d_phit || !d_fsum || !d_fsq))) {
+        release_new();
+        return set_error(LAT_ERR_ALLOC, "allocation of the off-lattice charge list failed");
+    }
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        e = hipMemcpyAsync(d_r, r, (size_t)n * 24, hipMemcpyHostToDevice, L->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_q, q, (size_t)n * 8, hipMemcpyHostToDevice, L->stream);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(d_xy, 0, 16, L->stream);
+    if (e == hipSuccess && forces) e = hipMemsetAsync(d_fsum, 0, cap * 24, L->stream);
+    if (e == hipSuccess && forces) e = hipMemsetAsync(d_fsq, 0, cap * 24, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) {
+        release_new();
+        return hip_fail(e, "off-lattice charge upload");
+    }
+    // replace every charge set by this one off-lattice set
+    L->mem.release(L->d_site);
+    L->mem.release(L->d_Q);
+    L->mem.release(L->d_S);
+    L->mem.release(L->d_partials);
+    L->mem.release(L->d_set_off);
+    L->mem.release(L->d_lastxy);
+    L->d_site = nullptr;
+    L->d_Q = L->d_S = nullptr;
+    L->d_set_off = nullptr;
+    release_offlattice(L);
+    graphs_reset(L);
+    L->d_partials = d_part;
+    L->d_lastxy = d_xy;
+    L->d_r = d_r;
+    L->d_qo = d_q;
+    L->d_phit = d_phit;
+    L->d_fsum = d_fsum;
+    L->d_fsq = d_fsq;
+    L->offl = true;
+    L->n_off = (uint32_t)n;
+    L->n_sites = 0;
+    L->n_raw = n;
+    L->meas_blocks = blocks;
+    L->n_meas = 0;
+    L->bin_size = 0;
+    L->force_base = 0;
+    if (L->n_sets != 1) {
+        L->mem.release(L->d_bins);
+        L->d_bins = nullptr;
+        L->bin_cap = 0;
+        L->n_sets = 1;
+    } else if (L->d_bins) {
+        e = hipMemsetAsync(L->d_bins, 0, sizeof(double) * 2 * (size_t)L->bin_cap, L->stream);
+        if (e != hipSuccess) return hip_fail(e, "bin reset");
+    }
+    return LAT_OK;
+}
+
+int lattice_force_estimate(lattice_t* L, double* dE_dr, double* stderr_naive, int64_t* n_samples) {
+    if (int r_ = check_lattice(L)) return r_;
+    if (!L->offl || !L->d_fsum) return set_error(LAT_ERR_STATE, "no off-lattice charges with forces");
+    const int64_t M = L->n_meas - L->force_base;
+    if (n_samples) *n_samples = M;
+    const size_t k = (size_t)L->n_off * 3;
+    std::vector<double> s(std::max<size_t>(k, 1)), s2(std::max<size_t>(k, 1));
+    hipError_t e = hipStreamSynchronize(L->stream);
+    if (e == hipSuccess && k > 0) e = hipMemcpy(s.data(), L->d_fsum, k * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && k > 0) e = hipMemcpy(s2.data(), L->d_fsq, k * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "force readback");
+    if (M < 2) return set_error(LAT_ERR_STATE, "fewer than 2 force samples");
+    for (size_t i = 0; i < k; ++i) {
+        const double mean = s[i] / (double)M;
+        if (dE_dr) dE_dr[i] = mean;
+        if (stderr_naive) {
+            const double var = std::max(0.0, (s2[i] - (double)M * mean * mean) / (double)(M - 1));
+            stderr_naive[i] = std::sqrt(var / (double)M);
+        }
+    }
+    return LAT_OK;
+}
+
 int lattice_get_field(lattice_t* L, float* host_out) {
     if (int r = check_lattice(L)) return r;
     if (!host_out) return set_error(LAT_ERR_ARG, "host_out is NULL");
@@ -877,6 +1032,12 @@ int lattice_set_state(lattice_t* L, int64_t sweep_counter, int64_t n_samples, in
     L->t = sweep_counter;
     L->n_meas = n_samples;
     L->bin_size = n_samples > 0 ? bin_size : 0;
+    if (L->d_fsum) {  // force sums are not part of a checkpoint: restart them
+        e = hipMemsetAsync(L->d_fsum, 0, (size_t)L->n_off * 24, L->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(L->d_fsq, 0, (size_t)L->n_off * 24, L->stream);
+        if (e != hipSuccess) return hip_fail(e, "force reset");
+        L->force_base = n_samples;
+    }
     return LAT_OK;
 }
 

@@ -112,6 +112,14 @@ __global__ __launch_bounds__(kMeasureThreads) void finalize_measure(const double
     }
 }
 
+hipError_t launch_finalize_measure(const double* partials, uint32_t blocks, uint32_t n_sets, double* bins,
+                                   uint32_t m, uint32_t bin_size, const uint32_t* mdev, double* last_xy,
+                                   uint32_t bin_stride, hipStream_t stream) {
+    hipLaunchKernelGGL(finalize_measure, dim3(n_sets), dim3(kMeasureThreads), 0, stream, partials, blocks, bins, m,
+                       bin_size, mdev, last_xy, bin_stride);
+    return hipGetLastError();
+}
+
 template <class St>
 static hipError_t launch_measure_t(const MeasureArgs& a, hipStream_t stream) {
     if (a.n_sets < 1 || (a.n_sets > 1 && !a.set_off)) return hipErrorInvalidValue;

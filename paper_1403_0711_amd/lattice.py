@@ -65,6 +65,8 @@ def load_library() -> ctypes.CDLL:
         "energy_estimate": (_int, [_p, _pd, _pd, _pi64, _pi64]),
         "lattice_set_charge_sets": (_int, [_p, _i64, _p, _p, _p]),
         "lattice_energy_estimate_set": (_int, [_p, _i64, _pd, _pd, _pi64, _pi64]),
+        "lattice_set_offlattice_charges": (_int, [_p, _i64, _p, _p, _int]),
+        "lattice_force_estimate": (_int, [_p, _p, _p, _pi64]),
         "lattice_destroy": (None, [_p]),
         "lattice_last_error": (ctypes.c_char_p, []),
         "lattice_sweep_count": (_int, [_p, _pi64]),
@@ -164,6 +166,7 @@ class Lattice:
                                            ctypes.byref(h)))
         self.h = h
         self.n_sets = 1  # charge sets measured per sweep
+        self.n_offlattice = 0
 
     # -- lifetime --------------------------------------------------------
     def close(self):
@@ -217,6 +220,28 @@ class Lattice:
         q = np.ascontiguousarray(np.concatenate(qs) if qs else np.zeros(0), dtype=np.float64)
         self._call(self.lib.lattice_set_charge_sets, len(counts), _ptr(counts), _ptr(xyz), _ptr(q))
         self.n_sets = len(counts)
+    def set_offlattice_charges(self, r, q, forces: bool = False):
+        """Charges at real positions ``r`` (n x 3, lattice units), each spread
+        over the 8 corners of its cell; with ``forces``, also estimate
+        dE/dr per charge (``force_estimate``)."""
+        r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1, 3)
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        if r.shape[0] != q.shape[0]:
+            raise ValueError("r and q differ in length")
+        self._call(self.lib.lattice_set_offlattice_charges, q.shape[0], _ptr(r), _ptr(q), 1 if forces else 0)
+        self.n_sets = 1
+        self.n_offlattice = q.shape[0]
+
+    def force_estimate(self):
+        """Returns ``(dE_dr, stderr, n_samples)`` with arrays (n, 3); the
+        physical force is -dE_dr / 2 (E sums ordered pairs)."""
+        n = self.n_offlattice
+        g = np.zeros((max(n, 1), 3))
+        se = np.zeros((max(n, 1), 3))
+        m = ctypes.c_int64()
+        self._call(self.lib.lattice_force_estimate, _ptr(g), _ptr(se), ctypes.byref(m))
+        return g[:n], se[:n], m.value
+
     def thermalise(self, n_sweeps: int):
         self._call(self.lib.thermalise, int(n_sweeps))
 
