@@ -18,8 +18,9 @@ stored in tests/golden/exact_energies.json), the same sweep with FP16 field
 storage and the 512-chain batched workload for comparison, and the CPU oracle
 timed on a bounded sample of the same workload; with extras, also a coupled
 FP32 / BF16 / FP16 comparison on the 384^3 Gaussian blob (bias of the 16-bit
-chains and their cost per sweep), four charge sets sampled on one chain, and
-the paper's two accuracy figures (132 charge sets on one 128^3 chain).
+chains and their cost per sweep), four charge sets sampled on one chain, the
+paper's two accuracy figures (132 charge sets on one 128^3 chain), and the
+charges moved off the lattice with force estimates.
 """
 
 from __future__ import annotations
@@ -283,6 +284,27 @@ def figures_comparison(sweeps: int = 200000):
     return out
 
 
+def offlattice_comparison(cs, spec, steps, bin_size, torch, lattice):
+    """The workload's charges moved off the lattice (each by a seeded uniform
+    offset in [0, 1) per axis, kept in the box) with force estimates on:
+    cost per step against the on-lattice step."""
+    rng = np.random.default_rng(1)
+    hi = np.array(cs.shape, dtype=np.float64) - 1.0
+    r = np.minimum(cs.xyz + rng.uniform(size=cs.xyz.shape), hi)
+    lat = lattice.Lattice(cs.shape, "fp32", seed=spec["philox_seed"])
+    lat.set_offlattice_charges(r, cs.q, forces=True)
+    lat.sweep_and_measure(5, 1, bin_size)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.sweep_and_measure(steps, 1, bin_size)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g, se, n = lat.force_estimate()
+    lat.close()
+    return {"charges": int(cs.n), "forces": True, "ms_per_step": 1e3 * dt / steps,
+            "force_samples": int(n), "median_force_stderr_rel": float(np.median(se / np.maximum(np.abs(g), 1e-30)))}
+
+
 def copy_reference(n_bytes: int, torch, reps: int = 10):
     """A device-to-device copy of n_bytes (read n_bytes, write n_bytes), timed
     with HIP events: the practical ceiling for a kernel that streams one array
@@ -424,6 +446,9 @@ def main():
                                               lattice)
                 sets["set_samples_vs_one_set"] = sets["set_samples_per_s"] / (1e3 / ms_per_step)
                 out["charge_sets"] = sets
+                off = offlattice_comparison(cs, spec, min(args.steps, 200), args.bin_size, torch, lattice)
+                off["cost_vs_on_lattice"] = off["ms_per_step"] / ms_per_step
+                out["offlattice_forces"] = off
         except Exception as exc:  # comparisons must not hide the headline line
             out["extras_error"] = repr(exc)
     if not args.no_cpu_baseline:
