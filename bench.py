@@ -67,6 +67,10 @@ def parse():
     p.add_argument("--kernel-reps", type=int, default=50,
                    help="sweeps timed for the per-kernel (half-sweep) duration")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--figures-sweeps", type=int, default=200000,
+                   help="measured sweeps of the figures comparison (128^3, 132 charge sets)")
+    p.add_argument("--coupled-sweeps", type=int, default=10000,
+                   help="sweeps per storage format of the coupled precision comparison")
     return p.parse_args()
 
 
@@ -268,7 +272,7 @@ def figures_comparison(sweeps: int = 200000):
 
     with open(EXACT_FILE) as f:
         ex = json.load(f)
-    res = figures.run(L=128, therm=5000, sweeps=sweeps, bin_size=2000)
+    res = figures.run(L=128, therm=min(5000, sweeps), sweeps=sweeps, bin_size=min(2000, max(sweeps // 10, 1)))
     n_pair = len(ex["fig1_pair_scan_128"]["E_lat"])
     e_lat = np.array(ex["fig1_pair_scan_128"]["E_lat"] + ex["fig2_cubes_128"]["E_lat"])
     e_s1 = np.array(ex["fig1_pair_scan_128"]["E_continuum"] + ex["fig2_cubes_128"]["E_continuum"])
@@ -439,8 +443,8 @@ def main():
                 f16["speedup_vs_fp32"] = ms_per_step / f16["ms_per_step"]
                 out["fp16_storage"] = f16
             out["batched_512"] = batched_comparison(200, torch, lattice, workloads)
-            out["precision_coupled"] = precision_coupled(10000, torch, lattice, workloads)
-            out["figures_128"] = figures_comparison()
+            out["precision_coupled"] = precision_coupled(args.coupled_sweeps, torch, lattice, workloads)
+            out["figures_128"] = figures_comparison(args.figures_sweeps)
             if args.storage == "fp32":
                 sets = charge_sets_comparison(cs, spec, workloads, min(args.steps, 200), args.bin_size, torch,
                                               lattice)
