@@ -32,10 +32,11 @@ def figure_sets(L: int = 128, cube_sides=(2, 4, 8, 16, 32)):
 
 
 def run(L: int = 128, therm: int = 5000, sweeps: int = 200000, bin_size: int = 2000, checkpoints=None,
-        storage: str = "fp32", seed: int = 0, cube_sides=(2, 4, 8, 16, 32)):
+        storage: str = "fp32", seed: int = 0, cube_sides=(2, 4, 8, 16, 32), progress=None):
     """Thermalise, then sample every set after every sweep; at each checkpoint
     (a number of samples, a multiple of bin_size) record every set's running
-    mean, binned error and number of full bins.  Returns a dict."""
+    mean, binned error and number of full bins; ``progress(row)`` is called
+    with each checkpoint's record as it completes.  Returns a dict."""
     import torch
 
     from . import lattice
@@ -58,7 +59,9 @@ def run(L: int = 128, therm: int = 5000, sweeps: int = 200000, bin_size: int = 2
         done = m
         est = [lat.energy_estimate(allow_few_bins=True, charge_set=k) for k in range(len(sets))]
         rows.append({"M": m, "mean": [e[0] for e in est], "stderr": [e[1] for e in est],
-                     "bins": est[0][3]})
+                     "bins": est[0][3], "seconds": time.perf_counter() - t0})
+        if progress:
+            progress(rows[-1])
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     lat.close()
@@ -74,8 +77,12 @@ def main():
     p.add_argument("--sweeps", type=int, default=200000)
     p.add_argument("--bin-size", type=int, default=2000)
     p.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
+    p.add_argument("--checkpoints", type=str, default=None,
+                   help="comma-separated sample counts (multiples of --bin-size); default: 10, 20, 50, 100 bins and the end")
     a = p.parse_args()
-    res = run(a.L, a.therm, a.sweeps, a.bin_size, storage=a.storage)
+    cps = [int(float(v)) for v in a.checkpoints.split(",")] if a.checkpoints else None
+    res = run(a.L, a.therm, a.sweeps, a.bin_size, checkpoints=cps, storage=a.storage,
+              progress=lambda row: print(json.dumps({"checkpoint": row["M"], "seconds": row["seconds"]}), flush=True))
     print(json.dumps(res))
 
 

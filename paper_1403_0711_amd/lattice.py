@@ -56,6 +56,12 @@ def load_library() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_1403_0711_amd.build_lib` (or __graft_entry__.build())")
+    # PyTorch (which provides the device memory and streams) brings its own
+    # HIP runtime: load it and let it find the devices before this library's
+    # HIP calls, whatever the caller imported first.
+    import torch
+
+    torch.cuda.is_available()
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "lattice_create": (_int, [_i64, _i64, _i64, _int, _u64, _u32, _p, _p, _p]),
