@@ -217,6 +217,17 @@ int lattice_set_tuning(lattice_t *lat, int64_t planes, int tile, int xcd_order);
  * order. */
 int lattice_get_tuning(const lattice_t *lat, int *variant, int64_t *planes, int *tile, int *xcd_order);
 
+/* How the samples of the most recent sweep_and_measure were gathered:
+ * *fused = 1 if the streaming sweep kernel summed X and Y of each sample
+ * from its LDS plane ring (the charged colour-0 sites while it updated
+ * colour 1 of the measured sweep, the colour-1 sites while it updated colour
+ * 0 of the next sweep), which needs one on-lattice charge set,
+ * LAT_SWEEP_STREAM and a per-tile charge list short enough to stage in LDS
+ * without lowering the kernel's occupancy; 0 if a separate gather kernel
+ * read the field after each measured sweep.  The two give the same samples
+ * up to the order of the FP64 partial sums. */
+int lattice_get_sample_path(const lattice_t *lat, int *fused);
+
 /* Graph capture of the multi-launch sweep path: runs of sweeps (with their
  * samples) are recorded once as a hipGraph of K-sweep chunks whose kernels
  * read the sweep and sample counters from device memory, then replayed.

@@ -212,6 +212,16 @@ struct StoreBF16 {
     }
 };
 
+// The FP32 value v as a register: the rounding to FP16 that follows cannot
+// be folded into the FMA that produced v (a mixed-precision FMA rounds once,
+// from the exact result), so every kernel stores the FP32 update rounded to
+// FP16, and a value recomputed elsewhere rounds the same way.
+__device__ __forceinline__ float fp32_reg(float v) {
+    asm("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ _Float16 to_f16(float v) { return (_Float16)fp32_reg(v); }
+
 struct StoreF16 {
     using T = _Float16;
     static constexpr int kBytes = 2;
@@ -224,18 +234,18 @@ struct StoreF16 {
     __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) {
         typedef _Float16 h4 __attribute__((ext_vector_type(4)));
         h4 w;
-        w[0] = (_Float16)v.x;
-        w[1] = (_Float16)v.y;
-        w[2] = (_Float16)v.z;
-        w[3] = (_Float16)v.w;
+        w[0] = to_f16(v.x);
+        w[1] = to_f16(v.y);
+        w[2] = to_f16(v.z);
+        w[3] = to_f16(v.w);
         at<h4>(p, i) = w;
     }
     __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v) {
         typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        const h4 w = {(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
+        const h4 w = {to_f16(v.x), to_f16(v.y), to_f16(v.z), to_f16(v.w)};
         __builtin_nontemporal_store(w, &at<h4>(p, i));
     }
-    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<_Float16>(p, i) = (_Float16)v; }
+    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<_Float16>(p, i) = to_f16(v); }
     __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
         typedef _Float16 h4 __attribute__((ext_vector_type(4)));
@@ -246,7 +256,7 @@ struct StoreF16 {
         return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
     }
     __device__ static __forceinline__ float4 round4(float4 v) {
-        return make_float4((float)(_Float16)v.x, (float)(_Float16)v.y, (float)(_Float16)v.z, (float)(_Float16)v.w);
+        return make_float4((float)to_f16(v.x), (float)to_f16(v.y), (float)to_f16(v.z), (float)to_f16(v.w));
     }
 };
 

@@ -21,11 +21,43 @@ struct SweepArgs {
     uint32_t xcd_order;  // slab kernels: XCD-aware block order
     uint32_t tile;    // slab kernels: tile configuration (kZslabTiles / kStreamTiles of them)
     const uint32_t* tdev;  // if set, h += 2 * tdev[0] (sweep counter on the device)
+    // streaming kernel: fused gather of the charged sites of the other
+    // colour (1 - c) over per-tile lists (g_off: tiles + 1 absolute offsets;
+    // g_key: site j in that colour's array; g_Q, g_S; g_n entries in the
+    // arrays), one (X, Y) partial per tile into g_part.  g_cap: LDS entries
+    // staged per workgroup (a multiple of 64, at least the longest tile
+    // list).  Null: no gather.
+    const uint32_t* g_off = nullptr;
+    const uint32_t* g_key = nullptr;
+    const double* g_Q = nullptr;
+    const double* g_S = nullptr;
+    double* g_part = nullptr;
+    uint32_t g_n = 0, g_cap = 0;
 };
+constexpr uint32_t kGatherEntryBytes = 20;  // staged key (4 B), Q and S (8 B each)
 constexpr int kZslabTiles = 8;
 constexpr int kStreamTiles = 10;  // tile configurations of the streaming slab kernel
 hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream);
 hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream);  // tile 0 .. kStreamTiles-1
+// Shape of a streaming-kernel tile configuration at element size esz: quads
+// per tile row, rows, static LDS bytes (the plane ring), waves per workgroup.
+struct StreamTileShape {
+    uint32_t quads, rows, lds, waves;
+};
+bool stream_tile_geometry(uint32_t tile, uint32_t esz, StreamTileShape* out);
+// The colour-1 part of a fused-gather sample from the colour-1 array in
+// memory, in the streaming kernel's order (one partial per tile).
+struct GatherTailArgs {
+    const void* field1;  // colour-1 array
+    int storage;
+    uint32_t lh, ly, lz, zc, tile;
+    const uint32_t* g_off;  // the colour-1 lists
+    const uint32_t* g_key;
+    const double* g_Q;
+    const double* g_S;
+    double* g_part;
+};
+hipError_t launch_gather_tail(const GatherTailArgs& a, hipStream_t stream);
 // device-side sweep / sample counters (ctr[0], ctr[1]) for graph replays
 hipError_t launch_set_counters(uint32_t* ctr, uint32_t t, uint32_t m, hipStream_t stream);
 hipError_t launch_advance_counters(uint32_t* ctr, uint32_t dt, uint32_t dm, hipStream_t stream);

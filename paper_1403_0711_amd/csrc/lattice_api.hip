@@ -62,6 +62,34 @@ struct lattice {
     double* d_fsum = nullptr;  // 3 n_off force sums (null: forces off)
     double* d_fsq = nullptr;
     int64_t force_base = 0;    // n_meas when the force sums were last cleared
+    // host copy of the aggregated list of a single on-lattice charge set
+    std::vector<uint32_t> h_site;
+    std::vector<double> h_Q, h_S;
+    // fused gather of the streaming kernel: the list split by colour and
+    // regrouped per tile and by plane, for one tile shape and slab (d_off:
+    // the colour-0 then the colour-1 offset tables, tiles + 1 each, into
+    // d_key / d_Q / d_S; d_part: the colour-0 then the colour-1 partials)
+    struct FusedGather {
+        bool ready = false;
+        bool tried = false;  // lists considered for (tile, slab): ready, or the separate gather
+        bool last = false;  // the samples of the last sweep_and_measure took this path
+        uint32_t tile = 0, slab = 0, blocks = 0;
+        uint32_t n = 0, cap = 0;  // entries in all; LDS entries staged per workgroup
+        uint32_t* d_off = nullptr;
+        uint32_t* d_key = nullptr;
+        double* d_Q = nullptr;
+        double* d_S = nullptr;
+        double* d_part = nullptr;
+    } fg;
+    // How the fused gather takes part in one sweep: its colour-0 launch
+    // completes the open sample (its colour-1 sites) and finalizes it as
+    // sample m (on the device counter mdev when captured); its colour-1
+    // launch opens this sweep's sample (its colour-0 sites).
+    struct FusedStep {
+        bool finish = false, open = false;
+        uint32_t m = 0;
+        const uint32_t* mdev = nullptr;
+    };
     // misc block: last X, Y (doubles at 64)
     void* d_misc = nullptr;
     // samples
@@ -78,6 +106,7 @@ struct lattice {
         uint32_t slab = 0, tile = 0, xcd = 0;
         const void* bins = nullptr;
         const void* site = nullptr;
+        const void* gather = nullptr;  // per-tile lists of a fused gather, else null
     };
     SweepGraph g_therm, g_meas;
     hipStream_t cap = nullptr;  // private capture stream
@@ -129,9 +158,128 @@ static int check_lattice(const lattice* L) {
     return LAT_OK;
 }
 
+static void graphs_reset(lattice* L);
+
+static void fused_gather_release(lattice* L) {
+    L->mem.release(L->fg.d_off);
+    L->mem.release(L->fg.d_key);
+    L->mem.release(L->fg.d_Q);
+    L->mem.release(L->fg.d_S);
+    L->mem.release(L->fg.d_part);
+    L->fg = lattice::FusedGather();
+}
+
+// Whether samples of this lattice are gathered inside the streaming kernel:
+// one on-lattice charge set and the lists built for the current tiling.
+static bool fused_gather_on(const lattice* L) {
+    return L->fg.ready && L->effective_variant() == LAT_SWEEP_STREAM && L->n_sets == 1 && !L->offl &&
+           L->fg.tile == L->resolved_tile(LAT_SWEEP_STREAM) && L->fg.slab == (L->slab ? L->slab : 16u);
+}
+
+// Resident workgroups per CU of a kernel with `lds` bytes of LDS and `waves`
+// waves per workgroup (160 KiB of LDS and 32 wave slots per CU).
+static uint32_t workgroups_per_cu(uint32_t lds, uint32_t waves) {
+    return std::min<uint32_t>(lds ? 163840u / lds : 32u, 32u / waves);
+}
+
+// Build the per-tile lists of the fused gather for the current tiling (host
+// sort of the aggregated list, one upload); outside any capture.  Without
+// them (other kernels, several or off-lattice sets, a tile list too long to
+// stage in LDS without costing the sweep kernel a resident workgroup,
+// allocation failure) the samples go through the separate gather.
+static int fused_gather_prepare(lattice* L) {
+    const uint32_t tile = L->resolved_tile(LAT_SWEEP_STREAM), slab = L->slab ? L->slab : 16u;
+    if (L->effective_variant() != LAT_SWEEP_STREAM || L->n_sets != 1 || L->offl ||
+        L->h_site.size() != L->n_sites)
+        return LAT_OK;
+    if (L->fg.tried && L->fg.tile == tile && L->fg.slab == slab) return LAT_OK;
+    fused_gather_release(L);
+    graphs_reset(L);
+    L->fg.tried = true;
+    L->fg.tile = tile;
+    L->fg.slab = slab;
+    StreamTileShape sh;
+    if (!stream_tile_geometry(tile, L->esz, &sh)) return LAT_OK;
+    const uint32_t tq = sh.quads, ty = sh.rows;
+    const uint32_t nq = L->lh / 4, ly = (uint32_t)L->ly, lz = (uint32_t)L->lz;
+    const uint32_t nbx = (nq + tq - 1) / tq, nby = (ly + ty - 1) / ty, nbz = (lz + slab - 1) / slab;
+    const uint32_t blocks = nbx * nby * nbz;
+    const uint32_t plane = (uint32_t)L->ly * L->lh;
+    const size_t n = L->h_site.size();
+    // sort key of every charged site: its colour, its tile, its plane
+    std::vector<uint64_t> key_of(n);
+    std::vector<uint32_t> tile_of(n), j_of(n);
+    size_t n0 = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const uint32_t c = L->h_site[i] >= L->vh ? 1u : 0u;
+        const uint32_t j = L->h_site[i] - c * L->vh;
+        const uint32_t z = j / plane, rem = j - z * plane, y = rem / L->lh, jx = rem - y * L->lh;
+        tile_of[i] = (jx / 4) / tq + nbx * (y / ty + nby * (z / slab));
+        j_of[i] = j;
+        key_of[i] = ((uint64_t)c * blocks + tile_of[i]) * lz + z;
+        n0 += c ? 0u : 1u;
+    }
+    std::vector<uint32_t> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key_of[a] < key_of[b]; });
+    // offsets: colour 0 at [0, blocks], colour 1 at [blocks + 1, 2 blocks + 1]
+    std::vector<uint32_t> off(2 * ((size_t)blocks + 1), 0u), key(n);
+    std::vector<double> Q(n), S(n);
+    for (size_t k = 0; k < n; ++k) {
+        const uint32_t i = order[k];
+        const size_t c = k < n0 ? 0 : 1;
+        off[c * (blocks + 1) + tile_of[i] + 1] += 1;
+        key[k] = j_of[i];
+        Q[k] = L->h_Q[i];
+        S[k] = L->h_S[i];
+    }
+    uint32_t longest = 0;
+    for (size_t t = 0; t < 2 * ((size_t)blocks + 1); ++t) longest = std::max(longest, off[t]);
+    const uint64_t cap = ((uint64_t)longest + 63u) / 64u * 64u;
+    const uint64_t lds = sh.lds + (uint64_t)kGatherEntryBytes * cap;
+    if (lds > 65536u || workgroups_per_cu((uint32_t)lds, sh.waves) < workgroups_per_cu(sh.lds, sh.waves) ||
+        (uint64_t)n * 8u >= (1ull << 32))
+        return LAT_OK;  // the separate gather
+    off[blocks + 1] = (uint32_t)n0;
+    for (size_t c = 0; c < 2; ++c)
+        for (size_t t = 0; t < blocks; ++t) off[c * (blocks + 1) + t + 1] += off[c * (blocks + 1) + t];
+    lattice::FusedGather g = L->fg;
+    g.d_off = static_cast<uint32_t*>(L->mem.alloc(off.size() * 4));
+    g.d_key = static_cast<uint32_t*>(L->mem.alloc(std::max<size_t>(n, 1) * 4));
+    g.d_Q = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
+    g.d_S = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
+    g.d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * 32));
+    L->fg = g;  // released by fused_gather_release on any failure below
+    if (!g.d_off || !g.d_key || !g.d_Q || !g.d_S || !g.d_part) {
+        fused_gather_release(L);
+        L->fg.tried = true;  // the separate gather for this tiling
+        L->fg.tile = tile;
+        L->fg.slab = slab;
+        return LAT_OK;
+    }
+    hipError_t e = hipMemcpyAsync(g.d_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_key, key.data(), n * 4, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_Q, Q.data(), n * 8, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_S, S.data(), n * 8, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) {
+        fused_gather_release(L);
+        return hip_fail(e, "fused gather list upload");
+    }
+    L->fg.ready = true;
+    L->fg.tile = tile;
+    L->fg.slab = slab;
+    L->fg.blocks = blocks;
+    L->fg.n = (uint32_t)n;
+    L->fg.cap = (uint32_t)cap;
+    return LAT_OK;
+}
+
 // One sweep on `stream`.  Eager (tdev null): sweep index L->t, which is
 // advanced.  Captured: index tdev[0] + rel, read on the device at run time.
-static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint32_t rel) {
+// fs: the fused gather's part in this sweep (streaming kernel only).
+static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint32_t rel,
+                            const lattice::FusedStep* fs = nullptr) {
     const uint32_t h0 = tdev ? 2u * rel : (uint32_t)(2 * L->t);
     const int v = L->effective_variant();
     hipError_t e;
@@ -150,10 +298,28 @@ static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev
         SweepArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, 0u, h0,
                     (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, kv, L->slab,
                     L->xcd_order, L->resolved_tile(v), tdev};
+        const lattice::FusedGather& g = L->fg;
+        auto gather_lists = [&](uint32_t colour) {  // gather the charged sites of `colour`
+            a.g_off = g.d_off + (size_t)colour * (g.blocks + 1);
+            a.g_key = g.d_key;
+            a.g_Q = g.d_Q;
+            a.g_S = g.d_S;
+            a.g_part = g.d_part + (size_t)colour * 2 * g.blocks;
+            a.g_n = g.n;
+            a.g_cap = g.cap;
+        };
+        if (fs && fs->finish) gather_lists(1u);
         e = launch_halfsweep(a, stream);
+        if (e == hipSuccess && fs && fs->finish)
+            e = launch_finalize_measure(g.d_part, 2 * g.blocks, 1u, L->d_bins, fs->m, (uint32_t)L->bin_size,
+                                        fs->mdev, L->last_xy(), (uint32_t)L->bin_cap, stream);
         if (e == hipSuccess) {
             a.c = 1u;
             a.h = h0 + 1u;
+            a.g_off = a.g_key = nullptr;
+            a.g_Q = a.g_S = nullptr;
+            a.g_part = nullptr;
+            if (fs && fs->open) gather_lists(0u);
             e = launch_halfsweep(a, stream);
         }
     }
@@ -162,9 +328,23 @@ static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev
     return LAT_OK;
 }
 
-static int enqueue_sweep(lattice* L) {
+static int enqueue_sweep(lattice* L, const lattice::FusedStep* fs = nullptr) {
     if (L->t >= (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_STATE, "sweep counter exhausted (2^31 sweeps)");
-    return enqueue_sweep_ex(L, L->stream, nullptr, 0);
+    return enqueue_sweep_ex(L, L->stream, nullptr, 0, fs);
+}
+
+// The open sample's colour-1 sites from memory (no sweep follows it), then
+// its finalize as sample m.
+static int enqueue_fused_tail(lattice* L, hipStream_t stream, uint32_t m, const uint32_t* mdev) {
+    const lattice::FusedGather& g = L->fg;
+    GatherTailArgs a{L->c1cur(), L->storage, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->slab, g.tile,
+                     g.d_off + g.blocks + 1, g.d_key, g.d_Q, g.d_S, g.d_part + 2 * (size_t)g.blocks};
+    hipError_t e = launch_gather_tail(a, stream);
+    if (e == hipSuccess)
+        e = launch_finalize_measure(g.d_part, 2 * g.blocks, 1u, L->d_bins, m, (uint32_t)L->bin_size, mdev,
+                                    L->last_xy(), (uint32_t)L->bin_cap, stream);
+    if (e != hipSuccess) return hip_fail(e, "measure launch");
+    return LAT_OK;
 }
 
 // The resident path: n_therm unmeasured sweeps then n_meas sweeps with a
@@ -266,8 +446,12 @@ static int64_t graph_chunk(const lattice* L, int64_t every) {
     return K;
 }
 
+static const void* graph_gather_key(const lattice* L, int64_t every) {
+    return every > 0 && fused_gather_on(L) ? L->fg.d_off : nullptr;
+}
+
 static bool graph_matches(const lattice* L, const lattice::SweepGraph& g, int64_t K, int64_t every) {
-    return g.exec && g.K == K && g.every == every && g.variant == L->effective_variant() && g.slab == L->slab &&
+    return g.exec && g.gather == graph_gather_key(L, every) && g.K == K && g.every == every && g.variant == L->effective_variant() && g.slab == L->slab &&
            g.tile == L->tile && g.xcd == L->xcd_order && g.site == L->d_site &&
            (every == 0 || (g.bins == L->d_bins && g.bin_size == L->bin_size));
 }
@@ -285,11 +469,25 @@ static int graph_capture(lattice* L, lattice::SweepGraph& g, int64_t K, int64_t 
     if (e != hipSuccess) return hip_fail(e, "begin capture");
     int rc = LAT_OK;
     uint32_t m = 0;
+    const bool fused = graph_gather_key(L, every) != nullptr;
+    bool open = false;  // fused: sample m - 1 awaits its colour-1 sites
     for (int64_t s = 0; s < K && rc == LAT_OK; ++s) {
-        rc = enqueue_sweep_ex(L, L->cap, L->counters(), (uint32_t)s);
-        if (rc == LAT_OK && every > 0 && (s + 1) % every == 0)
-            rc = enqueue_measure_ex(L, L->cap, L->counters() + 1, m++);
+        const bool measured = every > 0 && (s + 1) % every == 0;
+        if (fused) {
+            lattice::FusedStep fs;
+            fs.finish = open;
+            fs.open = measured;
+            fs.m = m - 1u;
+            fs.mdev = L->counters() + 1;
+            rc = enqueue_sweep_ex(L, L->cap, L->counters(), (uint32_t)s, &fs);
+            open = measured;
+            m += measured ? 1u : 0u;
+        } else {
+            rc = enqueue_sweep_ex(L, L->cap, L->counters(), (uint32_t)s);
+            if (rc == LAT_OK && measured) rc = enqueue_measure_ex(L, L->cap, L->counters() + 1, m++);
+        }
     }
+    if (rc == LAT_OK && open) rc = enqueue_fused_tail(L, L->cap, m - 1u, L->counters() + 1);
     if (rc == LAT_OK) {
         e = launch_advance_counters(L->counters(), (uint32_t)K, m, L->cap);
         if (e != hipSuccess) rc = hip_fail(e, "capture");
@@ -317,6 +515,7 @@ static int graph_capture(lattice* L, lattice::SweepGraph& g, int64_t K, int64_t 
     g.xcd = L->xcd_order;
     g.bins = L->d_bins;
     g.site = L->d_site;
+    g.gather = graph_gather_key(L, every);
     return LAT_OK;
 }
 
@@ -339,11 +538,26 @@ static int run_sweeps(lattice* L, int64_t n, int64_t every) {
         L->t += done;
         if (every > 0) L->n_meas += done / every;
     }
+    const bool fused = every > 0 && fused_gather_on(L);
+    bool open = false;  // fused: sample L->n_meas - 1 awaits its colour-1 sites
     for (int64_t s = done; s < n; ++s) {
-        if (int r = enqueue_sweep(L)) return r;
-        if (every > 0 && (s + 1) % every == 0)
-            if (int r = enqueue_measure(L)) return r;
+        const bool measured = every > 0 && (s + 1) % every == 0;
+        if (fused) {
+            lattice::FusedStep fs;
+            fs.finish = open;
+            fs.open = measured;
+            fs.m = (uint32_t)(L->n_meas - 1);
+            if (int r = enqueue_sweep(L, &fs)) return r;
+            open = measured;
+            L->n_meas += measured ? 1 : 0;
+        } else {
+            if (int r = enqueue_sweep(L)) return r;
+            if (measured)
+                if (int r = enqueue_measure(L)) return r;
+        }
     }
+    if (open)
+        if (int r = enqueue_fused_tail(L, L->stream, (uint32_t)(L->n_meas - 1), nullptr)) return r;
     return settle_colour1(L);
 }
 
@@ -574,6 +788,7 @@ void lattice_destroy(lattice_t* L) {
     L->mem.release(L->d_phit);
     L->mem.release(L->d_fsum);
     L->mem.release(L->d_fsq);
+    fused_gather_release(L);
     L->mem.release(L->d_bins);
     delete L;
 }
@@ -640,6 +855,12 @@ int lattice_get_tuning(const lattice_t* L, int* variant, int64_t* planes, int* t
     if (planes) *planes = L->slab;
     if (tile) *tile = (int)L->resolved_tile(v);
     if (xcd_order) *xcd_order = (int)L->xcd_order;
+    return LAT_OK;
+}
+
+int lattice_get_sample_path(const lattice_t* L, int* fused) {
+    if (int r = check_lattice(L)) return r;
+    if (fused) *fused = L->fg.last ? 1 : 0;
     return LAT_OK;
 }
 
@@ -757,6 +978,16 @@ int lattice_set_charge_sets(lattice_t* L, int64_t n_sets, const int64_t* counts,
     L->d_set_off = d_off;
     L->d_lastxy = d_xy;
     release_offlattice(L);
+    fused_gather_release(L);
+    if (n_sets == 1) {
+        L->h_site.swap(all.site);
+        L->h_Q.swap(all.Q);
+        L->h_S.swap(all.S);
+    } else {
+        L->h_site.clear();
+        L->h_Q.clear();
+        L->h_S.clear();
+    }
     L->n_sites = ns;
     L->n_raw = n;
     L->meas_blocks = blocks;
@@ -807,7 +1038,12 @@ int sweep_and_measure(lattice_t* L, int64_t n_sweeps, int64_t measure_every, int
         return set_error(LAT_ERR_ARG, "too many bins");
     if (int r = ensure_bins(L, (total + bin_size - 1) / bin_size)) return r;
     L->bin_size = bin_size;
-    if (L->effective_variant() == LAT_SWEEP_RESIDENT) return enqueue_resident(L, 0, n_sweeps, measure_every);
+    if (L->effective_variant() == LAT_SWEEP_RESIDENT) {
+        L->fg.last = false;
+        return enqueue_resident(L, 0, n_sweeps, measure_every);
+    }
+    if (int r = fused_gather_prepare(L)) return r;
+    L->fg.last = fused_gather_on(L);
     return run_sweeps(L, n_sweeps, measure_every);
 }
 
@@ -904,6 +1140,10 @@ int lattice_set_offlattice_charges(lattice_t* L, int64_t n, const double* r, con
     L->d_Q = L->d_S = nullptr;
     L->d_set_off = nullptr;
     release_offlattice(L);
+    fused_gather_release(L);
+    L->h_site.clear();
+    L->h_Q.clear();
+    L->h_S.clear();
     graphs_reset(L);
     L->d_partials = d_part;
     L->d_lastxy = d_xy;

@@ -79,23 +79,43 @@ __global__ __launch_bounds__(kMeasureThreads) void gather_partials(const typenam
     }
 }
 
+constexpr int kFinalThreads = 1024;
+constexpr int kFinalUnroll = 8;  // partial loads in flight per thread
+
 // Sample m (counted from the device counter mdev when given: graph replays)
 // goes to bin (m [+ *mdev]) / bin_size of the block's charge set.
-__global__ __launch_bounds__(kMeasureThreads) void finalize_measure(const double* __restrict__ partials,
-                                                                    uint32_t blocks, double* bins, uint32_t m,
-                                                                    uint32_t bin_size,
-                                                                    const uint32_t* __restrict__ mdev,
-                                                                    double* last_xy, uint32_t bin_stride) {
+__global__ __launch_bounds__(kFinalThreads) void finalize_measure(const double* __restrict__ partials,
+                                                                  uint32_t blocks, double* bins, uint32_t m,
+                                                                  uint32_t bin_size,
+                                                                  const uint32_t* __restrict__ mdev,
+                                                                  double* last_xy, uint32_t bin_stride) {
     const uint32_t bin = (m + (mdev ? mdev[0] : 0u)) / bin_size;
     const uint32_t set = blockIdx.x;
-    partials += 2 * (size_t)set * blocks;
+    const double2* p = reinterpret_cast<const double2*>(partials + 2 * (size_t)set * blocks);
     bins += 2 * (size_t)set * bin_stride;
-    double X = 0.0, Y = 0.0;
-    for (uint32_t b = threadIdx.x; b < blocks; b += kMeasureThreads) {
-        X += partials[2 * b];
-        Y += partials[2 * b + 1];
+    // kFinalUnroll independent chains per thread, summed in a fixed order
+    double xs[kFinalUnroll], ys[kFinalUnroll];
+#pragma unroll
+    for (int u = 0; u < kFinalUnroll; ++u) xs[u] = ys[u] = 0.0;
+    for (uint32_t b0 = 0; b0 < blocks; b0 += kFinalThreads * kFinalUnroll) {
+        double2 v[kFinalUnroll];
+#pragma unroll
+        for (int u = 0; u < kFinalUnroll; ++u)  // unconditional loads (clamped index), all in flight
+            v[u] = p[min(b0 + (uint32_t)u * kFinalThreads + threadIdx.x, blocks - 1u)];
+#pragma unroll
+        for (int u = 0; u < kFinalUnroll; ++u)
+            if (b0 + (uint32_t)u * kFinalThreads + threadIdx.x < blocks) {
+                xs[u] += v[u].x;
+                ys[u] += v[u].y;
+            }
     }
-    block_sum2<kMeasureThreads>(X, Y);
+    double X = 0.0, Y = 0.0;
+#pragma unroll
+    for (int u = 0; u < kFinalUnroll; ++u) {
+        X += xs[u];
+        Y += ys[u];
+    }
+    block_sum2<kFinalThreads>(X, Y);
     if (threadIdx.x == 0) {
         const double O = X * X - Y;
         // Kahan: bins[2b] running sum, bins[2b+1] compensation (lost low part, negated)
@@ -115,7 +135,7 @@ __global__ __launch_bounds__(kMeasureThreads) void finalize_measure(const double
 hipError_t launch_finalize_measure(const double* partials, uint32_t blocks, uint32_t n_sets, double* bins,
                                    uint32_t m, uint32_t bin_size, const uint32_t* mdev, double* last_xy,
                                    uint32_t bin_stride, hipStream_t stream) {
-    hipLaunchKernelGGL(finalize_measure, dim3(n_sets), dim3(kMeasureThreads), 0, stream, partials, blocks, bins, m,
+    hipLaunchKernelGGL(finalize_measure, dim3(n_sets), dim3(kFinalThreads), 0, stream, partials, blocks, bins, m,
                        bin_size, mdev, last_xy, bin_stride);
     return hipGetLastError();
 }
@@ -126,7 +146,7 @@ static hipError_t launch_measure_t(const MeasureArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL(gather_partials<St>, dim3(a.blocks, a.n_sets), dim3(kMeasureThreads), 0, stream,
                        static_cast<const typename St::T*>(a.field0), static_cast<const typename St::T*>(a.field1),
                        a.vh, a.site, a.Q, a.S, a.n, a.set_off, a.partials);
-    hipLaunchKernelGGL(finalize_measure, dim3(a.n_sets), dim3(kMeasureThreads), 0, stream, a.partials, a.blocks,
+    hipLaunchKernelGGL(finalize_measure, dim3(a.n_sets), dim3(kFinalThreads), 0, stream, a.partials, a.blocks,
                        a.bins, a.m, a.bin_size, a.mdev, a.last_xy, a.bin_stride);
     return hipGetLastError();
 }

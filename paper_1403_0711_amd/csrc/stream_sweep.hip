@@ -30,9 +30,26 @@
 // tiles) are masked off and never write: the ring is zeroed once, so they
 // read 0, the Dirichlet ghost.  The plane past the last (z = lz) is zeroed
 // by the producer with LDS stores.
+//
+// Fused sample gather (g_key set): X = sum Q phi and Y = sum S phi^2 of a
+// sample split by colour.  The sites of the colour that a launch does not
+// update are final in the ring: the colour-1 half-sweep of a measured sweep
+// gathers the charged colour-0 sites, the colour-0 half-sweep of the next
+// sweep the charged colour-1 sites (whose values of the measured sweep it
+// holds in its ring), so no value is read from memory twice or recomputed.
+// The producer wave walks its tile's list (sorted by plane) plane by plane,
+// idle between its loads, and writes one (X, Y) partial per tile.  The
+// list (j, Q, S) is staged into dynamic LDS by the same direct loads, issued
+// before the first plane's: the waits of the ring cover them, and the walk
+// touches only LDS, so it never waits on the plane loads in flight.  The
+// colour-1 part of a run's last sample, with no next sweep, comes from
+// gather_tail, which takes the same walk over the field in memory: every
+// partial is the same whichever kernel wrote it.
 
 #include "device_common.hpp"
 #include "kernels.hpp"
+
+#include <type_traits>
 
 namespace latcoul {
 
@@ -83,6 +100,75 @@ __device__ __forceinline__ void lds_load_b32(__amdgpu_buffer_rsrc_t r, lds_ptr_t
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 4, voff, soff, 0, 0);
 }
 
+// LDS reads of the producer wave.  The compiler makes any LDS access that
+// follows a direct buffer-to-LDS load wait until all of them have landed
+// (vmcnt 0), which would drain the plane ring at every step; these reads
+// wait only for themselves (lgkmcnt 0), inside the asm statement that issues
+// them, so no output register is left pending.  Addresses are LDS byte
+// addresses.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) { return (uint32_t)(size_t)(lds_ptr_t)p; }
+
+__device__ __forceinline__ uint32_t lds_read_u32(uint32_t a) {
+    uint32_t r;
+    asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(r) : "v"(a) : "memory");
+    return r;
+}
+// two doubles at a and b
+__device__ __forceinline__ void lds_read_2f64(uint32_t a, uint32_t b, double& x, double& y) {
+    u32x2 u, v;
+    asm volatile("ds_read_b64 %0, %2\n\tds_read_b64 %1, %3\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(u), "=&v"(v)
+                 : "v"(a), "v"(b)
+                 : "memory");
+    x = __builtin_bit_cast(double, u);
+    y = __builtin_bit_cast(double, v);
+}
+
+// One value of the storage format at an LDS address, as FP32.
+template <class St>
+__device__ __forceinline__ float lds_read_value(uint32_t a) {
+    if constexpr (St::kBytes == 4) {
+        return __uint_as_float(lds_read_u32(a));
+    } else {
+        uint32_t r;
+        asm volatile("ds_read_u16 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(r) : "v"(a) : "memory");
+        if constexpr (std::is_same<St, StoreBF16>::value)
+            return __uint_as_float(r << 16);
+        else
+            return (float)__builtin_bit_cast(_Float16, (uint16_t)r);
+    }
+}
+
+// The fused gather's walk over plane z of one tile's list (entries sorted
+// by plane, gcur the first not yet taken): batches of up to 64 consecutive
+// entries, entry gcur + lane to lane, until the next entry lies beyond z.
+// key_at(i) is entry i's site j, qs_at(i) its (Q, S), value_at(j) the
+// site's value.  The streaming kernel and gather_tail share it, so each
+// lane adds the same terms in the same order in both.
+template <class KeyAt, class QSAt, class ValueAt>
+__device__ __forceinline__ void gather_walk_plane(uint32_t z, uint32_t lane, uint32_t& gcur, uint32_t ng,
+                                                  uint32_t plane, KeyAt key_at, QSAt qs_at, ValueAt value_at,
+                                                  double& gx, double& gy) {
+    while (gcur < ng) {  // wave-uniform
+        const uint32_t i = gcur + lane;
+        const uint32_t j = i < ng ? key_at(i) : 0u;
+        const bool here = i < ng && j / plane == z;
+        const uint64_t mask = __builtin_amdgcn_ballot_w64(here);
+        if (mask == 0) break;
+        if (here) {
+            const double d = (double)value_at(j);
+            double Qi, Si;
+            qs_at(i, Qi, Si);
+            gx = fma(Qi, d, gx);
+            gy = fma(Si, d * d, gy);
+        }
+        gcur += (uint32_t)__builtin_popcountll(mask);
+    }
+}
+
 // s_waitcnt immediates (gfx9 encoding): vmcnt in bits 3:0 and 15:14, expcnt
 // 6:4, lgkmcnt 11:8; a field at its maximum does not wait.
 template <int kVm>
@@ -105,10 +191,14 @@ template <class St, int kM, int kTY, int kRing, bool kNT>
 __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsweep_stream(
     const typename St::T* __restrict__ other, typename St::T* __restrict__ own, uint32_t lh, uint32_t ly,
     uint32_t lz, uint32_t zc, uint32_t c, uint32_t h, uint32_t k0, uint32_t k1, uint32_t chain,
-    uint32_t xcd_order, const uint32_t* __restrict__ tdev) {
+    uint32_t xcd_order, const uint32_t* __restrict__ tdev, const uint32_t* __restrict__ g_off,
+    const uint32_t* __restrict__ g_key, const double* __restrict__ g_Q, const double* __restrict__ g_S,
+    double* __restrict__ g_part, uint32_t g_n, uint32_t g_cap) {
     using S = Stream<St, kM, kTY, kRing>;
     using T = typename St::T;
     __shared__ __align__(16) unsigned char ring[S::kRing * S::kSlot];
+    // fused gather: the tile's keys, then Q, then S (g_cap entries each)
+    extern __shared__ __align__(16) unsigned char stage[];
     if (tdev) h += 2u * tdev[0];
 
     const uint32_t nq = lh >> 2;
@@ -123,6 +213,10 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
     const uint32_t z1 = min(z0 + zc, lz);
     const uint32_t n = z1 - z0;  // planes this workgroup updates (>= 1)
     const uint32_t plane = ly * lh, plane_b = plane * S::kEsz;
+    // fused gather: this tile's list, requested before the ring is cleared
+    // so that its latency overlaps the clearing
+    const uint32_t tile = bx + nbx * (by + nby * bz);
+    const uint32_t gbase = g_key ? g_off[tile] : 0u, ng = g_key ? g_off[tile + 1] - gbase : 0u;  // ng <= g_cap
 
     for (uint32_t i = threadIdx.x; i < S::kRing * S::kSlot / 16; i += S::kThreads)
         reinterpret_cast<uint4*>(ring)[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -185,13 +279,58 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
                 default: wait_vm_lgkm0<(S::kRing >= 7 ? 3 : 0) * S::kNI>(); break;
             }
         };
+        // fused gather: this tile's charged sites of the other colour, sorted
+        // by plane, staged into LDS before the first plane is requested
+        const bool gather = g_key != nullptr;
+        uint32_t gcur = 0;
+        double gx = 0.0, gy = 0.0;
+        const uint32_t a_key = lds_addr(stage), a_Q = a_key + 4u * g_cap, a_S = a_key + 12u * g_cap;
+        const uint32_t a_ring = lds_addr(ring);
+        if (gather) {
+            const __amdgpu_buffer_rsrc_t rk = make_rsrc(g_key, 4u * g_n);
+            const __amdgpu_buffer_rsrc_t rq = make_rsrc(g_Q, 8u * g_n);
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(g_S, 8u * g_n);
+            for (uint32_t i = 0; 64u * i < ng; ++i)  // 64 keys per instruction
+                if (64u * i + lane < ng)
+                    lds_load_b32(rk, (lds_ptr_t)(stage + 256u * i), 4u * (64u * i + lane), 4u * gbase);
+            for (uint32_t i = 0; 32u * i < ng; ++i)  // 32 doubles per instruction
+                if (64u * i + lane < 2u * ng) {
+                    lds_load_b32(rq, (lds_ptr_t)(stage + 4u * g_cap + 256u * i), 4u * (64u * i + lane), 8u * gbase);
+                    lds_load_b32(rs, (lds_ptr_t)(stage + 12u * g_cap + 256u * i), 4u * (64u * i + lane),
+                                 8u * gbase);
+                }
+        }
+        // plane z0 + s, in ring slot s + 1 (landed, as has the staged list,
+        // loaded before it)
+        auto gather_plane = [&](uint32_t s) {
+            const uint32_t slot = a_ring + ((s + 1u) % S::kRing) * S::kSlot;
+            gather_walk_plane(
+                z0 + s, lane, gcur, ng, plane, [&](uint32_t i) { return lds_read_u32(a_key + 4u * i); },
+                [&](uint32_t i, double& Qi, double& Si) { lds_read_2f64(a_Q + 8u * i, a_S + 8u * i, Qi, Si); },
+                [&](uint32_t j) {
+                    const uint32_t rem = j % plane, yy = rem / lh, jx = rem - yy * lh;
+                    return lds_read_value<St>(slot + (yy - y0 + 1u) * S::kRB + (jx - 4u * q0 + 4u) * S::kEsz);
+                },
+                gx, gy);
+        };
         for (uint32_t l = 0; l + 1u < (uint32_t)S::kRing; ++l) produce(l);  // planes l = 0 .. R-2
         wait_landed(3u, S::kRing - 2u);
         producer_barrier();  // b_0
-        for (uint32_t s = 0; s + 1u < n; ++s) {
-            produce(s + S::kRing - 1u);
-            wait_landed(s + 4u, s + S::kRing - 1u);
-            producer_barrier();  // b_{s+1}
+        for (uint32_t s = 0; s < n; ++s) {
+            if (s + 1u < n) produce(s + S::kRing - 1u);
+            if (gather) gather_plane(s);
+            if (s + 1u < n) {
+                wait_landed(s + 4u, s + S::kRing - 1u);
+                producer_barrier();  // b_{s+1}
+            }
+        }
+        if (gather) {
+            gx = wave_sum(gx);
+            gy = wave_sum(gy);
+            if (lane == 0) {
+                g_part[2 * tile] = gx;
+                g_part[2 * tile + 1] = gy;
+            }
         }
     } else {
         // ---------------- compute waves ----------------
@@ -226,17 +365,19 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
     }
 }
 
-// Tile 0: 8 rows (4 compute waves + producer, 27 KB LDS at FP32); tile 1:
-// 16 rows (8 + 1 waves, 49 KB).  Requires lh % 4 == 0 and the other colour's
-// array below 2 GiB (32-bit byte offsets).
+// One configuration: grid of tiles x slabs, dynamic LDS for a staged gather
+// list.  Requires lh % 4 == 0 and the other colour's array below 2 GiB
+// (32-bit byte offsets).
 template <class St, int kM, int kTY, int kRing, bool kNT>
 static void launch_stream_cfg(const SweepArgs& a, const typename St::T* other, typename St::T* own,
                               uint32_t zc, hipStream_t stream) {
     using S = Stream<St, kM, kTY, kRing>;
     const uint32_t nq = a.lh >> 2;
     const uint32_t nb = ((nq + S::kTX - 1) / S::kTX) * ((a.ly + kTY - 1) / kTY) * ((a.lz + zc - 1) / zc);
-    hipLaunchKernelGGL((halfsweep_stream<St, kM, kTY, kRing, kNT>), dim3(nb), dim3(S::kThreads), 0, stream, other,
-                       own, a.lh, a.ly, a.lz, zc, a.c, a.h, a.k0, a.k1, a.chain, a.xcd_order, a.tdev);
+    const uint32_t dyn = a.g_key ? kGatherEntryBytes * a.g_cap : 0u;
+    hipLaunchKernelGGL((halfsweep_stream<St, kM, kTY, kRing, kNT>), dim3(nb), dim3(S::kThreads), dyn, stream, other,
+                       own, a.lh, a.ly, a.lz, zc, a.c, a.h, a.k0, a.k1, a.chain, a.xcd_order, a.tdev, a.g_off,
+                       a.g_key, a.g_Q, a.g_S, a.g_part, a.g_n, a.g_cap);
 }
 
 // Tile configurations: tile width 32m quads, rows, ring slots, non-temporal
@@ -261,8 +402,31 @@ static hipError_t launch_stream_t(const SweepArgs& a, const typename St::T* othe
     return hipGetLastError();
 }
 
+// Shape of each configuration: the layout of the per-tile charge lists of
+// the fused gather and the LDS budget of their staging.
+bool stream_tile_geometry(uint32_t tile, uint32_t esz, StreamTileShape* out) {
+    static const uint32_t kShape[kStreamTiles][3] = {{32, 8, 6},  {32, 8, 5}, {32, 16, 5}, {32, 8, 6}, {64, 4, 5},
+                                                     {64, 8, 5},  {96, 4, 5}, {96, 4, 6},  {128, 4, 5}, {96, 4, 5}};
+    if (tile >= (uint32_t)kStreamTiles || (esz != 4 && esz != 2)) return false;
+    const uint32_t q = kShape[tile][0], rows = kShape[tile][1], slots = kShape[tile][2];
+    out->quads = q;
+    out->rows = rows;
+    out->lds = slots * (rows + 2u) * (q + 2u) * 4u * esz;
+    out->waves = q * rows / 64u + 1u;
+    return true;
+}
+
 hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream) {
     if (a.lh % 4 != 0) return hipErrorInvalidValue;
+    if (a.g_key && (!a.g_off || !a.g_Q || !a.g_S || !a.g_part || a.g_cap % 64u != 0 ||
+                    (uint64_t)a.g_n * 8u >= (1ull << 32)))
+        return hipErrorInvalidValue;
+    if (a.g_key) {
+        StreamTileShape sh;
+        if (!stream_tile_geometry(a.tile, a.storage == 0 ? 4u : 2u, &sh) ||
+            sh.lds + (uint64_t)kGatherEntryBytes * a.g_cap > 65536u)
+            return hipErrorInvalidValue;
+    }
     const uint32_t esz = a.storage == 0 ? 4u : 2u;
     if ((uint64_t)a.vh * esz >= (1ull << 31)) return hipErrorInvalidValue;
     switch (a.storage) {
@@ -280,6 +444,66 @@ hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream) {
         }
         default: return hipErrorInvalidValue;
     }
+}
+
+// The colour-1 part of a sample from the field in memory (a run's last
+// sample): one wave per tile, the streaming kernel's walk over the same
+// per-tile list, partial per tile.
+template <class St>
+__global__ __launch_bounds__(64) void gather_tail(const typename St::T* __restrict__ f, uint32_t lh, uint32_t ly,
+                                                 uint32_t lz, uint32_t zc, uint32_t tq, uint32_t ty,
+                                                 const uint32_t* __restrict__ g_off, const uint32_t* __restrict__ g_key,
+                                                 const double* __restrict__ g_Q, const double* __restrict__ g_S,
+                                                 double* __restrict__ g_part) {
+    const uint32_t nq = lh >> 2, nbx = (nq + tq - 1) / tq, nby = (ly + ty - 1) / ty;
+    const uint32_t tile = blockIdx.x, lane = threadIdx.x;
+    const uint32_t z0 = (tile / (nbx * nby)) * zc, n = min(z0 + zc, lz) - z0;
+    const uint32_t plane = ly * lh, gbase = g_off[tile], ng = g_off[tile + 1] - gbase;
+    uint32_t gcur = 0;
+    double gx = 0.0, gy = 0.0;
+    for (uint32_t s = 0; s < n; ++s)
+        gather_walk_plane(
+            z0 + s, lane, gcur, ng, plane, [&](uint32_t i) { return g_key[gbase + i]; },
+            [&](uint32_t i, double& Qi, double& Si) {
+                Qi = g_Q[gbase + i];
+                Si = g_S[gbase + i];
+            },
+            [&](uint32_t j) { return St::ld(f, j); }, gx, gy);
+    gx = wave_sum(gx);
+    gy = wave_sum(gy);
+    if (lane == 0) {
+        g_part[2 * tile] = gx;
+        g_part[2 * tile + 1] = gy;
+    }
+}
+
+hipError_t launch_gather_tail(const GatherTailArgs& a, hipStream_t stream) {
+    StreamTileShape sh;
+    if (a.lh % 4 != 0 || !a.field1 || !a.g_off || !a.g_key || !a.g_Q || !a.g_S || !a.g_part ||
+        !stream_tile_geometry(a.tile, a.storage == 0 ? 4u : 2u, &sh))
+        return hipErrorInvalidValue;
+    const uint32_t zc = a.zc ? a.zc : 16u, nq = a.lh / 4;
+    const uint32_t tiles =
+        ((nq + sh.quads - 1) / sh.quads) * ((a.ly + sh.rows - 1) / sh.rows) * ((a.lz + zc - 1) / zc);
+    switch (a.storage) {
+        case 0:
+            hipLaunchKernelGGL(gather_tail<StoreF32>, dim3(tiles), dim3(64), 0, stream,
+                               static_cast<const float*>(a.field1), a.lh, a.ly, a.lz, zc, sh.quads, sh.rows, a.g_off,
+                               a.g_key, a.g_Q, a.g_S, a.g_part);
+            break;
+        case 1:
+            hipLaunchKernelGGL(gather_tail<StoreBF16>, dim3(tiles), dim3(64), 0, stream,
+                               static_cast<const uint16_t*>(a.field1), a.lh, a.ly, a.lz, zc, sh.quads, sh.rows,
+                               a.g_off, a.g_key, a.g_Q, a.g_S, a.g_part);
+            break;
+        case 2:
+            hipLaunchKernelGGL(gather_tail<StoreF16>, dim3(tiles), dim3(64), 0, stream,
+                               static_cast<const _Float16*>(a.field1), a.lh, a.ly, a.lz, zc, sh.quads, sh.rows,
+                               a.g_off, a.g_key, a.g_Q, a.g_S, a.g_part);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace latcoul

@@ -80,6 +80,7 @@ def load_library() -> ctypes.CDLL:
         "lattice_set_tuning": (_int, [_p, _i64, _int, _int]),
         "lattice_use_graphs": (_int, [_p, _int]),
         "lattice_get_tuning": (_int, [_p, ctypes.POINTER(_int), _pi64, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
+        "lattice_get_sample_path": (_int, [_p, ctypes.POINTER(_int)]),
         "lattice_autotune": (_int, [_p, _i64, ctypes.POINTER(_int), _pi64, ctypes.POINTER(_int),
                                     ctypes.POINTER(_int), _pd]),
         "lattice_get_field": (_int, [_p, _p]),
@@ -294,6 +295,13 @@ class Lattice:
         names = {val: key for key, val in VARIANT.items()}
         return {"variant": names.get(v.value, v.value), "planes": pl.value, "tile": t.value,
                 "xcd_order": bool(x.value)}
+
+    def sample_path(self) -> str:
+        """How the samples of the last sweep_and_measure were gathered:
+        "fused" (inside the streaming sweep kernel) or "separate"."""
+        f = ctypes.c_int()
+        self._call(self.lib.lattice_get_sample_path, ctypes.byref(f))
+        return "fused" if f.value else "separate"
 
     def autotune(self, reps: int = 5) -> dict:
         """Time the sweep kernels on scratch memory and keep the fastest."""

@@ -1,0 +1,224 @@
+"""The sample gather fused into the streaming sweep kernel: the loader wave
+of each workgroup sums X = sum Q phi and Y = sum S phi^2 over the charged
+sites of its tile whose values are final in its plane ring (the colour-0
+sites in the colour-1 half-sweep of a measured sweep, the colour-1 sites in
+the colour-0 half-sweep of the next sweep; a run's last sample takes its
+colour-1 sites from a tail kernel with the same per-tile walk).  Checked
+against the separate gather kernel on the same chain (bit-identical fields,
+samples equal up to the order of the FP64 sums), the oracle's gather of the
+read-back field, graph replays (bit-identical to launch-by-launch runs),
+tiling changes between runs, 16-bit storage, measure_every > 1, the
+full-size box, and the cases that keep the separate gather."""
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lat_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1403_0711_amd import lattice
+
+    lattice.load_library()
+    return lattice
+
+
+def _charges(shape, n, seed):
+    """Random sites of both colours, every box corner, the first and last
+    site of each edge row, and co-located duplicates; charges N(0, 1)."""
+    lx, ly, lz = shape
+    rng = np.random.default_rng(seed)
+    xyz = np.stack([rng.integers(0, lx, n), rng.integers(0, ly, n), rng.integers(0, lz, n)], axis=1)
+    corners = np.array([(a, b, c) for a in (0, lx - 1) for b in (0, ly - 1) for c in (0, lz - 1)])
+    rows = np.array([(a, ly // 2, lz // 2) for a in (0, 1, lx - 2, lx - 1)])
+    xyz = np.concatenate([xyz, corners, rows, xyz[:7]])
+    q = rng.standard_normal(len(xyz))
+    return xyz.astype(np.int32), q
+
+
+def _scale(q, phi):
+    return float(np.sum(np.abs(q)) ** 2 * max(1.0, np.abs(phi).max()) ** 2)
+
+
+def _pair(lat_mod, shape, storage, slab, tile, xcd, xyz, q, seed=3, chain=5):
+    a = lat_mod.Lattice(shape, storage, seed=seed, chain_id=chain)
+    a.set_variant("stream")
+    a.set_tuning(slab, tile, xcd)
+    b = lat_mod.Lattice(shape, storage, seed=seed, chain_id=chain)
+    b.set_variant("zslab")
+    for lat in (a, b):
+        lat.set_charges(xyz, q)
+    return a, b
+
+
+# FP32 tiles whose plane ring leaves LDS for a (short) staged list without
+# losing a resident workgroup per CU; the others keep the separate gather
+FP32_FUSING_TILES = (2, 5, 6, 7, 8, 9)
+
+CASES = [
+    ((64, 24, 20), "fp32", 0, 9, True),
+    ((64, 24, 20), "fp32", 7, 2, False),
+    ((64, 24, 20), "fp16", 0, 0, True),
+    ((64, 24, 20), "bf16", 5, 4, False),
+    ((200, 37, 33), "fp32", 16, 9, True),     # 50 quads per row: a partial 96-quad tile, ragged rows and slab
+    ((264, 17, 19), "fp32", 7, 6, True),
+    ((136, 13, 7), "fp16", 7, 8, False),     # one slab, 17 quads per row of a 128-quad tile
+    ((72, 9, 40), "bf16", 16, 2, True),      # 16-row tiles over 9 rows
+    ((520, 12, 5), "fp32", 0, 5, True),      # short lists: a 64-entry LDS stage keeps 3 workgroups per CU
+    ((8, 1, 3), "fp32", 0, 2, True),         # one row per plane, one quad per row
+]
+
+
+@pytest.mark.parametrize("shape,storage,slab,tile,xcd", CASES)
+def test_fused_gather_matches_separate_and_oracle(lat_mod, shape, storage, slab, tile, xcd):
+    print(f"[gpu] fused gather {shape} {storage} slab={slab} tile={tile} xcd={xcd}", flush=True)
+    xyz, q = _charges(shape, 60 if tile == 5 else 300, 11)
+    a, b = _pair(lat_mod, shape, storage, slab, tile, xcd, xyz, q)
+    for lat in (a, b):
+        lat.thermalise(5)
+        lat.sweep_and_measure(40, 1, 1)
+    fused = storage != "fp32" or tile in FP32_FUSING_TILES
+    assert a.sample_path() == ("fused" if fused else "separate") and b.sample_path() == "separate"
+    fa, fb = a.get_field(), b.get_field()
+    np.testing.assert_array_equal(fa, fb)
+    sa, sb = a.get_state(), b.get_state()
+    assert sa[:2] == sb[:2] == (45, 40)
+    tol = 1e-12 * _scale(q, fa)
+    assert np.abs(sa[2] - sb[2]).max() <= tol
+    # the last sample against the oracle's gather of the read-back field
+    ref = oracle.OracleChain(shape)
+    ref.phi = fa.astype(np.float64)
+    ref.set_charges(xyz, q)
+    X, Y = ref.gather()
+    Xa, Ya = a.last_measure()
+    assert abs(Xa - X) <= 1e-12 * max(1.0, np.sum(np.abs(q)) * np.abs(fa).max())
+    assert abs(Ya - Y) <= tol
+
+
+def test_fused_gather_graphs_and_retiling(lat_mod):
+    """Graph replays of fused sweeps are bit-identical to launch-by-launch
+    runs; changing the tile or slab between runs rebuilds the per-tile lists
+    and the samples stay those of the separate gather."""
+    print("[gpu] fused gather graphs + retiling", flush=True)
+    shape = (64, 24, 20)
+    xyz, q = _charges(shape, 150, 4)
+    lats = []
+    for mode in (0, 2):
+        lat = lat_mod.Lattice(shape, seed=21, chain_id=2)
+        lat.set_variant("stream")
+        lat.use_graphs(mode)
+        lat.set_charges(xyz, q)
+        lats.append(lat)
+    sep = lat_mod.Lattice(shape, seed=21, chain_id=2)
+    sep.set_variant("zslab")
+    sep.set_charges(xyz, q)
+    tunings = [(0, 9, True), (7, 5, False), (3, 0, True), (20, 2, True), (5, 8, False)]
+    for step, (slab, tile, xcd) in enumerate(tunings):
+        for lat in lats:
+            lat.set_tuning(slab, tile, xcd)
+            lat.thermalise(70)
+            lat.sweep_and_measure(96, 3, 8)
+            assert lat.sample_path() == ("fused" if tile in FP32_FUSING_TILES else "separate")
+        sep.thermalise(70)
+        sep.sweep_and_measure(96, 3, 8)
+        s0, s1, s2 = lats[0].get_state(), lats[1].get_state(), sep.get_state()
+        assert s0[0] == s1[0] == s2[0] == 166 * (step + 1)
+        np.testing.assert_array_equal(s0[2], s1[2])
+        np.testing.assert_array_equal(lats[0].get_field(), lats[1].get_field())
+        np.testing.assert_array_equal(lats[0].get_field(), sep.get_field())
+        assert np.abs(s0[2] - s2[2]).max() <= 1e-12 * _scale(q, sep.get_field()) * 8
+        assert lats[0].last_measure() == lats[1].last_measure()
+    # samples every 5th sweep with 2 unmeasured sweeps at the end (the next
+    # sweep, not the tail kernel, completes the last sample), then every sweep
+    for n, every in ((37, 5), (3, 1), (64, 1)):
+        for lat in lats + [sep]:
+            lat.sweep_and_measure(n, every, 8)
+        s0, s1, s2 = lats[0].get_state(), lats[1].get_state(), sep.get_state()
+        assert s0[1] == s1[1] == s2[1]
+        np.testing.assert_array_equal(s0[2], s1[2])
+        assert np.abs(s0[2] - s2[2]).max() <= 1e-12 * _scale(q, sep.get_field()) * 8
+        assert lats[0].last_measure() == lats[1].last_measure()
+        X2, Y2 = sep.last_measure()
+        assert abs(lats[0].last_measure()[1] - Y2) <= 1e-12 * max(1.0, abs(Y2))
+
+
+def test_fused_gather_new_charges_and_fallbacks(lat_mod):
+    """New charges rebuild the lists; several charge sets, off-lattice
+    charges and the other kernels keep the separate gather; an empty charge
+    list gives zero samples."""
+    print("[gpu] fused gather fallbacks", flush=True)
+    shape = (64, 24, 20)
+    x1, q1 = _charges(shape, 50, 1)
+    x2, q2 = _charges(shape, 80, 2)
+    a, b = _pair(lat_mod, shape, "fp32", 0, 9, True, x1, q1)
+    for xyz, q in ((x1, q1), (x2, q2)):
+        for lat in (a, b):
+            lat.set_charges(xyz, q)
+            lat.sweep_and_measure(12, 2, 2)
+        assert a.sample_path() == "fused"
+        sa, sb = a.get_state(), b.get_state()
+        assert np.abs(sa[2] - sb[2]).max() <= 2e-12 * _scale(q, a.get_field())
+    a.set_charge_sets([(x1, q1), (x2, q2)])
+    a.sweep_and_measure(4, 1, 1)
+    assert a.sample_path() == "separate"
+    a.set_offlattice_charges(x1.astype(np.float64) * 0.5, q1)
+    a.sweep_and_measure(4, 1, 1)
+    assert a.sample_path() == "separate"
+    a.set_charges(x1, q1)
+    a.set_variant("quad")
+    a.sweep_and_measure(4, 1, 1)
+    assert a.sample_path() == "separate"
+    a.set_variant("stream")
+    a.sweep_and_measure(4, 1, 1)
+    assert a.sample_path() == "fused"
+    e = lat_mod.Lattice(shape, seed=1)
+    e.set_variant("stream")
+    e.set_tuning(0, 0, True)  # a tile that fuses only an empty list at FP32
+    e.set_charges(np.zeros((0, 3), np.int32), np.zeros(0))
+    e.sweep_and_measure(6, 1, 2)
+    assert e.sample_path() == "fused"
+    _, n, bins = e.get_state()
+    assert n == 6 and np.all(bins == 0.0)
+    e.set_charges(x1, q1)
+    e.sweep_and_measure(2, 1, 2)
+    assert e.sample_path() == "separate"
+
+
+def test_fused_gather_full_size(lat_mod):
+    """768^3 in the configuration the benchmark times (library default
+    kernel and tiling) with its charge workload: fused samples against the
+    separate gather on the same chain."""
+    print("[gpu] fused gather 768^3", flush=True)
+    from paper_1403_0711_amd import workloads
+
+    c = workloads.largest_subdomain()
+    shape, xyz, q = c.shape, c.xyz, c.q
+    a = lat_mod.Lattice(shape, seed=77)
+    a.set_charges(xyz, q)
+    assert a.tuning()["variant"] == "stream"
+    a.thermalise(2)
+    a.sweep_and_measure(3, 1, 1)
+    assert a.sample_path() == "fused"
+    sa = a.get_state()
+    Xa, Ya = a.last_measure()
+    a.close()
+    b = lat_mod.Lattice(shape, seed=77)
+    b.set_variant("zslab")
+    b.set_charges(xyz, q)
+    b.thermalise(2)
+    b.sweep_and_measure(3, 1, 1)
+    sb = b.get_state()
+    Xb, Yb = b.last_measure()
+    b.close()
+    # X sums ~1e6 terms of |q phi| <~ 10: FP64 order differences stay far below 1e-9
+    qa = float(np.sum(np.abs(q)))
+    assert abs(Xa - Xb) <= 1e-12 * qa * 10.0
+    assert abs(Ya - Yb) <= 1e-12 * max(abs(Yb), 1.0)
+    assert np.abs(sa[2] - sb[2]).max() <= 1e-12 * (qa * 10.0) ** 2
