@@ -314,4 +314,21 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
     __syncthreads();
 }
 
+// Record one sample (X, Y): O = X^2 - Y added to bin `bin` (bins[2b] running
+// sum, bins[2b+1] the Kahan compensation, the lost low part negated), and
+// (X, Y) kept in last_xy.  One thread.
+__device__ __forceinline__ void record_sample(double X, double Y, double* bins, uint32_t bin, double* last_xy) {
+    const double O = X * X - Y;
+    double sum = bins[2 * bin];
+    double comp = bins[2 * bin + 1];
+    const double yk = O - comp;
+    const double tk = sum + yk;
+    comp = (tk - sum) - yk;
+    sum = tk;
+    bins[2 * bin] = sum;
+    bins[2 * bin + 1] = comp;
+    last_xy[0] = X;
+    last_xy[1] = Y;
+}
+
 }  // namespace latcoul

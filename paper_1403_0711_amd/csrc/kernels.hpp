@@ -9,6 +9,18 @@ namespace latcoul {
 enum : int { kVariantQuad = 1, kVariantGeneric = 2, kVariantZslab = 3, kVariantFused = 4, kVariantStream = 6 };
 
 // One half-sweep of colour c = h & 1 on one lattice.
+// Finalize of one sample inside a sweep launch (workgroup 0, overlapped with
+// its first plane loads): the sum of n (X, Y) partial pairs at part is
+// recorded as sample m (+ *mdev) in bin (m [+ *mdev]) / bin_size.
+struct SampleFinalize {
+    const double* part = nullptr;  // null: none
+    uint32_t n = 0;
+    double* bins = nullptr;
+    uint32_t m = 0, bin_size = 1;
+    const uint32_t* mdev = nullptr;
+    double* last_xy = nullptr;
+};
+
 struct SweepArgs {
     void* field;      // 2 * vh elements: colour 0 then colour 1
     uint32_t lh, ly, lz, vh;
@@ -33,6 +45,8 @@ struct SweepArgs {
     const double* g_S = nullptr;
     double* g_part = nullptr;
     uint32_t g_n = 0, g_cap = 0;
+    // streaming kernel: finalize of the previous sample (see SampleFinalize)
+    SampleFinalize fin;
 };
 constexpr uint32_t kGatherEntryBytes = 20;  // staged key (4 B), Q and S (8 B each)
 constexpr int kZslabTiles = 8;

@@ -68,7 +68,8 @@ struct lattice {
     // fused gather of the streaming kernel: the list split by colour and
     // regrouped per tile and by plane, for one tile shape and slab (d_off:
     // the colour-0 then the colour-1 offset tables, tiles + 1 each, into
-    // d_key / d_Q / d_S; d_part: the colour-0 then the colour-1 partials)
+    // d_key / d_Q / d_S; d_part: two buffers, by sample parity, each the
+    // colour-0 then the colour-1 partials of one sample, 2 x tiles pairs)
     struct FusedGather {
         bool ready = false;
         bool tried = false;  // lists considered for (tile, slab): ready, or the separate gather
@@ -82,9 +83,10 @@ struct lattice {
         double* d_part = nullptr;
     } fg;
     // How the fused gather takes part in one sweep: its colour-0 launch
-    // completes the open sample (its colour-1 sites) and finalizes it as
-    // sample m (on the device counter mdev when captured); its colour-1
-    // launch opens this sweep's sample (its colour-0 sites).
+    // completes the open sample m (its colour-1 sites), which workgroup 0 of
+    // the colour-1 launch records (sample m + *mdev when captured); the
+    // colour-1 launch opens this sweep's sample m + 1 (its colour-0 sites;
+    // m is the last sample number, modulo 2^32, when none is open).
     struct FusedStep {
         bool finish = false, open = false;
         uint32_t m = 0;
@@ -248,7 +250,7 @@ static int fused_gather_prepare(lattice* L) {
     g.d_key = static_cast<uint32_t*>(L->mem.alloc(std::max<size_t>(n, 1) * 4));
     g.d_Q = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
     g.d_S = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
-    g.d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * 32));
+    g.d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * 64));
     L->fg = g;  // released by fused_gather_release on any failure below
     if (!g.d_off || !g.d_key || !g.d_Q || !g.d_S || !g.d_part) {
         fused_gather_release(L);
@@ -299,27 +301,35 @@ static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev
                     (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, kv, L->slab,
                     L->xcd_order, L->resolved_tile(v), tdev};
         const lattice::FusedGather& g = L->fg;
-        auto gather_lists = [&](uint32_t colour) {  // gather the charged sites of `colour`
+        // sample k's partials: buffer k & 1, the colour-0 then the colour-1 pairs
+        auto part = [&](uint32_t k, uint32_t colour) { return g.d_part + ((size_t)(k & 1u) * 2 + colour) * 2 * g.blocks; };
+        auto gather_lists = [&](uint32_t colour, uint32_t k) {  // gather the charged sites of `colour` for sample k
             a.g_off = g.d_off + (size_t)colour * (g.blocks + 1);
             a.g_key = g.d_key;
             a.g_Q = g.d_Q;
             a.g_S = g.d_S;
-            a.g_part = g.d_part + (size_t)colour * 2 * g.blocks;
+            a.g_part = part(k, colour);
             a.g_n = g.n;
             a.g_cap = g.cap;
         };
-        if (fs && fs->finish) gather_lists(1u);
+        if (fs && fs->finish) gather_lists(1u, fs->m);
         e = launch_halfsweep(a, stream);
-        if (e == hipSuccess && fs && fs->finish)
-            e = launch_finalize_measure(g.d_part, 2 * g.blocks, 1u, L->d_bins, fs->m, (uint32_t)L->bin_size,
-                                        fs->mdev, L->last_xy(), (uint32_t)L->bin_cap, stream);
         if (e == hipSuccess) {
             a.c = 1u;
             a.h = h0 + 1u;
             a.g_off = a.g_key = nullptr;
             a.g_Q = a.g_S = nullptr;
             a.g_part = nullptr;
-            if (fs && fs->open) gather_lists(0u);
+            if (fs && fs->finish) {
+                a.fin.part = part(fs->m, 0u);
+                a.fin.n = 2 * g.blocks;
+                a.fin.bins = L->d_bins;
+                a.fin.m = fs->m;
+                a.fin.bin_size = (uint32_t)L->bin_size;
+                a.fin.mdev = fs->mdev;
+                a.fin.last_xy = L->last_xy();
+            }
+            if (fs && fs->open) gather_lists(0u, fs->m + 1u);  // the next sample
             e = launch_halfsweep(a, stream);
         }
     }
@@ -337,11 +347,12 @@ static int enqueue_sweep(lattice* L, const lattice::FusedStep* fs = nullptr) {
 // its finalize as sample m.
 static int enqueue_fused_tail(lattice* L, hipStream_t stream, uint32_t m, const uint32_t* mdev) {
     const lattice::FusedGather& g = L->fg;
+    double* buf = g.d_part + (size_t)(m & 1u) * 4 * g.blocks;  // sample m's partials, colour 0 then 1
     GatherTailArgs a{L->c1cur(), L->storage, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->slab, g.tile,
-                     g.d_off + g.blocks + 1, g.d_key, g.d_Q, g.d_S, g.d_part + 2 * (size_t)g.blocks};
+                     g.d_off + g.blocks + 1, g.d_key, g.d_Q, g.d_S, buf + 2 * (size_t)g.blocks};
     hipError_t e = launch_gather_tail(a, stream);
     if (e == hipSuccess)
-        e = launch_finalize_measure(g.d_part, 2 * g.blocks, 1u, L->d_bins, m, (uint32_t)L->bin_size, mdev,
+        e = launch_finalize_measure(buf, 2 * g.blocks, 1u, L->d_bins, m, (uint32_t)L->bin_size, mdev,
                                     L->last_xy(), (uint32_t)L->bin_cap, stream);
     if (e != hipSuccess) return hip_fail(e, "measure launch");
     return LAT_OK;

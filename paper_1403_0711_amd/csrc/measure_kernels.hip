@@ -116,20 +116,7 @@ __global__ __launch_bounds__(kFinalThreads) void finalize_measure(const double* 
         Y += ys[u];
     }
     block_sum2<kFinalThreads>(X, Y);
-    if (threadIdx.x == 0) {
-        const double O = X * X - Y;
-        // Kahan: bins[2b] running sum, bins[2b+1] compensation (lost low part, negated)
-        double sum = bins[2 * bin];
-        double comp = bins[2 * bin + 1];
-        const double yk = O - comp;
-        const double tk = sum + yk;
-        comp = (tk - sum) - yk;
-        sum = tk;
-        bins[2 * bin] = sum;
-        bins[2 * bin + 1] = comp;
-        last_xy[2 * set] = X;
-        last_xy[2 * set + 1] = Y;
-    }
+    if (threadIdx.x == 0) record_sample(X, Y, bins, bin, last_xy + 2 * set);
 }
 
 hipError_t launch_finalize_measure(const double* partials, uint32_t blocks, uint32_t n_sets, double* bins,

@@ -44,7 +44,10 @@
 // touches only LDS, so it never waits on the plane loads in flight.  The
 // colour-1 part of a run's last sample, with no next sweep, comes from
 // gather_tail, which takes the same walk over the field in memory: every
-// partial is the same whichever kernel wrote it.
+// partial is the same whichever kernel wrote it.  A sample completed by a
+// colour-0 launch is finalized by workgroup 0 of the colour-1 launch that
+// follows (fin set), while its first planes load; partials are kept in two
+// buffers by sample parity, so that launch may open the next sample.
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -186,6 +189,34 @@ __device__ __forceinline__ void producer_barrier() {
     asm volatile("" ::: "memory");
 }
 
+// Finalize of the previous sample by workgroup 0 of a launch: threads below
+// kLoaders (the compute waves, which issue no direct-to-LDS loads) sum the
+// partial pairs with several loads in flight each, every thread takes part in
+// the workgroup sum, thread 0 records the sample.  It runs while the
+// producer's first planes are in flight.
+template <int kThreads, int kLoaders>
+__device__ __forceinline__ void finalize_in_workgroup(const SampleFinalize& f) {
+    constexpr int kUnroll = 4;  // few registers: this code shares the kernel's register budget
+    const uint32_t t = threadIdx.x;
+    double X = 0.0, Y = 0.0;
+    if (t < (uint32_t)kLoaders) {
+        const double2* p = reinterpret_cast<const double2*>(f.part);
+        for (uint32_t b0 = 0; b0 < f.n; b0 += kLoaders * kUnroll) {
+            double2 v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) v[u] = p[min(b0 + (uint32_t)u * kLoaders + t, f.n - 1u)];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (b0 + (uint32_t)u * kLoaders + t < f.n) {
+                    X += v[u].x;
+                    Y += v[u].y;
+                }
+        }
+    }
+    block_sum2<kThreads>(X, Y);
+    if (t == 0) record_sample(X, Y, f.bins, (f.m + (f.mdev ? f.mdev[0] : 0u)) / f.bin_size, f.last_xy);
+}
+
 // kNT: non-temporal stores of the updated colour.
 template <class St, int kM, int kTY, int kRing, bool kNT>
 __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsweep_stream(
@@ -193,7 +224,7 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
     uint32_t lz, uint32_t zc, uint32_t c, uint32_t h, uint32_t k0, uint32_t k1, uint32_t chain,
     uint32_t xcd_order, const uint32_t* __restrict__ tdev, const uint32_t* __restrict__ g_off,
     const uint32_t* __restrict__ g_key, const double* __restrict__ g_Q, const double* __restrict__ g_S,
-    double* __restrict__ g_part, uint32_t g_n, uint32_t g_cap) {
+    double* __restrict__ g_part, uint32_t g_n, uint32_t g_cap, SampleFinalize fin) {
     using S = Stream<St, kM, kTY, kRing>;
     using T = typename St::T;
     __shared__ __align__(16) unsigned char ring[S::kRing * S::kSlot];
@@ -217,6 +248,7 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
     // so that its latency overlaps the clearing
     const uint32_t tile = bx + nbx * (by + nby * bz);
     const uint32_t gbase = g_key ? g_off[tile] : 0u, ng = g_key ? g_off[tile + 1] - gbase : 0u;  // ng <= g_cap
+    const bool finalize = fin.part != nullptr && blockIdx.x == 0;  // the previous sample, in the first workgroup
 
     for (uint32_t i = threadIdx.x; i < S::kRing * S::kSlot / 16; i += S::kThreads)
         reinterpret_cast<uint4*>(ring)[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -314,6 +346,7 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
                 gx, gy);
         };
         for (uint32_t l = 0; l + 1u < (uint32_t)S::kRing; ++l) produce(l);  // planes l = 0 .. R-2
+        if (finalize) finalize_in_workgroup<S::kThreads, S::kCompute>(fin);
         wait_landed(3u, S::kRing - 2u);
         producer_barrier();  // b_0
         for (uint32_t s = 0; s < n; ++s) {
@@ -340,6 +373,7 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
         const bool active = q < nq && y < ly;
         const uint32_t rowj = y * lh + 4u * q;
         const uint32_t qoff = (row + 1u) * S::kRB + (tx + 1u) * S::kQB;  // the thread's quad in a slot
+        if (finalize) finalize_in_workgroup<S::kThreads, S::kCompute>(fin);
         for (uint32_t s = 0; s < n; ++s) {
             __syncthreads();  // b_s
             if (!active) continue;
@@ -377,7 +411,7 @@ static void launch_stream_cfg(const SweepArgs& a, const typename St::T* other, t
     const uint32_t dyn = a.g_key ? kGatherEntryBytes * a.g_cap : 0u;
     hipLaunchKernelGGL((halfsweep_stream<St, kM, kTY, kRing, kNT>), dim3(nb), dim3(S::kThreads), dyn, stream, other,
                        own, a.lh, a.ly, a.lz, zc, a.c, a.h, a.k0, a.k1, a.chain, a.xcd_order, a.tdev, a.g_off,
-                       a.g_key, a.g_Q, a.g_S, a.g_part, a.g_n, a.g_cap);
+                       a.g_key, a.g_Q, a.g_S, a.g_part, a.g_n, a.g_cap, a.fin);
 }
 
 // Tile configurations: tile width 32m quads, rows, ring slots, non-temporal
@@ -420,6 +454,8 @@ hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream) {
     if (a.lh % 4 != 0) return hipErrorInvalidValue;
     if (a.g_key && (!a.g_off || !a.g_Q || !a.g_S || !a.g_part || a.g_cap % 64u != 0 ||
                     (uint64_t)a.g_n * 8u >= (1ull << 32)))
+        return hipErrorInvalidValue;
+    if (a.fin.part && (!a.fin.bins || !a.fin.last_xy || a.fin.n == 0 || a.fin.bin_size == 0))
         return hipErrorInvalidValue;
     if (a.g_key) {
         StreamTileShape sh;
