@@ -62,6 +62,8 @@ def parse():
     p.add_argument("--no-extras", action="store_true", help="skip the FP16 and batched comparisons")
     p.add_argument("--planes", type=int, default=None, help="slab kernels: planes per workgroup")
     p.add_argument("--tile", type=int, default=-1, help="slab kernels: tile configuration (-1: library default)")
+    p.add_argument("--xcd-order", type=int, default=None, choices=[0, 1],
+                   help="slab kernels: 1 XCD runs of tiles, 0 round-robin (default: the library's)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain device copy of the workload's colour-array size (counter calibration)")
     p.add_argument("--kernel-reps", type=int, default=50,
@@ -375,8 +377,8 @@ def main():
         lat.autotune(5)
     else:
         lat.set_variant(args.variant)
-        if args.planes is not None or args.tile != -1:
-            lat.set_tuning(args.planes or 0, args.tile, True)
+        if args.planes is not None or args.tile != -1 or args.xcd_order is not None:
+            lat.set_tuning(args.planes or 0, args.tile, args.xcd_order)
     tuning = lat.tuning()  # what runs: library defaults or the autotuner's choice, resolved
     variant = tuning["variant"]
     lat.set_charges(cs.xyz, cs.q)

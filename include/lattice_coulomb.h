@@ -197,18 +197,21 @@ int lattice_set_variant(lattice_t *lat, int variant);
 
 /* Tuning of the slab kernels (LAT_SWEEP_ZSLAB, LAT_SWEEP_STREAM, and the
  * planes of LAT_SWEEP_FUSED): planes of the box one workgroup walks along z
- * (0 = library default: 16 at FP32, 32 at 16-bit storage; at most lz); tile
- * configuration (-1 = library default: for LAT_SWEEP_STREAM 96-quad tiles
- * at FP32 where they divide the rows, else 32-quad tiles, with non-temporal
- * stores where a colour array is at least 256 MiB: tiles 9 / 6 / 0 / 3;
- * tile 0 for the other kernels): 0..7 for
- * LAT_SWEEP_ZSLAB (workgroup tile width x rows and register budget), 0..9
- * for LAT_SWEEP_STREAM (tile width 128..512 sites, rows, depth of the LDS
- * plane ring, non-temporal stores); whether workgroups are ordered so that
- * each of the chip's 8 XCDs gets a contiguous run of tiles.  LAT_ERR_ARG for
- * a tile the selected variant does not have (and lattice_set_variant(
- * LAT_SWEEP_STREAM) with a tile above 9).  Results do not depend on any of
- * them. */
+ * (0 = library default: 24 for the streaming kernel's full-row FP32 tile 9,
+ * else 16 at FP32 and 32 at 16-bit storage; at most lz); tile configuration
+ * (-1 = library default: for LAT_SWEEP_STREAM 96-quad tiles at FP32 where
+ * they divide the rows, else 32-quad tiles, with non-temporal stores where a
+ * colour array is at least 256 MiB: tiles 9 / 6 / 0 / 3; tile 0 for the
+ * other kernels): 0..7 for LAT_SWEEP_ZSLAB (workgroup tile width x rows and
+ * register budget), 0..9 for LAT_SWEEP_STREAM (tile width 128..512 sites,
+ * rows, depth of the LDS plane ring, non-temporal stores); xcd_order 1 if
+ * workgroups are ordered so that each of the chip's 8 XCDs gets a
+ * contiguous run of tiles, 0 for the hardware's round-robin order, -1 =
+ * library default (round-robin for the streaming kernel's tile 9 at FP32,
+ * else XCD runs).  Defaults are resolved for the kernel each sweep runs.
+ * LAT_ERR_ARG for a tile the selected variant does not have (and
+ * lattice_set_variant(LAT_SWEEP_STREAM) with a tile above 9).  Results do
+ * not depend on any of them. */
 int lattice_set_tuning(lattice_t *lat, int64_t planes, int tile, int xcd_order);
 
 /* The configuration the next sweep runs (any output may be NULL): the

@@ -35,10 +35,11 @@ struct SweepArgs {
     const uint32_t* tdev;  // if set, h += 2 * tdev[0] (sweep counter on the device)
     // streaming kernel: fused gather of the charged sites of the other
     // colour (1 - c) over per-tile lists (g_off: tiles + 1 absolute offsets;
-    // g_key: site j in that colour's array; g_Q, g_S; g_n entries in the
-    // arrays), one (X, Y) partial per tile into g_part.  g_cap: LDS entries
-    // staged per workgroup (a multiple of 64, at least the longest tile
-    // list).  Null: no gather.
+    // g_key: the site's plane within the tile's slab << 16 | its byte offset
+    // in a ring slot; g_Q, g_S; g_n entries in the arrays), one (X, Y)
+    // partial per tile into g_part.  g_cap: LDS entries staged per workgroup
+    // (a multiple of 64, at least the longest tile list, at most 256).
+    // Null: no gather.
     const uint32_t* g_off = nullptr;
     const uint32_t* g_key = nullptr;
     const double* g_Q = nullptr;
@@ -54,7 +55,8 @@ constexpr int kStreamTiles = 10;  // tile configurations of the streaming slab k
 hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream);
 hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream);  // tile 0 .. kStreamTiles-1
 // Shape of a streaming-kernel tile configuration at element size esz: quads
-// per tile row, rows, static LDS bytes (the plane ring), waves per workgroup.
+// per tile row, rows, static LDS bytes (the plane ring and the kernel's small
+// static arrays), waves per workgroup.
 struct StreamTileShape {
     uint32_t quads, rows, lds, waves;
 };
@@ -64,9 +66,9 @@ bool stream_tile_geometry(uint32_t tile, uint32_t esz, StreamTileShape* out);
 struct GatherTailArgs {
     const void* field1;  // colour-1 array
     int storage;
-    uint32_t lh, ly, lz, zc, tile;
-    const uint32_t* g_off;  // the colour-1 lists
-    const uint32_t* g_key;
+    uint32_t tiles;
+    const uint32_t* g_off;  // the colour-1 lists: tiles + 1 offsets into
+    const uint32_t* g_j;    // site j in the colour-1 array, per entry
     const double* g_Q;
     const double* g_S;
     double* g_part;

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -25,6 +26,12 @@ constexpr uint32_t kTileDefault = 0xFFFFFFFFu;  // lattice_set_tuning(tile = -1)
 constexpr uint32_t kStreamTileFullRow96 = 9;        // streaming kernel: 96-quad tiles, non-temporal stores
 constexpr uint32_t kStreamTileFullRow96Cached = 6;  // 96-quad tiles, ordinary stores
 constexpr uint32_t kStreamTileCached = 3;           // 32 quads x 8 rows, 6-slot ring, ordinary stores
+
+// Planes per workgroup the slab kernels default to: 16 at FP32, where the
+// sweep is bound by memory traffic and short slabs balance the chip best; 32
+// at 16-bit storage, where arithmetic binds and longer slabs amortise each
+// workgroup's start-up.
+static uint32_t default_slab(size_t esz) { return esz == 4 ? 16u : 32u; }
 
 struct lattice {
     int64_t lx = 0, ly = 0, lz = 0;
@@ -63,8 +70,12 @@ struct lattice {
     double* d_fsq = nullptr;
     int64_t force_base = 0;    // n_meas when the force sums were last cleared
     // host copy of the aggregated list of a single on-lattice charge set
-    std::vector<uint32_t> h_site;
-    std::vector<double> h_Q, h_S;
+    // (shared: copies of the handle made by the autotuner do not copy it)
+    struct HostCharges {
+        std::vector<uint32_t> site;
+        std::vector<double> Q, S;
+    };
+    std::shared_ptr<const HostCharges> host_charges;
     // fused gather of the streaming kernel: the list split by colour and
     // regrouped per tile and by plane, for one tile shape and slab (d_off:
     // the colour-0 then the colour-1 offset tables, tiles + 1 each, into
@@ -77,7 +88,8 @@ struct lattice {
         uint32_t tile = 0, slab = 0, blocks = 0;
         uint32_t n = 0, cap = 0;  // entries in all; LDS entries staged per workgroup
         uint32_t* d_off = nullptr;
-        uint32_t* d_key = nullptr;
+        uint32_t* d_key = nullptr;  // staged key: plane in slab << 16 | ring-slot byte offset
+        uint32_t* d_j = nullptr;    // the site in its colour array (for gather_tail)
         double* d_Q = nullptr;
         double* d_S = nullptr;
         double* d_part = nullptr;
@@ -105,7 +117,8 @@ struct lattice {
         hipGraphExec_t exec = nullptr;
         int64_t K = 0, every = 0, bin_size = 0;
         int variant = -1;
-        uint32_t slab = 0, tile = 0, xcd = 0;
+        uint32_t slab = 0, tile = 0;
+        int xcd = 0;
         const void* bins = nullptr;
         const void* site = nullptr;
         const void* gather = nullptr;  // per-tile lists of a fused gather, else null
@@ -114,8 +127,8 @@ struct lattice {
     hipStream_t cap = nullptr;  // private capture stream
     int graph_mode = 1;         // 0 never, 1 boxes up to 2^24 sites, 2 always
     int variant = LAT_SWEEP_AUTO;
-    uint32_t slab = 16;      // planes per workgroup for the slab kernels (set per storage at creation)
-    uint32_t xcd_order = 1;  // XCD-aware workgroup order for the slab kernels
+    uint32_t slab = 0;       // planes per workgroup for the slab kernels (0: library default)
+    int xcd_order = -1;      // XCD-aware workgroup order for the slab kernels (-1: library default)
     uint32_t tile = kTileDefault;  // tile configuration of the slab kernels
 
     // the tile the slab kernel `v` runs: the set one, else the library's
@@ -132,6 +145,18 @@ struct lattice {
         const bool nt = (size_t)vh * esz >= ((size_t)256 << 20);
         return wide ? (nt ? kStreamTileFullRow96 : kStreamTileFullRow96Cached) : (nt ? 0u : kStreamTileCached);
     }
+    // the planes per workgroup and the workgroup order the slab kernel `v`
+    // runs: the set ones, else the library's defaults.  The streaming
+    // kernel's full-row FP32 tile measured fastest with 24 planes and the
+    // hardware's own round-robin order of workgroups over the XCDs (at 768^3:
+    // 345-349 us against 355 us per half-sweep with 16 planes and the
+    // XCD-aware order); everything else with 16 (FP32) or 32 (16-bit) planes
+    // and the XCD-aware order.
+    bool full_row_default(int v) const {
+        return v == LAT_SWEEP_STREAM && esz == 4 && resolved_tile(v) == kStreamTileFullRow96;
+    }
+    uint32_t resolved_slab(int v) const { return slab ? slab : full_row_default(v) ? 24u : default_slab(esz); }
+    uint32_t resolved_xcd(int v) const { return xcd_order >= 0 ? (uint32_t)xcd_order : full_row_default(v) ? 0u : 1u; }
     double* last_xy() { return d_lastxy ? d_lastxy : reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
     uint32_t* counters() { return static_cast<uint32_t*>(d_misc); }  // [0] sweeps, [1] samples
     void* c1main() const { return static_cast<char*>(field) + (size_t)vh * esz; }
@@ -149,12 +174,6 @@ struct lattice {
     }
 };
 
-// Planes per workgroup the slab kernels default to: 16 at FP32, where the
-// sweep is bound by memory traffic and short slabs balance the chip best; 32
-// at 16-bit storage, where arithmetic binds and longer slabs amortise each
-// workgroup's start-up.
-static uint32_t default_slab(size_t esz) { return esz == 4 ? 16u : 32u; }
-
 static int check_lattice(const lattice* L) {
     if (!L) return set_error(LAT_ERR_ARG, "null lattice handle");
     return LAT_OK;
@@ -165,6 +184,7 @@ static void graphs_reset(lattice* L);
 static void fused_gather_release(lattice* L) {
     L->mem.release(L->fg.d_off);
     L->mem.release(L->fg.d_key);
+    L->mem.release(L->fg.d_j);
     L->mem.release(L->fg.d_Q);
     L->mem.release(L->fg.d_S);
     L->mem.release(L->fg.d_part);
@@ -175,7 +195,7 @@ static void fused_gather_release(lattice* L) {
 // one on-lattice charge set and the lists built for the current tiling.
 static bool fused_gather_on(const lattice* L) {
     return L->fg.ready && L->effective_variant() == LAT_SWEEP_STREAM && L->n_sets == 1 && !L->offl &&
-           L->fg.tile == L->resolved_tile(LAT_SWEEP_STREAM) && L->fg.slab == (L->slab ? L->slab : 16u);
+           L->fg.tile == L->resolved_tile(LAT_SWEEP_STREAM) && L->fg.slab == L->resolved_slab(LAT_SWEEP_STREAM);
 }
 
 // Resident workgroups per CU of a kernel with `lds` bytes of LDS and `waves`
@@ -190,9 +210,9 @@ static uint32_t workgroups_per_cu(uint32_t lds, uint32_t waves) {
 // stage in LDS without costing the sweep kernel a resident workgroup,
 // allocation failure) the samples go through the separate gather.
 static int fused_gather_prepare(lattice* L) {
-    const uint32_t tile = L->resolved_tile(LAT_SWEEP_STREAM), slab = L->slab ? L->slab : 16u;
+    const uint32_t tile = L->resolved_tile(LAT_SWEEP_STREAM), slab = L->resolved_slab(LAT_SWEEP_STREAM);
     if (L->effective_variant() != LAT_SWEEP_STREAM || L->n_sets != 1 || L->offl ||
-        L->h_site.size() != L->n_sites)
+        !L->host_charges || L->host_charges->site.size() != L->n_sites)
         return LAT_OK;
     if (L->fg.tried && L->fg.tile == tile && L->fg.slab == slab) return LAT_OK;
     fused_gather_release(L);
@@ -207,17 +227,25 @@ static int fused_gather_prepare(lattice* L) {
     const uint32_t nbx = (nq + tq - 1) / tq, nby = (ly + ty - 1) / ty, nbz = (lz + slab - 1) / slab;
     const uint32_t blocks = nbx * nby * nbz;
     const uint32_t plane = (uint32_t)L->ly * L->lh;
-    const size_t n = L->h_site.size();
+    const lattice::HostCharges& hc = *L->host_charges;
+    const size_t n = hc.site.size();
     // sort key of every charged site: its colour, its tile, its plane
+    // staged key: plane within the slab << 16 | byte offset of the site in
+    // a ring slot (rows y0-1 .. y0+ty of tq + 2 quads: halo quad first)
+    if (slab > 0xFFFFu) return LAT_OK;
+    const uint32_t row_bytes = (tq + 2u) * 4u * (uint32_t)L->esz;
     std::vector<uint64_t> key_of(n);
-    std::vector<uint32_t> tile_of(n), j_of(n);
+    std::vector<uint32_t> tile_of(n), j_of(n), packed_of(n);
     size_t n0 = 0;
     for (size_t i = 0; i < n; ++i) {
-        const uint32_t c = L->h_site[i] >= L->vh ? 1u : 0u;
-        const uint32_t j = L->h_site[i] - c * L->vh;
+        const uint32_t c = hc.site[i] >= L->vh ? 1u : 0u;
+        const uint32_t j = hc.site[i] - c * L->vh;
         const uint32_t z = j / plane, rem = j - z * plane, y = rem / L->lh, jx = rem - y * L->lh;
-        tile_of[i] = (jx / 4) / tq + nbx * (y / ty + nby * (z / slab));
+        const uint32_t bx = (jx / 4) / tq, by = y / ty, bz = z / slab;
+        tile_of[i] = bx + nbx * (by + nby * bz);
         j_of[i] = j;
+        const uint32_t off = (y - by * ty + 1u) * row_bytes + (jx - 4u * tq * bx + 4u) * (uint32_t)L->esz;
+        packed_of[i] = ((z - bz * slab) << 16) | off;
         key_of[i] = ((uint64_t)c * blocks + tile_of[i]) * lz + z;
         n0 += c ? 0u : 1u;
     }
@@ -225,19 +253,21 @@ static int fused_gather_prepare(lattice* L) {
     for (size_t i = 0; i < n; ++i) order[i] = (uint32_t)i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key_of[a] < key_of[b]; });
     // offsets: colour 0 at [0, blocks], colour 1 at [blocks + 1, 2 blocks + 1]
-    std::vector<uint32_t> off(2 * ((size_t)blocks + 1), 0u), key(n);
+    std::vector<uint32_t> off(2 * ((size_t)blocks + 1), 0u), key(n), jv(n);
     std::vector<double> Q(n), S(n);
     for (size_t k = 0; k < n; ++k) {
         const uint32_t i = order[k];
         const size_t c = k < n0 ? 0 : 1;
         off[c * (blocks + 1) + tile_of[i] + 1] += 1;
-        key[k] = j_of[i];
-        Q[k] = L->h_Q[i];
-        S[k] = L->h_S[i];
+        key[k] = packed_of[i];
+        jv[k] = j_of[i];
+        Q[k] = hc.Q[i];
+        S[k] = hc.S[i];
     }
     uint32_t longest = 0;
     for (size_t t = 0; t < 2 * ((size_t)blocks + 1); ++t) longest = std::max(longest, off[t]);
     const uint64_t cap = ((uint64_t)longest + 63u) / 64u * 64u;
+    if (cap > 256u) return LAT_OK;  // the kernel holds up to 4 x 64 keys per tile in registers
     const uint64_t lds = sh.lds + (uint64_t)kGatherEntryBytes * cap;
     if (lds > 65536u || workgroups_per_cu((uint32_t)lds, sh.waves) < workgroups_per_cu(sh.lds, sh.waves) ||
         (uint64_t)n * 8u >= (1ull << 32))
@@ -248,11 +278,12 @@ static int fused_gather_prepare(lattice* L) {
     lattice::FusedGather g = L->fg;
     g.d_off = static_cast<uint32_t*>(L->mem.alloc(off.size() * 4));
     g.d_key = static_cast<uint32_t*>(L->mem.alloc(std::max<size_t>(n, 1) * 4));
+    g.d_j = static_cast<uint32_t*>(L->mem.alloc(std::max<size_t>(n, 1) * 4));
     g.d_Q = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
     g.d_S = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
     g.d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * 64));
     L->fg = g;  // released by fused_gather_release on any failure below
-    if (!g.d_off || !g.d_key || !g.d_Q || !g.d_S || !g.d_part) {
+    if (!g.d_off || !g.d_key || !g.d_j || !g.d_Q || !g.d_S || !g.d_part) {
         fused_gather_release(L);
         L->fg.tried = true;  // the separate gather for this tiling
         L->fg.tile = tile;
@@ -261,6 +292,7 @@ static int fused_gather_prepare(lattice* L) {
     }
     hipError_t e = hipMemcpyAsync(g.d_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_key, key.data(), n * 4, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_j, jv.data(), n * 4, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_Q, Q.data(), n * 8, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_S, S.data(), n * 8, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
@@ -288,7 +320,8 @@ static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev
     if (v == LAT_SWEEP_FUSED) {
         void* out = L->alt_current ? L->c1main() : L->c1alt;
         FusedArgs a{L->field, L->c1cur(), out, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, h0,
-                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, L->slab, L->xcd_order,
+                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, L->resolved_slab(v),
+                    L->resolved_xcd(v),
                     tdev};
         e = launch_fused_sweep(a, stream);
         if (e == hipSuccess) L->alt_current = !L->alt_current;
@@ -298,8 +331,8 @@ static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev
                        : v == LAT_SWEEP_STREAM ? kVariantStream
                                                : kVariantGeneric;
         SweepArgs a{L->field, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, 0u, h0,
-                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, kv, L->slab,
-                    L->xcd_order, L->resolved_tile(v), tdev};
+                    (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, kv, L->resolved_slab(v),
+                    L->resolved_xcd(v), L->resolved_tile(v), tdev};
         const lattice::FusedGather& g = L->fg;
         // sample k's partials: buffer k & 1, the colour-0 then the colour-1 pairs
         auto part = [&](uint32_t k, uint32_t colour) { return g.d_part + ((size_t)(k & 1u) * 2 + colour) * 2 * g.blocks; };
@@ -348,8 +381,8 @@ static int enqueue_sweep(lattice* L, const lattice::FusedStep* fs = nullptr) {
 static int enqueue_fused_tail(lattice* L, hipStream_t stream, uint32_t m, const uint32_t* mdev) {
     const lattice::FusedGather& g = L->fg;
     double* buf = g.d_part + (size_t)(m & 1u) * 4 * g.blocks;  // sample m's partials, colour 0 then 1
-    GatherTailArgs a{L->c1cur(), L->storage, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->slab, g.tile,
-                     g.d_off + g.blocks + 1, g.d_key, g.d_Q, g.d_S, buf + 2 * (size_t)g.blocks};
+    GatherTailArgs a{L->c1cur(), L->storage, g.blocks, g.d_off + g.blocks + 1, g.d_j, g.d_Q, g.d_S,
+                     buf + 2 * (size_t)g.blocks};
     hipError_t e = launch_gather_tail(a, stream);
     if (e == hipSuccess)
         e = launch_finalize_measure(buf, 2 * g.blocks, 1u, L->d_bins, m, (uint32_t)L->bin_size, mdev,
@@ -462,8 +495,9 @@ static const void* graph_gather_key(const lattice* L, int64_t every) {
 }
 
 static bool graph_matches(const lattice* L, const lattice::SweepGraph& g, int64_t K, int64_t every) {
-    return g.exec && g.gather == graph_gather_key(L, every) && g.K == K && g.every == every && g.variant == L->effective_variant() && g.slab == L->slab &&
-           g.tile == L->tile && g.xcd == L->xcd_order && g.site == L->d_site &&
+    return g.exec && g.gather == graph_gather_key(L, every) && g.K == K && g.every == every &&
+           g.variant == L->effective_variant() && g.slab == L->slab && g.tile == L->tile &&
+           g.xcd == L->xcd_order && g.site == L->d_site &&
            (every == 0 || (g.bins == L->d_bins && g.bin_size == L->bin_size));
 }
 
@@ -623,17 +657,22 @@ static std::vector<TuneChoice> tune_candidates(const lattice* L) {
         return c;
     }
     const bool slab_ok = (size_t)L->vh * L->esz < ((size_t)1 << 31);
-    if (slab_ok && (size_t)2 * L->vh * L->esz >= ((size_t)256 << 20))
-        c.push_back({LAT_SWEEP_STREAM, default_slab(L->esz), L->resolved_tile(LAT_SWEEP_STREAM), 1, 0});
+    if (slab_ok && (size_t)2 * L->vh * L->esz >= ((size_t)256 << 20)) {
+        lattice d = *L;  // the library's own choice for the box
+        d.slab = 0;
+        d.tile = kTileDefault;
+        d.xcd_order = -1;
+        c.push_back({LAT_SWEEP_STREAM, d.resolved_slab(LAT_SWEEP_STREAM), d.resolved_tile(LAT_SWEEP_STREAM),
+                     d.resolved_xcd(LAT_SWEEP_STREAM), 0});
+    }
     c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
     if (V > kResidentMaxSites && V <= (uint64_t)1 << 18 && resident_ok)
         c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
     if (slab_ok)
         for (uint32_t tile = 0; tile < (uint32_t)kStreamTiles; ++tile)
-            for (uint32_t slab : {16u, 32u, 48u})
+            for (uint32_t slab : {16u, 24u, 32u, 48u})
                 for (uint32_t xcd : {1u, 0u})
-                    if (slab <= L->lz && (xcd == 1 || tile == 0 || tile == 9))
-                        c.push_back({LAT_SWEEP_STREAM, slab, tile, xcd, 0});
+                    if (slab <= L->lz) c.push_back({LAT_SWEEP_STREAM, slab, tile, xcd, 0});
     if (slab_ok)
         for (uint32_t tile : {0u, 1u, 7u})
             for (uint32_t slab : {8u, 16u, 32u})
@@ -648,7 +687,7 @@ static void apply_choice(lattice* L, const TuneChoice& ch) {
     L->variant = ch.variant;
     L->slab = ch.slab;
     L->tile = ch.tile;
-    L->xcd_order = ch.xcd;
+    L->xcd_order = (int)ch.xcd;
 }
 
 static int autotune(lattice* L, int64_t reps, TuneChoice* out) {
@@ -758,7 +797,6 @@ int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t see
     L->vh = (uint32_t)(lx / 2 * ly * lz);
     L->storage = storage;
     L->esz = storage == LAT_FP32 ? 4 : 2;
-    L->slab = default_slab(L->esz);
     L->seed = seed;
     L->chain = chain_id;
     L->mem = DeviceAllocator(alloc);
@@ -863,9 +901,9 @@ int lattice_get_tuning(const lattice_t* L, int* variant, int64_t* planes, int* t
     if (int r = check_lattice(L)) return r;
     const int v = L->effective_variant();
     if (variant) *variant = v;
-    if (planes) *planes = L->slab;
+    if (planes) *planes = L->resolved_slab(v);
     if (tile) *tile = (int)L->resolved_tile(v);
-    if (xcd_order) *xcd_order = (int)L->xcd_order;
+    if (xcd_order) *xcd_order = (int)L->resolved_xcd(v);
     return LAT_OK;
 }
 
@@ -888,9 +926,9 @@ int lattice_set_tuning(lattice_t* L, int64_t planes, int tile, int xcd_order) {
     if (planes < 0 || planes > L->lz) return set_error(LAT_ERR_ARG, "planes must be in [0, lz]");
     if (tile < -1 || (tile >= 0 && (uint32_t)tile >= tiles_of(L->variant)))
         return set_error(LAT_ERR_ARG, "unknown tile configuration for the selected sweep kernel");
-    L->slab = planes ? (uint32_t)planes : default_slab(L->esz);
+    L->slab = (uint32_t)planes;
     L->tile = tile < 0 ? kTileDefault : (uint32_t)tile;
-    L->xcd_order = xcd_order ? 1u : 0u;
+    L->xcd_order = xcd_order < 0 ? -1 : xcd_order ? 1 : 0;
     graphs_reset(L);
     return LAT_OK;
 }
@@ -991,13 +1029,13 @@ int lattice_set_charge_sets(lattice_t* L, int64_t n_sets, const int64_t* counts,
     release_offlattice(L);
     fused_gather_release(L);
     if (n_sets == 1) {
-        L->h_site.swap(all.site);
-        L->h_Q.swap(all.Q);
-        L->h_S.swap(all.S);
+        auto hc = std::make_shared<lattice::HostCharges>();
+        hc->site.swap(all.site);
+        hc->Q.swap(all.Q);
+        hc->S.swap(all.S);
+        L->host_charges = std::move(hc);
     } else {
-        L->h_site.clear();
-        L->h_Q.clear();
-        L->h_S.clear();
+        L->host_charges.reset();
     }
     L->n_sites = ns;
     L->n_raw = n;
@@ -1152,9 +1190,7 @@ int lattice_set_offlattice_charges(lattice_t* L, int64_t n, const double* r, con
     L->d_set_off = nullptr;
     release_offlattice(L);
     fused_gather_release(L);
-    L->h_site.clear();
-    L->h_Q.clear();
-    L->h_S.clear();
+    L->host_charges.reset();
     graphs_reset(L);
     L->d_partials = d_part;
     L->d_lastxy = d_xy;

@@ -37,14 +37,16 @@
 // gathers the charged colour-0 sites, the colour-0 half-sweep of the next
 // sweep the charged colour-1 sites (whose values of the measured sweep it
 // holds in its ring), so no value is read from memory twice or recomputed.
-// The producer wave walks its tile's list (sorted by plane) plane by plane,
-// idle between its loads, and writes one (X, Y) partial per tile.  The
-// list (j, Q, S) is staged into dynamic LDS by the same direct loads, issued
-// before the first plane's: the waits of the ring cover them, and the walk
-// touches only LDS, so it never waits on the plane loads in flight.  The
-// colour-1 part of a run's last sample, with no next sweep, comes from
-// gather_tail, which takes the same walk over the field in memory: every
-// partial is the same whichever kernel wrote it.  A sample completed by a
+// The producer wave, idle between its loads, takes its tile's list plane by
+// plane and writes one (X, Y) partial per tile.  The list (packed key, Q, S)
+// is staged into dynamic LDS by the same direct loads, issued in step 0
+// right after the first planes'; step 1 waits for it and moves the keys to
+// registers.  Plane s is gathered in step s + 1, after that step's loads
+// are requested; it touches only LDS, so it never waits on the plane loads
+// in flight.  The colour-1 part of a run's last sample, with no next sweep,
+// comes from gather_tail, whose lanes add the same entries in the same
+// order from the field in memory: every partial is the same whichever
+// kernel wrote it.  A sample completed by a
 // colour-0 launch is finalized by workgroup 0 of the colour-1 launch that
 // follows (fin set), while its first planes load; partials are kept in two
 // buffers by sample parity, so that launch may open the next sample.
@@ -119,57 +121,38 @@ __device__ __forceinline__ uint32_t lds_read_u32(uint32_t a) {
     asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(r) : "v"(a) : "memory");
     return r;
 }
-// two doubles at a and b
-__device__ __forceinline__ void lds_read_2f64(uint32_t a, uint32_t b, double& x, double& y) {
-    u32x2 u, v;
-    asm volatile("ds_read_b64 %0, %2\n\tds_read_b64 %1, %3\n\ts_waitcnt lgkmcnt(0)"
-                 : "=&v"(u), "=&v"(v)
-                 : "v"(a), "v"(b)
-                 : "memory");
-    x = __builtin_bit_cast(double, u);
-    y = __builtin_bit_cast(double, v);
-}
+// Fused-gather list entries.  Staged key of entry i of a tile's list: the
+// site's plane within the tile's slab (bits 16..31) and its byte offset in
+// a ring slot (bits 0..15); entries are sorted by plane, and entry i always
+// belongs to lane i % 64, which adds Q_i phi and S_i phi^2 in order of i.
+// kGatherRegs keys per lane are held in registers (lists of up to 256).
+constexpr int kGatherRegs = 4;
+constexpr uint32_t kNoEntry = 0xFFFFFFFFu;  // plane field never matches
 
-// One value of the storage format at an LDS address, as FP32.
+// One entry's value (at a ring address) and its Q and S (LDS), one wait.
 template <class St>
-__device__ __forceinline__ float lds_read_value(uint32_t a) {
-    if constexpr (St::kBytes == 4) {
-        return __uint_as_float(lds_read_u32(a));
-    } else {
-        uint32_t r;
-        asm volatile("ds_read_u16 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(r) : "v"(a) : "memory");
-        if constexpr (std::is_same<St, StoreBF16>::value)
-            return __uint_as_float(r << 16);
-        else
-            return (float)__builtin_bit_cast(_Float16, (uint16_t)r);
-    }
-}
-
-// The fused gather's walk over plane z of one tile's list (entries sorted
-// by plane, gcur the first not yet taken): batches of up to 64 consecutive
-// entries, entry gcur + lane to lane, until the next entry lies beyond z.
-// key_at(i) is entry i's site j, qs_at(i) its (Q, S), value_at(j) the
-// site's value.  The streaming kernel and gather_tail share it, so each
-// lane adds the same terms in the same order in both.
-template <class KeyAt, class QSAt, class ValueAt>
-__device__ __forceinline__ void gather_walk_plane(uint32_t z, uint32_t lane, uint32_t& gcur, uint32_t ng,
-                                                  uint32_t plane, KeyAt key_at, QSAt qs_at, ValueAt value_at,
-                                                  double& gx, double& gy) {
-    while (gcur < ng) {  // wave-uniform
-        const uint32_t i = gcur + lane;
-        const uint32_t j = i < ng ? key_at(i) : 0u;
-        const bool here = i < ng && j / plane == z;
-        const uint64_t mask = __builtin_amdgcn_ballot_w64(here);
-        if (mask == 0) break;
-        if (here) {
-            const double d = (double)value_at(j);
-            double Qi, Si;
-            qs_at(i, Qi, Si);
-            gx = fma(Qi, d, gx);
-            gy = fma(Si, d * d, gy);
-        }
-        gcur += (uint32_t)__builtin_popcountll(mask);
-    }
+__device__ __forceinline__ void lds_read_entry(uint32_t av, uint32_t aq, uint32_t as, float& v, double& Qi,
+                                               double& Si) {
+    u32x2 q, sv;
+    uint32_t r;
+    if constexpr (St::kBytes == 4)
+        asm volatile("ds_read_b32 %0, %3\n\tds_read_b64 %1, %4\n\tds_read_b64 %2, %5\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(r), "=&v"(q), "=&v"(sv)
+                     : "v"(av), "v"(aq), "v"(as)
+                     : "memory");
+    else
+        asm volatile("ds_read_u16 %0, %3\n\tds_read_b64 %1, %4\n\tds_read_b64 %2, %5\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(r), "=&v"(q), "=&v"(sv)
+                     : "v"(av), "v"(aq), "v"(as)
+                     : "memory");
+    if constexpr (St::kBytes == 4)
+        v = __uint_as_float(r);
+    else if constexpr (std::is_same<St, StoreBF16>::value)
+        v = __uint_as_float(r << 16);
+    else
+        v = (float)__builtin_bit_cast(_Float16, (uint16_t)r);
+    Qi = __builtin_bit_cast(double, q);
+    Si = __builtin_bit_cast(double, sv);
 }
 
 // s_waitcnt immediates (gfx9 encoding): vmcnt in bits 3:0 and 15:14, expcnt
@@ -228,7 +211,9 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
     using S = Stream<St, kM, kTY, kRing>;
     using T = typename St::T;
     __shared__ __align__(16) unsigned char ring[S::kRing * S::kSlot];
-    // fused gather: the tile's keys, then Q, then S (g_cap entries each)
+    // fused gather: the tile's list offsets, then its keys, Q and S (g_cap
+    // entries each)
+    __shared__ __align__(16) uint32_t list_off[4];
     extern __shared__ __align__(16) unsigned char stage[];
     if (tdev) h += 2u * tdev[0];
 
@@ -244,10 +229,7 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
     const uint32_t z1 = min(z0 + zc, lz);
     const uint32_t n = z1 - z0;  // planes this workgroup updates (>= 1)
     const uint32_t plane = ly * lh, plane_b = plane * S::kEsz;
-    // fused gather: this tile's list, requested before the ring is cleared
-    // so that its latency overlaps the clearing
     const uint32_t tile = bx + nbx * (by + nby * bz);
-    const uint32_t gbase = g_key ? g_off[tile] : 0u, ng = g_key ? g_off[tile + 1] - gbase : 0u;  // ng <= g_cap
     const bool finalize = fin.part != nullptr && blockIdx.x == 0;  // the previous sample, in the first workgroup
 
     for (uint32_t i = threadIdx.x; i < S::kRing * S::kSlot / 16; i += S::kThreads)
@@ -304,21 +286,25 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
             uint32_t k = 0;
             for (uint32_t l = lo; l <= hi; ++l) k += loads(l) ? 1u : 0u;
             if (!every) k = 0;
-            switch (k) {
+            switch (k) {  // (a count beyond vmcnt's 6 bits waits for all)
                 case 0: wait_vm_lgkm0<0>(); break;
                 case 1: wait_vm_lgkm0<S::kNI>(); break;
-                case 2: wait_vm_lgkm0<(S::kRing >= 6 ? 2 : 0) * S::kNI>(); break;
-                default: wait_vm_lgkm0<(S::kRing >= 7 ? 3 : 0) * S::kNI>(); break;
+                case 2: wait_vm_lgkm0<(2 * S::kNI < 64 ? 2 * S::kNI : 0)>(); break;
+                case 3: wait_vm_lgkm0<(3 * S::kNI < 64 ? 3 * S::kNI : 0)>(); break;
+                default: wait_vm_lgkm0<0>(); break;
             }
         };
         // fused gather: this tile's charged sites of the other colour, sorted
-        // by plane, staged into LDS before the first plane is requested
+        // by plane.  The tile's two list offsets are loaded to LDS ahead of
+        // the first planes and read after barrier b_0 (their latency hidden
+        // by the plane loads).
         const bool gather = g_key != nullptr;
-        uint32_t gcur = 0;
+        uint32_t gbase = 0, ng = 0;
+        uint32_t key[kGatherRegs];
         double gx = 0.0, gy = 0.0;
         const uint32_t a_key = lds_addr(stage), a_Q = a_key + 4u * g_cap, a_S = a_key + 12u * g_cap;
         const uint32_t a_ring = lds_addr(ring);
-        if (gather) {
+        auto stage_list = [&]() {
             const __amdgpu_buffer_rsrc_t rk = make_rsrc(g_key, 4u * g_n);
             const __amdgpu_buffer_rsrc_t rq = make_rsrc(g_Q, 8u * g_n);
             const __amdgpu_buffer_rsrc_t rs = make_rsrc(g_S, 8u * g_n);
@@ -331,33 +317,64 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
                     lds_load_b32(rs, (lds_ptr_t)(stage + 12u * g_cap + 256u * i), 4u * (64u * i + lane),
                                  8u * gbase);
                 }
-        }
-        // plane z0 + s, in ring slot s + 1 (landed, as has the staged list,
-        // loaded before it)
+        };
+        auto load_keys = [&]() {
+#pragma unroll
+            for (int k = 0; k < kGatherRegs; ++k) {
+                const uint32_t i = lane + 64u * (uint32_t)k;
+                key[k] = i < ng ? lds_read_u32(a_key + 4u * i) : kNoEntry;
+            }
+        };
+        // plane z0 + s, in ring slot s + 1: gathered in step s + 1 (or after
+        // the last step), before step s + 2 refills the slot
         auto gather_plane = [&](uint32_t s) {
             const uint32_t slot = a_ring + ((s + 1u) % S::kRing) * S::kSlot;
-            gather_walk_plane(
-                z0 + s, lane, gcur, ng, plane, [&](uint32_t i) { return lds_read_u32(a_key + 4u * i); },
-                [&](uint32_t i, double& Qi, double& Si) { lds_read_2f64(a_Q + 8u * i, a_S + 8u * i, Qi, Si); },
-                [&](uint32_t j) {
-                    const uint32_t rem = j % plane, yy = rem / lh, jx = rem - yy * lh;
-                    return lds_read_value<St>(slot + (yy - y0 + 1u) * S::kRB + (jx - 4u * q0 + 4u) * S::kEsz);
-                },
-                gx, gy);
+#pragma unroll
+            for (int k = 0; k < kGatherRegs; ++k) {
+                const bool hit = (key[k] >> 16) == s;
+                if (__builtin_amdgcn_ballot_w64(hit) == 0) continue;  // wave-uniform
+                if (hit) {
+                    const uint32_t i = lane + 64u * (uint32_t)k;
+                    float v;
+                    double Qi, Si;
+                    lds_read_entry<St>(slot + (key[k] & 0xFFFFu), a_Q + 8u * i, a_S + 8u * i, v, Qi, Si);
+                    const double d = (double)v;
+                    gx = fma(Qi, d, gx);
+                    gy = fma(Si, d * d, gy);
+                }
+            }
         };
+        if (gather && lane < 2u)  // g_off[tile], g_off[tile + 1] into list_off
+            lds_load_b32(make_rsrc(g_off, 4u * (gridDim.x + 1u)), (lds_ptr_t)list_off, 4u * lane, 4u * tile);
         for (uint32_t l = 0; l + 1u < (uint32_t)S::kRing; ++l) produce(l);  // planes l = 0 .. R-2
         if (finalize) finalize_in_workgroup<S::kThreads, S::kCompute>(fin);
-        wait_landed(3u, S::kRing - 2u);
+        wait_landed(3u, S::kRing - 2u);  // (the offsets, loaded first, have landed)
         producer_barrier();  // b_0
+        if (gather) {
+            gbase = lds_read_u32(lds_addr(list_off));
+            ng = lds_read_u32(lds_addr(list_off) + 4u) - gbase;  // <= g_cap
+            stage_list();
+        }
         for (uint32_t s = 0; s < n; ++s) {
             if (s + 1u < n) produce(s + S::kRing - 1u);
-            if (gather) gather_plane(s);
+            if (gather && s >= 1u) {
+                if (s == 1u) {  // the list, staged before plane R - 1
+                    wait_landed(S::kRing - 1u, S::kRing);
+                    load_keys();
+                }
+                gather_plane(s - 1u);
+            }
             if (s + 1u < n) {
                 wait_landed(s + 4u, s + S::kRing - 1u);
                 producer_barrier();  // b_{s+1}
             }
         }
         if (gather) {
+            if (n == 1u) {
+                wait_vm_lgkm0<0>();
+                load_keys();
+            }
+            gather_plane(n - 1u);
             gx = wave_sum(gx);
             gy = wave_sum(gy);
             if (lane == 0) {
@@ -445,14 +462,17 @@ bool stream_tile_geometry(uint32_t tile, uint32_t esz, StreamTileShape* out) {
     const uint32_t q = kShape[tile][0], rows = kShape[tile][1], slots = kShape[tile][2];
     out->quads = q;
     out->rows = rows;
-    out->lds = slots * (rows + 2u) * (q + 2u) * 4u * esz;
     out->waves = q * rows / 64u + 1u;
+    // the plane ring, the list offsets (16 B, 16-byte aligned), the workgroup
+    // sum of the in-kernel finalize (two doubles per wave): the compiler's
+    // static LDS size of each instantiation
+    out->lds = slots * (rows + 2u) * (q + 2u) * 4u * esz + 32u + 16u * out->waves;
     return true;
 }
 
 hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream) {
     if (a.lh % 4 != 0) return hipErrorInvalidValue;
-    if (a.g_key && (!a.g_off || !a.g_Q || !a.g_S || !a.g_part || a.g_cap % 64u != 0 ||
+    if (a.g_key && (!a.g_off || !a.g_Q || !a.g_S || !a.g_part || a.g_cap % 64u != 0 || a.g_cap > 64u * kGatherRegs ||
                     (uint64_t)a.g_n * 8u >= (1ull << 32)))
         return hipErrorInvalidValue;
     if (a.fin.part && (!a.fin.bins || !a.fin.last_xy || a.fin.n == 0 || a.fin.bin_size == 0))
@@ -483,28 +503,22 @@ hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream) {
 }
 
 // The colour-1 part of a sample from the field in memory (a run's last
-// sample): one wave per tile, the streaming kernel's walk over the same
-// per-tile list, partial per tile.
+// sample): one wave per tile; lane i % 64 adds entry i of the tile's list in
+// order of i, as in the streaming kernel, so the partial per tile is the
+// same.
 template <class St>
-__global__ __launch_bounds__(64) void gather_tail(const typename St::T* __restrict__ f, uint32_t lh, uint32_t ly,
-                                                 uint32_t lz, uint32_t zc, uint32_t tq, uint32_t ty,
-                                                 const uint32_t* __restrict__ g_off, const uint32_t* __restrict__ g_key,
+__global__ __launch_bounds__(64) void gather_tail(const typename St::T* __restrict__ f,
+                                                 const uint32_t* __restrict__ g_off, const uint32_t* __restrict__ g_j,
                                                  const double* __restrict__ g_Q, const double* __restrict__ g_S,
                                                  double* __restrict__ g_part) {
-    const uint32_t nq = lh >> 2, nbx = (nq + tq - 1) / tq, nby = (ly + ty - 1) / ty;
     const uint32_t tile = blockIdx.x, lane = threadIdx.x;
-    const uint32_t z0 = (tile / (nbx * nby)) * zc, n = min(z0 + zc, lz) - z0;
-    const uint32_t plane = ly * lh, gbase = g_off[tile], ng = g_off[tile + 1] - gbase;
-    uint32_t gcur = 0;
+    const uint32_t gbase = g_off[tile], ng = g_off[tile + 1] - gbase;
     double gx = 0.0, gy = 0.0;
-    for (uint32_t s = 0; s < n; ++s)
-        gather_walk_plane(
-            z0 + s, lane, gcur, ng, plane, [&](uint32_t i) { return g_key[gbase + i]; },
-            [&](uint32_t i, double& Qi, double& Si) {
-                Qi = g_Q[gbase + i];
-                Si = g_S[gbase + i];
-            },
-            [&](uint32_t j) { return St::ld(f, j); }, gx, gy);
+    for (uint32_t i = lane; i < ng; i += 64u) {
+        const double d = (double)St::ld(f, g_j[gbase + i]);
+        gx = fma(g_Q[gbase + i], d, gx);
+        gy = fma(g_S[gbase + i], d * d, gy);
+    }
     gx = wave_sum(gx);
     gy = wave_sum(gy);
     if (lane == 0) {
@@ -514,28 +528,19 @@ __global__ __launch_bounds__(64) void gather_tail(const typename St::T* __restri
 }
 
 hipError_t launch_gather_tail(const GatherTailArgs& a, hipStream_t stream) {
-    StreamTileShape sh;
-    if (a.lh % 4 != 0 || !a.field1 || !a.g_off || !a.g_key || !a.g_Q || !a.g_S || !a.g_part ||
-        !stream_tile_geometry(a.tile, a.storage == 0 ? 4u : 2u, &sh))
-        return hipErrorInvalidValue;
-    const uint32_t zc = a.zc ? a.zc : 16u, nq = a.lh / 4;
-    const uint32_t tiles =
-        ((nq + sh.quads - 1) / sh.quads) * ((a.ly + sh.rows - 1) / sh.rows) * ((a.lz + zc - 1) / zc);
+    if (!a.field1 || !a.g_off || !a.g_j || !a.g_Q || !a.g_S || !a.g_part || a.tiles == 0) return hipErrorInvalidValue;
     switch (a.storage) {
         case 0:
-            hipLaunchKernelGGL(gather_tail<StoreF32>, dim3(tiles), dim3(64), 0, stream,
-                               static_cast<const float*>(a.field1), a.lh, a.ly, a.lz, zc, sh.quads, sh.rows, a.g_off,
-                               a.g_key, a.g_Q, a.g_S, a.g_part);
+            hipLaunchKernelGGL(gather_tail<StoreF32>, dim3(a.tiles), dim3(64), 0, stream,
+                               static_cast<const float*>(a.field1), a.g_off, a.g_j, a.g_Q, a.g_S, a.g_part);
             break;
         case 1:
-            hipLaunchKernelGGL(gather_tail<StoreBF16>, dim3(tiles), dim3(64), 0, stream,
-                               static_cast<const uint16_t*>(a.field1), a.lh, a.ly, a.lz, zc, sh.quads, sh.rows,
-                               a.g_off, a.g_key, a.g_Q, a.g_S, a.g_part);
+            hipLaunchKernelGGL(gather_tail<StoreBF16>, dim3(a.tiles), dim3(64), 0, stream,
+                               static_cast<const uint16_t*>(a.field1), a.g_off, a.g_j, a.g_Q, a.g_S, a.g_part);
             break;
         case 2:
-            hipLaunchKernelGGL(gather_tail<StoreF16>, dim3(tiles), dim3(64), 0, stream,
-                               static_cast<const _Float16*>(a.field1), a.lh, a.ly, a.lz, zc, sh.quads, sh.rows,
-                               a.g_off, a.g_key, a.g_Q, a.g_S, a.g_part);
+            hipLaunchKernelGGL(gather_tail<StoreF16>, dim3(a.tiles), dim3(64), 0, stream,
+                               static_cast<const _Float16*>(a.field1), a.g_off, a.g_j, a.g_Q, a.g_S, a.g_part);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -278,10 +278,11 @@ class Lattice:
     def set_variant(self, name: str):
         self._call(self.lib.lattice_set_variant, VARIANT[name])
 
-    def set_tuning(self, planes: int = 0, tile: int = -1, xcd_order: bool = True):
+    def set_tuning(self, planes: int = 0, tile: int = -1, xcd_order=None):
         """Slab-kernel tuning: planes per workgroup, tile configuration, XCD
-        order (0 / -1: library defaults)."""
-        self._call(self.lib.lattice_set_tuning, int(planes), int(tile), 1 if xcd_order else 0)
+        order (0 / -1 / None: library defaults)."""
+        x = -1 if xcd_order is None else (1 if xcd_order else 0)
+        self._call(self.lib.lattice_set_tuning, int(planes), int(tile), x)
 
     def use_graphs(self, mode: int = 1):
         """0: launch by launch; 1: hipGraph chunks for boxes up to 2^24 sites; 2: always."""

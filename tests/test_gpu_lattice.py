@@ -385,8 +385,9 @@ def test_default_tuning_resolution(lat_mod):
     """Library defaults: boxes whose field does not fit the 256 MiB last-level
     cache run the streaming slab kernel, at FP32 with 96-quad tiles where they
     divide the rows, else 32-quad tiles, and non-temporal stores only where a
-    colour array is at least 256 MiB; 16 planes per workgroup at FP32, 32 at
-    16-bit storage; explicit settings win."""
+    colour array is at least 256 MiB; 24 planes per workgroup and round-robin
+    workgroup order for the full-row FP32 tile 9, else 16 planes at FP32 and
+    32 at 16-bit storage with XCD runs; explicit settings win."""
     print("[gpu] default tuning", flush=True)
     lat = lat_mod.Lattice((768, 768, 128), "fp32")  # 2 x 151 MB
     assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 6, "xcd_order": True}
@@ -402,7 +403,14 @@ def test_default_tuning_resolution(lat_mod):
     assert lat.tuning() == {"variant": "stream", "planes": 32, "tile": 0, "xcd_order": True}
     lat.close()
     lat = lat_mod.Lattice((768, 768, 512), "fp32")  # 2 x 604 MB
-    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 9, "xcd_order": True}
+    assert lat.tuning() == {"variant": "stream", "planes": 24, "tile": 9, "xcd_order": False}
+    lat.set_variant("stream")  # tile 9 exists for the streaming kernel only
+    lat.set_tuning(0, 9, True)
+    assert lat.tuning() == {"variant": "stream", "planes": 24, "tile": 9, "xcd_order": True}
+    lat.set_tuning(16, 9)
+    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 9, "xcd_order": False}
+    lat.set_tuning(0, 6)
+    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 6, "xcd_order": True}
     lat.close()
     lat = lat_mod.Lattice((640, 640, 192), "fp32")  # 2 x 157 MB, 80 quads per row
     assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 3, "xcd_order": True}
