@@ -147,16 +147,17 @@ struct lattice {
     }
     // the planes per workgroup and the workgroup order the slab kernel `v`
     // runs: the set ones, else the library's defaults.  The streaming
-    // kernel's full-row FP32 tile measured fastest with 24 planes and the
-    // hardware's own round-robin order of workgroups over the XCDs (at 768^3:
-    // 345-349 us against 355 us per half-sweep with 16 planes and the
-    // XCD-aware order); everything else with 16 (FP32) or 32 (16-bit) planes
-    // and the XCD-aware order.
+    // kernel's full-row FP32 tile measured fastest with 24 planes and each
+    // XCD taking a band of every slab's tiles, all XCDs moving through the
+    // slabs together (order 2; at 768^3 338 us per half-sweep against 342 us
+    // in the hardware's round-robin order and 354-361 us with a contiguous
+    // run of tiles per XCD); everything else with 16 (FP32) or 32 (16-bit)
+    // planes and a run of tiles per XCD (order 1).
     bool full_row_default(int v) const {
         return v == LAT_SWEEP_STREAM && esz == 4 && resolved_tile(v) == kStreamTileFullRow96;
     }
     uint32_t resolved_slab(int v) const { return slab ? slab : full_row_default(v) ? 24u : default_slab(esz); }
-    uint32_t resolved_xcd(int v) const { return xcd_order >= 0 ? (uint32_t)xcd_order : full_row_default(v) ? 0u : 1u; }
+    uint32_t resolved_xcd(int v) const { return xcd_order >= 0 ? (uint32_t)xcd_order : full_row_default(v) ? 2u : 1u; }
     double* last_xy() { return d_lastxy ? d_lastxy : reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
     uint32_t* counters() { return static_cast<uint32_t*>(d_misc); }  // [0] sweeps, [1] samples
     void* c1main() const { return static_cast<char*>(field) + (size_t)vh * esz; }
@@ -671,7 +672,7 @@ static std::vector<TuneChoice> tune_candidates(const lattice* L) {
     if (slab_ok)
         for (uint32_t tile = 0; tile < (uint32_t)kStreamTiles; ++tile)
             for (uint32_t slab : {16u, 24u, 32u, 48u})
-                for (uint32_t xcd : {1u, 0u})
+                for (uint32_t xcd : {1u, 2u, 0u})
                     if (slab <= L->lz) c.push_back({LAT_SWEEP_STREAM, slab, tile, xcd, 0});
     if (slab_ok)
         for (uint32_t tile : {0u, 1u, 7u})
@@ -924,11 +925,12 @@ int lattice_use_graphs(lattice_t* L, int mode) {
 int lattice_set_tuning(lattice_t* L, int64_t planes, int tile, int xcd_order) {
     if (int r = check_lattice(L)) return r;
     if (planes < 0 || planes > L->lz) return set_error(LAT_ERR_ARG, "planes must be in [0, lz]");
+    if (xcd_order > 2) return set_error(LAT_ERR_ARG, "xcd_order must be -1, 0, 1 or 2");
     if (tile < -1 || (tile >= 0 && (uint32_t)tile >= tiles_of(L->variant)))
         return set_error(LAT_ERR_ARG, "unknown tile configuration for the selected sweep kernel");
     L->slab = (uint32_t)planes;
     L->tile = tile < 0 ? kTileDefault : (uint32_t)tile;
-    L->xcd_order = xcd_order < 0 ? -1 : xcd_order ? 1 : 0;
+    L->xcd_order = xcd_order < 0 ? -1 : xcd_order;
     graphs_reset(L);
     return LAT_OK;
 }

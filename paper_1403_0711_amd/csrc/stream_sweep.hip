@@ -219,10 +219,16 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
 
     const uint32_t nq = lh >> 2;
     const uint32_t nbx = (nq + S::kTX - 1) / S::kTX, nby = (ly + kTY - 1) / kTY;
+    // workgroup order over the 8 XCDs (the hardware deals blocks round-robin):
+    // 0 as dealt; 1 each XCD a contiguous run of tiles; 2 each XCD a band of
+    // the tiles of one slab, all XCDs moving through the slabs together
     uint32_t b = blockIdx.x;
-    if (xcd_order) {
+    if (xcd_order == 1u) {
         const uint32_t per = gridDim.x / 8u;
         if (b < 8u * per) b = (b % 8u) * per + b / 8u;
+    } else if (xcd_order == 2u) {
+        const uint32_t t = nbx * nby, w = b % t, per = t / 8u;
+        if (w < 8u * per) b = b - w + (w % 8u) * per + w / 8u;
     }
     const uint32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const uint32_t q0 = bx * S::kTX, y0 = by * kTY, z0 = bz * zc;

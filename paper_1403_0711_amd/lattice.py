@@ -281,7 +281,7 @@ class Lattice:
     def set_tuning(self, planes: int = 0, tile: int = -1, xcd_order=None):
         """Slab-kernel tuning: planes per workgroup, tile configuration, XCD
         order (0 / -1 / None: library defaults)."""
-        x = -1 if xcd_order is None else (1 if xcd_order else 0)
+        x = -1 if xcd_order is None else int(xcd_order)
         self._call(self.lib.lattice_set_tuning, int(planes), int(tile), x)
 
     def use_graphs(self, mode: int = 1):
@@ -295,7 +295,7 @@ class Lattice:
         self._call(self.lib.lattice_get_tuning, ctypes.byref(v), ctypes.byref(pl), ctypes.byref(t), ctypes.byref(x))
         names = {val: key for key, val in VARIANT.items()}
         return {"variant": names.get(v.value, v.value), "planes": pl.value, "tile": t.value,
-                "xcd_order": bool(x.value)}
+                "xcd_order": int(x.value)}
 
     def sample_path(self) -> str:
         """How the samples of the last sweep_and_measure were gathered:
@@ -312,7 +312,7 @@ class Lattice:
                    ctypes.byref(x), ctypes.byref(ms))
         names = {val: key for key, val in VARIANT.items()}
         return {"variant": names.get(v.value, v.value), "planes": pl.value, "tile": t.value,
-                "xcd_order": bool(x.value), "ms_per_sweep": ms.value}
+                "xcd_order": int(x.value), "ms_per_sweep": ms.value}
 
     def get_field(self) -> np.ndarray:
         lx, ly, lz = self.shape

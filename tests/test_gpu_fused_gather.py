@@ -222,3 +222,26 @@ def test_fused_gather_full_size(lat_mod):
     assert abs(Xa - Xb) <= 1e-12 * qa * 10.0
     assert abs(Ya - Yb) <= 1e-12 * max(abs(Yb), 1.0)
     assert np.abs(sa[2] - sb[2]).max() <= 1e-12 * (qa * 10.0) ** 2
+
+
+def test_workgroup_orders_agree(lat_mod):
+    """The three workgroup orders over the XCDs (as dealt, a run of tiles per
+    XCD, a band of each slab's tiles per XCD) give bit-identical fields and
+    samples: partials are kept per tile and summed in a fixed order."""
+    print("[gpu] workgroup orders", flush=True)
+    for shape, tile, slab in (((64, 40, 20), 9, 5), ((200, 37, 33), 9, 7), ((136, 200, 9), 2, 4)):
+        xyz, q = _charges(shape, 200, 6)
+        out = []
+        for order in (0, 1, 2):
+            lat = lat_mod.Lattice(shape, seed=8, chain_id=1)
+            lat.set_variant("stream")
+            lat.set_tuning(slab, tile, order)
+            assert lat.tuning()["xcd_order"] == order
+            lat.set_charges(xyz, q)
+            lat.thermalise(3)
+            lat.sweep_and_measure(10, 1, 2)
+            out.append((lat.get_field(), lat.get_state()[2], lat.sample_path()))
+        for f, bins, path in out[1:]:
+            np.testing.assert_array_equal(f, out[0][0])
+            np.testing.assert_array_equal(bins, out[0][1])
+            assert path == out[0][2] == "fused"

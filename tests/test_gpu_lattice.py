@@ -385,9 +385,9 @@ def test_default_tuning_resolution(lat_mod):
     """Library defaults: boxes whose field does not fit the 256 MiB last-level
     cache run the streaming slab kernel, at FP32 with 96-quad tiles where they
     divide the rows, else 32-quad tiles, and non-temporal stores only where a
-    colour array is at least 256 MiB; 24 planes per workgroup and round-robin
-    workgroup order for the full-row FP32 tile 9, else 16 planes at FP32 and
-    32 at 16-bit storage with XCD runs; explicit settings win."""
+    colour array is at least 256 MiB; 24 planes per workgroup and XCD bands
+    (workgroup order 2) for the full-row FP32 tile 9, else 16 planes at FP32
+    and 32 at 16-bit storage with XCD runs (order 1); explicit settings win."""
     print("[gpu] default tuning", flush=True)
     lat = lat_mod.Lattice((768, 768, 128), "fp32")  # 2 x 151 MB
     assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 6, "xcd_order": True}
@@ -403,12 +403,16 @@ def test_default_tuning_resolution(lat_mod):
     assert lat.tuning() == {"variant": "stream", "planes": 32, "tile": 0, "xcd_order": True}
     lat.close()
     lat = lat_mod.Lattice((768, 768, 512), "fp32")  # 2 x 604 MB
-    assert lat.tuning() == {"variant": "stream", "planes": 24, "tile": 9, "xcd_order": False}
+    assert lat.tuning() == {"variant": "stream", "planes": 24, "tile": 9, "xcd_order": 2}
     lat.set_variant("stream")  # tile 9 exists for the streaming kernel only
     lat.set_tuning(0, 9, True)
-    assert lat.tuning() == {"variant": "stream", "planes": 24, "tile": 9, "xcd_order": True}
+    assert lat.tuning() == {"variant": "stream", "planes": 24, "tile": 9, "xcd_order": 1}
+    lat.set_tuning(16, 9, 0)
+    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 9, "xcd_order": 0}
     lat.set_tuning(16, 9)
-    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 9, "xcd_order": False}
+    assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 9, "xcd_order": 2}
+    with pytest.raises(lat_mod.LatticeError):
+        lat.set_tuning(16, 9, 3)
     lat.set_tuning(0, 6)
     assert lat.tuning() == {"variant": "stream", "planes": 16, "tile": 6, "xcd_order": True}
     lat.close()
