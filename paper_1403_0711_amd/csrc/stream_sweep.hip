@@ -155,6 +155,62 @@ __device__ __forceinline__ void lds_read_entry(uint32_t av, uint32_t aq, uint32_
     Si = __builtin_bit_cast(double, sv);
 }
 
+// FP16 storage: the update of heatbath_quad on raw halves (element k of a
+// quad in half k & 1 of word k >> 1).  Each f16 term joins its FP32 sum in
+// one mixed-precision FMA, value * 1 + sum: the exact conversion and the
+// FP32 add of the float path, rounded once as that add is, in the same
+// order, so the result is bit for bit heatbath_quad's.
+template <bool kHi>
+__device__ __forceinline__ float add_f16(uint32_t w, float acc) {  // half kHi of w, plus acc
+    float r;
+    if constexpr (kHi)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(acc));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(acc));
+    return r;
+}
+template <bool kHiA, bool kHiB>
+__device__ __forceinline__ float add_f16_pair(uint32_t a, uint32_t b) {  // half kHiA of a plus half kHiB of b
+    float r;
+    if constexpr (!kHiA && !kHiB)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else if constexpr (!kHiA && kHiB)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else if constexpr (kHiA && !kHiB)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float4 heatbath_quad_f16(u32x2 bm, u32x2 bc, u32x2 bn, u32x2 up, u32x2 dn, uint32_t e,
+                                                    uint32_t p, uint32_t j0, uint32_t h, uint32_t chain, uint32_t k0,
+                                                    uint32_t k1) {
+    float a0, a1, a2, a3;  // e + x, x + y, y + z, z + w (p = 0); x + y, y + z, z + w, w + e (p = 1)
+    if (p == 0) {
+        a0 = add_f16_pair<false, false>(e, bc[0]);
+        a1 = add_f16_pair<false, true>(bc[0], bc[0]);
+        a2 = add_f16_pair<true, false>(bc[0], bc[1]);
+        a3 = add_f16_pair<false, true>(bc[1], bc[1]);
+    } else {
+        a0 = add_f16_pair<false, true>(bc[0], bc[0]);
+        a1 = add_f16_pair<true, false>(bc[0], bc[1]);
+        a2 = add_f16_pair<false, true>(bc[1], bc[1]);
+        a3 = add_f16_pair<true, false>(bc[1], e);
+    }
+    const uint4 r = philox4x32_10(j0 >> 2, h, chain, 0u, k0, k1);
+    const float sixth = 1.0f / 6.0f;
+    float4 out;
+    out.x = fmaf(add_f16<false>(bn[0], add_f16<false>(bm[0], add_f16<false>(dn[0], add_f16<false>(up[0], a0)))),
+                 sixth, heatbath_noise(r.x));
+    out.y = fmaf(add_f16<true>(bn[0], add_f16<true>(bm[0], add_f16<true>(dn[0], add_f16<true>(up[0], a1)))), sixth,
+                 heatbath_noise(r.y));
+    out.z = fmaf(add_f16<false>(bn[1], add_f16<false>(bm[1], add_f16<false>(dn[1], add_f16<false>(up[1], a2)))),
+                 sixth, heatbath_noise(r.z));
+    out.w = fmaf(add_f16<true>(bn[1], add_f16<true>(bm[1], add_f16<true>(dn[1], add_f16<true>(up[1], a3)))), sixth,
+                 heatbath_noise(r.w));
+    return out;
+}
+
 // s_waitcnt immediates (gfx9 encoding): vmcnt in bits 3:0 and 15:14, expcnt
 // 6:4, lgkmcnt 11:8; a field at its maximum does not wait.
 template <int kVm>
@@ -404,16 +460,26 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
             const unsigned char* pm = ring + (s % S::kRing) * S::kSlot + qoff;
             const unsigned char* pc = ring + ((s + 1u) % S::kRing) * S::kSlot + qoff;
             const unsigned char* pn = ring + ((s + 2u) % S::kRing) * S::kSlot + qoff;
-            const float4 bm = St::ld4(reinterpret_cast<const T*>(pm), 0);
-            const float4 bc = St::ld4(reinterpret_cast<const T*>(pc), 0);
-            const float4 bn = St::ld4(reinterpret_cast<const T*>(pn), 0);
-            const float4 up = St::ld4(reinterpret_cast<const T*>(pc - S::kRB), 0);
-            const float4 dn = St::ld4(reinterpret_cast<const T*>(pc + S::kRB), 0);
             const uint32_t p = __builtin_amdgcn_readfirstlane((c + y + z) & 1u);  // uniform per wave
-            const float e = p == 0 ? St::ld(reinterpret_cast<const T*>(pc - S::kEsz), 0)
-                                   : St::ld(reinterpret_cast<const T*>(pc + S::kQB), 0);
             const uint32_t j0 = z * plane + rowj;
-            const float4 out = heatbath_quad(bm, bc, bn, up, dn, e, p, j0, h, chain, k0, k1);
+            float4 out;
+            if constexpr (std::is_same<St, StoreF16>::value) {  // halves added in mixed-precision FMAs
+                const unsigned char* pe = p == 0 ? pc - S::kEsz : pc + S::kQB;
+                out = heatbath_quad_f16(*reinterpret_cast<const u32x2*>(pm), *reinterpret_cast<const u32x2*>(pc),
+                                        *reinterpret_cast<const u32x2*>(pn),
+                                        *reinterpret_cast<const u32x2*>(pc - S::kRB),
+                                        *reinterpret_cast<const u32x2*>(pc + S::kRB),
+                                        (uint32_t)*reinterpret_cast<const uint16_t*>(pe), p, j0, h, chain, k0, k1);
+            } else {
+                const float4 bm = St::ld4(reinterpret_cast<const T*>(pm), 0);
+                const float4 bc = St::ld4(reinterpret_cast<const T*>(pc), 0);
+                const float4 bn = St::ld4(reinterpret_cast<const T*>(pn), 0);
+                const float4 up = St::ld4(reinterpret_cast<const T*>(pc - S::kRB), 0);
+                const float4 dn = St::ld4(reinterpret_cast<const T*>(pc + S::kRB), 0);
+                const float e = p == 0 ? St::ld(reinterpret_cast<const T*>(pc - S::kEsz), 0)
+                                       : St::ld(reinterpret_cast<const T*>(pc + S::kQB), 0);
+                out = heatbath_quad(bm, bc, bn, up, dn, e, p, j0, h, chain, k0, k1);
+            }
             if constexpr (kNT)
                 St::st4_nt(own, j0, out);
             else
