@@ -33,32 +33,8 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
             const uint32_t y = rowi % ly, z = rowi / ly;
             const uint32_t p = (c + y + z) & 1u;
             const uint32_t j0 = rowi * lh + 4u * q;
-            const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-            const float4 cen = St::ld4(other, j0);
-            const float4 ym = y > 0 ? St::ld4(other, j0 - lh) : zero;
-            const float4 yp = y + 1 < ly ? St::ld4(other, j0 + lh) : zero;
-            const float4 zm = z > 0 ? St::ld4(other, j0 - plane) : zero;
-            const float4 zp = z + 1 < lz ? St::ld4(other, j0 + plane) : zero;
-            float a0, a1, a2, a3;
-            if (p == 0) {
-                const float e = q > 0 ? St::ld(other, j0 - 1) : 0.f;
-                a0 = e + cen.x;
-                a1 = cen.x + cen.y;
-                a2 = cen.y + cen.z;
-                a3 = cen.z + cen.w;
-            } else {
-                const float e = q + 1 < nq ? St::ld(other, j0 + 4) : 0.f;
-                a0 = cen.x + cen.y;
-                a1 = cen.y + cen.z;
-                a2 = cen.z + cen.w;
-                a3 = cen.w + e;
-            }
-            const uint4 r = philox4x32_10(j0 >> 2, h, d.chain_id, 0u, k0, k1);
-            float4 out;
-            out.x = fmaf(a0 + ym.x + yp.x + zm.x + zp.x, sixth, heatbath_noise(r.x));
-            out.y = fmaf(a1 + ym.y + yp.y + zm.y + zp.y, sixth, heatbath_noise(r.y));
-            out.z = fmaf(a2 + ym.z + yp.z + zm.z + zp.z, sixth, heatbath_noise(r.z));
-            out.w = fmaf(a3 + ym.w + yp.w + zm.w + zp.w, sixth, heatbath_noise(r.w));
+            const float4 out = quad_update_global<St>(other, j0, lh, plane, y > 0, y + 1 < ly, z > 0, z + 1 < lz,
+                                                      p == 0 ? q > 0 : q + 1 < nq, p, h, d.chain_id, k0, k1);
             St::st4(own, j0, out);
         }
     } else {

@@ -4,6 +4,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 #include "erfinv_coeffs.h"
@@ -259,6 +261,96 @@ struct StoreF16 {
         return make_float4((float)to_f16(v.x), (float)to_f16(v.y), (float)to_f16(v.z), (float)to_f16(v.w));
     }
 };
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// FP16 storage: the update of heatbath_quad on raw halves (element k of a
+// quad in half k & 1 of word k >> 1).  Each f16 term joins its FP32 sum in
+// one mixed-precision FMA, value * 1 + sum: the exact conversion and the
+// FP32 add of the float path, rounded once as that add is, in the same
+// order, so the result is bit for bit heatbath_quad's.
+template <bool kHi>
+__device__ __forceinline__ float add_f16(uint32_t w, float acc) {  // half kHi of w, plus acc
+    float r;
+    if constexpr (kHi)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(acc));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(acc));
+    return r;
+}
+template <bool kHiA, bool kHiB>
+__device__ __forceinline__ float add_f16_pair(uint32_t a, uint32_t b) {  // half kHiA of a plus half kHiB of b
+    float r;
+    if constexpr (!kHiA && !kHiB)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else if constexpr (!kHiA && kHiB)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else if constexpr (kHiA && !kHiB)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float4 heatbath_quad_f16(u32x2 bm, u32x2 bc, u32x2 bn, u32x2 up, u32x2 dn, uint32_t e,
+                                                    uint32_t p, uint32_t j0, uint32_t h, uint32_t chain, uint32_t k0,
+                                                    uint32_t k1) {
+    float a0, a1, a2, a3;  // e + x, x + y, y + z, z + w (p = 0); x + y, y + z, z + w, w + e (p = 1)
+    if (p == 0) {
+        a0 = add_f16_pair<false, false>(e, bc[0]);
+        a1 = add_f16_pair<false, true>(bc[0], bc[0]);
+        a2 = add_f16_pair<true, false>(bc[0], bc[1]);
+        a3 = add_f16_pair<false, true>(bc[1], bc[1]);
+    } else {
+        a0 = add_f16_pair<false, true>(bc[0], bc[0]);
+        a1 = add_f16_pair<true, false>(bc[0], bc[1]);
+        a2 = add_f16_pair<false, true>(bc[1], bc[1]);
+        a3 = add_f16_pair<true, false>(bc[1], e);
+    }
+    const uint4 r = philox4x32_10(j0 >> 2, h, chain, 0u, k0, k1);
+    const float sixth = 1.0f / 6.0f;
+    float4 out;
+    out.x = fmaf(add_f16<false>(bn[0], add_f16<false>(bm[0], add_f16<false>(dn[0], add_f16<false>(up[0], a0)))),
+                 sixth, heatbath_noise(r.x));
+    out.y = fmaf(add_f16<true>(bn[0], add_f16<true>(bm[0], add_f16<true>(dn[0], add_f16<true>(up[0], a1)))), sixth,
+                 heatbath_noise(r.y));
+    out.z = fmaf(add_f16<false>(bn[1], add_f16<false>(bm[1], add_f16<false>(dn[1], add_f16<false>(up[1], a2)))),
+                 sixth, heatbath_noise(r.z));
+    out.w = fmaf(add_f16<true>(bn[1], add_f16<true>(bm[1], add_f16<true>(dn[1], add_f16<true>(up[1], a3)))), sixth,
+                 heatbath_noise(r.w));
+    return out;
+}
+
+// The update of the quad at compact index j0 of a row, read straight from
+// the other colour's array (0 beyond the box faces; p and the quad's
+// position decide which x-neighbour beyond the quad is read).  FP16 storage
+// takes the raw halves.
+template <class St>
+__device__ __forceinline__ float4 quad_update_global(const typename St::T* other, uint32_t j0, uint32_t lh,
+                                                     uint32_t plane, bool ym_in, bool yp_in, bool zm_in, bool zp_in,
+                                                     bool e_in, uint32_t p, uint32_t h, uint32_t chain, uint32_t k0,
+                                                     uint32_t k1) {
+    const uint32_t je = p == 0 ? j0 - 1u : j0 + 4u;  // the x-neighbour beyond the quad
+    if constexpr (std::is_same<St, StoreF16>::value) {
+        const u32x2 zero = {0u, 0u};
+        const u32x2 cen = at<u32x2>(other, j0);
+        const u32x2 ym = ym_in ? at<u32x2>(other, j0 - lh) : zero;
+        const u32x2 yp = yp_in ? at<u32x2>(other, j0 + lh) : zero;
+        const u32x2 zm = zm_in ? at<u32x2>(other, j0 - plane) : zero;
+        const u32x2 zp = zp_in ? at<u32x2>(other, j0 + plane) : zero;
+        const uint32_t e = e_in ? (uint32_t)at<uint16_t>(other, je) : 0u;
+        return heatbath_quad_f16(zm, cen, zp, ym, yp, e, p, j0, h, chain, k0, k1);
+    } else {
+        const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 cen = St::ld4(other, j0);
+        const float4 ym = ym_in ? St::ld4(other, j0 - lh) : zero;
+        const float4 yp = yp_in ? St::ld4(other, j0 + lh) : zero;
+        const float4 zm = zm_in ? St::ld4(other, j0 - plane) : zero;
+        const float4 zp = zp_in ? St::ld4(other, j0 + plane) : zero;
+        const float e = e_in ? St::ld(other, je) : 0.f;
+        return heatbath_quad(zm, cen, zp, ym, yp, e, p, j0, h, chain, k0, k1);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Wave64 FP64 sum by DPP data movement (each 32-bit half moved separately,

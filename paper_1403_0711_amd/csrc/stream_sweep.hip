@@ -111,8 +111,6 @@ __device__ __forceinline__ void lds_load_b32(__amdgpu_buffer_rsrc_t r, lds_ptr_t
 // wait only for themselves (lgkmcnt 0), inside the asm statement that issues
 // them, so no output register is left pending.  Addresses are LDS byte
 // addresses.
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t lds_addr(const void* p) { return (uint32_t)(size_t)(lds_ptr_t)p; }
 
@@ -153,62 +151,6 @@ __device__ __forceinline__ void lds_read_entry(uint32_t av, uint32_t aq, uint32_
         v = (float)__builtin_bit_cast(_Float16, (uint16_t)r);
     Qi = __builtin_bit_cast(double, q);
     Si = __builtin_bit_cast(double, sv);
-}
-
-// FP16 storage: the update of heatbath_quad on raw halves (element k of a
-// quad in half k & 1 of word k >> 1).  Each f16 term joins its FP32 sum in
-// one mixed-precision FMA, value * 1 + sum: the exact conversion and the
-// FP32 add of the float path, rounded once as that add is, in the same
-// order, so the result is bit for bit heatbath_quad's.
-template <bool kHi>
-__device__ __forceinline__ float add_f16(uint32_t w, float acc) {  // half kHi of w, plus acc
-    float r;
-    if constexpr (kHi)
-        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(acc));
-    else
-        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(acc));
-    return r;
-}
-template <bool kHiA, bool kHiB>
-__device__ __forceinline__ float add_f16_pair(uint32_t a, uint32_t b) {  // half kHiA of a plus half kHiB of b
-    float r;
-    if constexpr (!kHiA && !kHiB)
-        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
-    else if constexpr (!kHiA && kHiB)
-        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
-    else if constexpr (kHiA && !kHiB)
-        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
-    else
-        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ float4 heatbath_quad_f16(u32x2 bm, u32x2 bc, u32x2 bn, u32x2 up, u32x2 dn, uint32_t e,
-                                                    uint32_t p, uint32_t j0, uint32_t h, uint32_t chain, uint32_t k0,
-                                                    uint32_t k1) {
-    float a0, a1, a2, a3;  // e + x, x + y, y + z, z + w (p = 0); x + y, y + z, z + w, w + e (p = 1)
-    if (p == 0) {
-        a0 = add_f16_pair<false, false>(e, bc[0]);
-        a1 = add_f16_pair<false, true>(bc[0], bc[0]);
-        a2 = add_f16_pair<true, false>(bc[0], bc[1]);
-        a3 = add_f16_pair<false, true>(bc[1], bc[1]);
-    } else {
-        a0 = add_f16_pair<false, true>(bc[0], bc[0]);
-        a1 = add_f16_pair<true, false>(bc[0], bc[1]);
-        a2 = add_f16_pair<false, true>(bc[1], bc[1]);
-        a3 = add_f16_pair<true, false>(bc[1], e);
-    }
-    const uint4 r = philox4x32_10(j0 >> 2, h, chain, 0u, k0, k1);
-    const float sixth = 1.0f / 6.0f;
-    float4 out;
-    out.x = fmaf(add_f16<false>(bn[0], add_f16<false>(bm[0], add_f16<false>(dn[0], add_f16<false>(up[0], a0)))),
-                 sixth, heatbath_noise(r.x));
-    out.y = fmaf(add_f16<true>(bn[0], add_f16<true>(bm[0], add_f16<true>(dn[0], add_f16<true>(up[0], a1)))), sixth,
-                 heatbath_noise(r.y));
-    out.z = fmaf(add_f16<false>(bn[1], add_f16<false>(bm[1], add_f16<false>(dn[1], add_f16<false>(up[1], a2)))),
-                 sixth, heatbath_noise(r.z));
-    out.w = fmaf(add_f16<true>(bn[1], add_f16<true>(bm[1], add_f16<true>(dn[1], add_f16<true>(up[1], a3)))), sixth,
-                 heatbath_noise(r.w));
-    return out;
 }
 
 // s_waitcnt immediates (gfx9 encoding): vmcnt in bits 3:0 and 15:14, expcnt
