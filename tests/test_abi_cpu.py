@@ -59,4 +59,5 @@ def test_null_handles_are_rejected(lib):
     assert lib.energy_estimate(None, None, None, None, None) == 1
     assert lib.lattice_set_charge_sets(None, 1, None, None, None) == 1
     assert lib.lattice_energy_estimate_set(None, 0, None, None, None, None) == 1
+    assert lib.lattice_get_sample_path(None, None) == 1
     lib.lattice_destroy(None)

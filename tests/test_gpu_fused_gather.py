@@ -73,10 +73,13 @@ CASES = [
     ((72, 9, 40), "bf16", 16, 2, True),      # 16-row tiles over 9 rows
     ((520, 12, 5), "fp32", 0, 5, True),      # short lists: a 64-entry LDS stage keeps 3 workgroups per CU
     ((8, 1, 3), "fp32", 0, 2, True),         # one row per plane, one quad per row
+    ((64, 24, 20), "fp32", 1, 9, 2),         # one plane per workgroup: the list is read after the last step
+    ((64, 24, 20), "fp16", 2, 0, 0),         # two planes: the list is waited for in the last step
+    ((200, 37, 33), "bf16", 3, 6, 2),
 ]
 
 
-@pytest.mark.parametrize("shape,storage,slab,tile,xcd", CASES)
+@pytest.mark.parametrize("shape,storage,slab,tile,xcd", CASES)  # xcd: workgroup order (bool = 0 / 1)
 def test_fused_gather_matches_separate_and_oracle(lat_mod, shape, storage, slab, tile, xcd):
     print(f"[gpu] fused gather {shape} {storage} slab={slab} tile={tile} xcd={xcd}", flush=True)
     xyz, q = _charges(shape, 60 if tile == 5 else 300, 11)
