@@ -30,6 +30,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -89,15 +90,23 @@ KERNEL_SOURCES = {
 }
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and whitespace (the sources contain no
+    string literal with a comment marker)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return "".join(text.split())
+
+
 def sources_hash(kname: str) -> str:
-    """Hash of the HIP sources a kernel is built from, to tell whether stored
-    counters are stale."""
+    """Hash of the code (comments and whitespace removed) of the HIP sources a
+    kernel is built from, to tell whether stored counters are stale."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1403_0711_amd", "csrc")
     for n in KERNEL_SOURCES.get(kname, []) + _COMMON_SOURCES:
-        with open(os.path.join(csrc, n), "rb") as f:
+        with open(os.path.join(csrc, n), encoding="utf-8") as f:
             h.update(n.encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

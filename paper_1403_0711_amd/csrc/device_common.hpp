@@ -263,7 +263,6 @@ struct StoreF16 {
 };
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // FP16 storage: the update of heatbath_quad on raw halves (element k of a
 // quad in half k & 1 of word k >> 1).  Each f16 term joins its FP32 sum in

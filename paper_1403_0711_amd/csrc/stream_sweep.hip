@@ -7,12 +7,11 @@
 // producer wave; a compute wave holds a 32-quad strip of two rows of the
 // same parity, so the x-pairing of the update is uniform per wave.  A tile
 // as wide as the box's rows makes every plane of the tile one contiguous run
-// of memory.  The
-// producer copies each plane of the other colour that the tile needs (its
-// kTY rows, the halo rows y0-1 and y0+kTY, and the quads left and right of
-// the tile) with `buffer_load ... lds`, which writes LDS without passing
-// through registers, into a ring of R plane slots (R = 5..7), R-3 planes
-// ahead of the plane being updated.  Its only memory operations are these
+// of memory.  The producer copies each plane of the other colour that the
+// tile needs (its kTY rows, the halo rows y0-1 and y0+kTY, and the quads
+// left and right of the tile) with `buffer_load ... lds`, which writes LDS
+// without passing through registers, into a ring of R plane slots
+// (R = 5..7), R-3 planes ahead of the plane being updated.  Its only memory operations are these
 // loads, which complete in order, so a wait that leaves the newest planes in
 // flight (vmcnt = their loads) is exact.  The compute waves read the 7-point
 // neighbourhood from LDS and only store to HBM: they never wait for a load
@@ -46,10 +45,10 @@
 // in flight.  The colour-1 part of a run's last sample, with no next sweep,
 // comes from gather_tail, whose lanes add the same entries in the same
 // order from the field in memory: every partial is the same whichever
-// kernel wrote it.  A sample completed by a
-// colour-0 launch is finalized by workgroup 0 of the colour-1 launch that
-// follows (fin set), while its first planes load; partials are kept in two
-// buffers by sample parity, so that launch may open the next sample.
+// kernel wrote it.  A sample completed by a colour-0 launch is finalized by
+// workgroup 0 of the colour-1 launch that follows (fin set), while its first
+// planes load; partials are kept in two buffers by sample parity, so that
+// launch may open the next sample.
 
 #include "device_common.hpp"
 #include "kernels.hpp"
