@@ -35,8 +35,8 @@ struct SweepArgs {
     const uint32_t* tdev;  // if set, h += 2 * tdev[0] (sweep counter on the device)
     // streaming kernel: fused gather of the charged sites of the other
     // colour (1 - c) over per-tile lists (g_off: tiles + 1 absolute offsets;
-    // g_key: the site's plane within the tile's slab << 16 | its byte offset
-    // in a ring slot; g_Q, g_S; g_n entries in the arrays), one (X, Y)
+    // g_key: the step of the tile's walk that updates the site's plane << 16
+    // | its byte offset in a ring slot; g_Q, g_S; g_n entries in the arrays), one (X, Y)
     // partial per tile into g_part.  g_cap: LDS entries staged per workgroup
     // (a multiple of 64, at least the longest tile list, at most 256).
     // Null: no gather.
@@ -52,6 +52,9 @@ struct SweepArgs {
 constexpr uint32_t kGatherEntryBytes = 20;  // staged key (4 B), Q and S (8 B each)
 constexpr int kZslabTiles = 8;
 constexpr int kStreamTiles = 10;  // tile configurations of the streaming slab kernel
+// streaming kernel: odd slabs walk down z (the fused gather's lists follow
+// each tile's walk order)
+constexpr bool kStreamAltZ = true;
 hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream);
 hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream);  // tile 0 .. kStreamTiles-1
 // Shape of a streaming-kernel tile configuration at element size esz: quads

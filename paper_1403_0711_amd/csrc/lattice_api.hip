@@ -88,7 +88,7 @@ struct lattice {
         uint32_t tile = 0, slab = 0, blocks = 0;
         uint32_t n = 0, cap = 0;  // entries in all; LDS entries staged per workgroup
         uint32_t* d_off = nullptr;
-        uint32_t* d_key = nullptr;  // staged key: plane in slab << 16 | ring-slot byte offset
+        uint32_t* d_key = nullptr;  // staged key: walk step << 16 | ring-slot byte offset
         uint32_t* d_j = nullptr;    // the site in its colour array (for gather_tail)
         double* d_Q = nullptr;
         double* d_S = nullptr;
@@ -231,8 +231,9 @@ static int fused_gather_prepare(lattice* L) {
     const lattice::HostCharges& hc = *L->host_charges;
     const size_t n = hc.site.size();
     // sort key of every charged site: its colour, its tile, its plane
-    // staged key: plane within the slab << 16 | byte offset of the site in
-    // a ring slot (rows y0-1 .. y0+ty of tq + 2 quads: halo quad first)
+    // staged key: the step of the tile's walk that updates the site's plane
+    // << 16 | byte offset of the site in a ring slot (rows y0-1 .. y0+ty of
+    // tq + 2 quads: halo quad first); a tile's list is sorted by step
     if (slab > 0xFFFFu) return LAT_OK;
     const uint32_t row_bytes = (tq + 2u) * 4u * (uint32_t)L->esz;
     std::vector<uint64_t> key_of(n);
@@ -246,8 +247,11 @@ static int fused_gather_prepare(lattice* L) {
         tile_of[i] = bx + nbx * (by + nby * bz);
         j_of[i] = j;
         const uint32_t off = (y - by * ty + 1u) * row_bytes + (jx - 4u * tq * bx + 4u) * (uint32_t)L->esz;
-        packed_of[i] = ((z - bz * slab) << 16) | off;
-        key_of[i] = ((uint64_t)c * blocks + tile_of[i]) * lz + z;
+        // the step at which the tile's walk updates plane z (odd slabs walk down)
+        const uint32_t z0 = bz * slab, z1 = std::min(z0 + slab, lz);
+        const uint32_t step = kStreamAltZ && (bz & 1u) ? z1 - 1u - z : z - z0;
+        packed_of[i] = (step << 16) | off;
+        key_of[i] = ((uint64_t)c * blocks + tile_of[i]) * lz + step;
         n0 += c ? 0u : 1u;
     }
     std::vector<uint32_t> order(n);

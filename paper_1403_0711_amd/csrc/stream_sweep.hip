@@ -204,7 +204,7 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
     uint32_t lz, uint32_t zc, uint32_t c, uint32_t h, uint32_t k0, uint32_t k1, uint32_t chain,
     uint32_t xcd_order, const uint32_t* __restrict__ tdev, const uint32_t* __restrict__ g_off,
     const uint32_t* __restrict__ g_key, const double* __restrict__ g_Q, const double* __restrict__ g_S,
-    double* __restrict__ g_part, uint32_t g_n, uint32_t g_cap, SampleFinalize fin) {
+    double* __restrict__ g_part, uint32_t g_n, uint32_t g_cap, SampleFinalize fin, uint32_t zalt) {
     using S = Stream<St, kM, kTY, kRing>;
     using T = typename St::T;
     __shared__ __align__(16) unsigned char ring[S::kRing * S::kSlot];
@@ -231,6 +231,13 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
     const uint32_t q0 = bx * S::kTX, y0 = by * kTY, z0 = bz * zc;
     const uint32_t z1 = min(z0 + zc, lz);
     const uint32_t n = z1 - z0;  // planes this workgroup updates (>= 1)
+    // walk direction: odd slabs walk down (zalt), so that the two slabs on
+    // either side of a slab boundary read the planes there at the same end of
+    // their walks, close in time (one of the two reads then finds them in L2).
+    // Walk index l (plane l in slot l % R) -> plane z0 - 1 + l going up,
+    // z1 - l going down; step s updates the plane of walk index s + 1.
+    const bool down = zalt && (bz & 1u);
+    auto plane_of = [&](uint32_t l) -> int { return down ? (int)z1 - (int)l : (int)z0 - 1 + (int)l; };
     const uint32_t plane = ly * lh, plane_b = plane * S::kEsz;
     const uint32_t tile = bx + nbx * (by + nby * bz);
     const bool finalize = fin.part != nullptr && blockIdx.x == 0;  // the previous sample, in the first workgroup
@@ -258,20 +265,24 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
                         : kNoLoad;
             every = every && __builtin_amdgcn_ballot_w64(ok) != 0;
         }
-        // whether plane l = z0-1+l is loaded (the ghost planes z0-1 = -1 and
-        // lz are not; planes past z1 are not needed)
-        auto loads = [&](uint32_t l) -> bool { return l <= n + 1u && !(l == 0 && z0 == 0) && z0 + l - 1u < lz; };
-        // plane l into slot l % kRing
+        // whether walk plane l is loaded (the ghost planes -1 and lz are not;
+        // planes past the slab's halo are not needed)
+        auto loads = [&](uint32_t l) -> bool {
+            const int zp = plane_of(l);
+            return l <= n + 1u && zp >= 0 && zp < (int)lz;
+        };
+        // walk plane l into slot l % kRing
         auto produce = [&](uint32_t l) {
             unsigned char* dst = ring + (l % S::kRing) * S::kSlot;
-            if (l > n + 1u || (l == 0 && z0 == 0)) return;  // not needed, or slot 0 still zero
-            const uint32_t zp = z0 + l - 1u;
-            if (zp >= lz) {  // the ghost plane past the box: only its kTY rows are read
-                for (uint32_t i = lane; i < kTY * S::kRB / 16; i += 64)
+            if (l > n + 1u) return;  // not needed
+            const int zp = plane_of(l);
+            if (zp < 0 || zp >= (int)lz) {  // a ghost plane beyond the box
+                if (l == 0) return;         // slot 0 is still zero
+                for (uint32_t i = lane; i < kTY * S::kRB / 16; i += 64)  // only its kTY rows are read
                     reinterpret_cast<uint4*>(dst + S::kRB)[i] = make_uint4(0u, 0u, 0u, 0u);
                 return;
             }
-            const uint32_t soff = zp * plane_b;
+            const uint32_t soff = (uint32_t)zp * plane_b;
 #pragma unroll
             for (int i = 0; i < S::kNI; ++i)
                 if (off[i] != kNoLoad) {
@@ -328,8 +339,9 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
                 key[k] = i < ng ? lds_read_u32(a_key + 4u * i) : kNoEntry;
             }
         };
-        // plane z0 + s, in ring slot s + 1: gathered in step s + 1 (or after
-        // the last step), before step s + 2 refills the slot
+        // the plane of step s (walk plane s + 1, in ring slot s + 1): gathered
+        // in step s + 1 (or after the last step), before step s + 2 refills
+        // the slot; a key's plane field is that step s
         auto gather_plane = [&](uint32_t s) {
             const uint32_t slot = a_ring + ((s + 1u) % S::kRing) * S::kSlot;
 #pragma unroll
@@ -397,10 +409,13 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
         for (uint32_t s = 0; s < n; ++s) {
             __syncthreads();  // b_s
             if (!active) continue;
-            const uint32_t z = z0 + s;
-            const unsigned char* pm = ring + (s % S::kRing) * S::kSlot + qoff;
+            const uint32_t z = down ? z1 - 1u - s : z0 + s;
+            // walk planes s, s + 1, s + 2: planes z -+ 1, z, z +- 1
+            const unsigned char* pw0 = ring + (s % S::kRing) * S::kSlot + qoff;
             const unsigned char* pc = ring + ((s + 1u) % S::kRing) * S::kSlot + qoff;
-            const unsigned char* pn = ring + ((s + 2u) % S::kRing) * S::kSlot + qoff;
+            const unsigned char* pw2 = ring + ((s + 2u) % S::kRing) * S::kSlot + qoff;
+            const unsigned char* pm = down ? pw2 : pw0;  // plane z - 1
+            const unsigned char* pn = down ? pw0 : pw2;  // plane z + 1
             const uint32_t p = __builtin_amdgcn_readfirstlane((c + y + z) & 1u);  // uniform per wave
             const uint32_t j0 = z * plane + rowj;
             float4 out;
@@ -441,7 +456,7 @@ static void launch_stream_cfg(const SweepArgs& a, const typename St::T* other, t
     const uint32_t dyn = a.g_key ? kGatherEntryBytes * a.g_cap : 0u;
     hipLaunchKernelGGL((halfsweep_stream<St, kM, kTY, kRing, kNT>), dim3(nb), dim3(S::kThreads), dyn, stream, other,
                        own, a.lh, a.ly, a.lz, zc, a.c, a.h, a.k0, a.k1, a.chain, a.xcd_order, a.tdev, a.g_off,
-                       a.g_key, a.g_Q, a.g_S, a.g_part, a.g_n, a.g_cap, a.fin);
+                       a.g_key, a.g_Q, a.g_S, a.g_part, a.g_n, a.g_cap, a.fin, kStreamAltZ ? 1u : 0u);
 }
 
 // Tile configurations: tile width 32m quads, rows, ring slots, non-temporal
