@@ -1,0 +1,155 @@
+// The autotuner: times every sweep kernel and tuning that can handle a box
+// on scratch memory and keeps the fastest; choices are cached per (box,
+// storage).
+
+#include "lattice_impl.hpp"
+
+// ---------------------------------------------------------------------------
+// Autotuner: times every sweep kernel and tuning that can handle a box on
+// scratch memory, keeps the fastest; choices are cached per (box, storage).
+// ---------------------------------------------------------------------------
+struct TuneChoice {
+    int variant;
+    uint32_t slab, tile, xcd;
+    double ms;
+};
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int64_t, int64_t, int64_t, int>, TuneChoice> g_tune_cache;
+
+// Candidates in order of preference: the first is the library default for
+// the box; a later one replaces the current best only if it is more than 3%
+// faster, so that choices do not flip on timing noise.
+static std::vector<TuneChoice> tune_candidates(const lattice* L) {
+    std::vector<TuneChoice> c;
+    const uint64_t V = (uint64_t)L->vh * 2;
+    const bool resident_ok = L->n_sets == 1 && !L->offl;  // the resident kernel measures one on-lattice set
+    if (V <= kResidentMaxSites && resident_ok) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
+    if (L->lh % 4 != 0) {
+        if (V > kResidentMaxSites && V <= (uint64_t)1 << 18 && resident_ok)
+            c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
+        c.push_back({LAT_SWEEP_GENERIC, 0, 0, 1, 0});
+        return c;
+    }
+    const bool slab_ok = (size_t)L->vh * L->esz < ((size_t)1 << 31);
+    if (slab_ok && (size_t)2 * L->vh * L->esz >= ((size_t)256 << 20)) {
+        lattice d = *L;  // the library's own choice for the box
+        d.slab = 0;
+        d.tile = kTileDefault;
+        d.xcd_order = -1;
+        c.push_back({LAT_SWEEP_STREAM, d.resolved_slab(LAT_SWEEP_STREAM), d.resolved_tile(LAT_SWEEP_STREAM),
+                     d.resolved_xcd(LAT_SWEEP_STREAM), 0});
+    }
+    c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
+    if (V > kResidentMaxSites && V <= (uint64_t)1 << 18 && resident_ok)
+        c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
+    if (slab_ok)
+        for (uint32_t tile = 0; tile < (uint32_t)kStreamTiles; ++tile)
+            for (uint32_t slab : {16u, 24u, 32u, 48u})
+                for (uint32_t xcd : {1u, 2u, 0u})
+                    if (slab <= L->lz) c.push_back({LAT_SWEEP_STREAM, slab, tile, xcd, 0});
+    if (slab_ok)
+        for (uint32_t tile : {0u, 1u, 7u})
+            for (uint32_t slab : {8u, 16u, 32u})
+                if (slab <= L->lz) c.push_back({LAT_SWEEP_ZSLAB, slab, tile, 1, 0});
+    if (fused_sweep_supported(L->lh, (uint32_t)L->ly))
+        for (uint32_t slab : {16u, 32u})
+            if (slab <= L->lz) c.push_back({LAT_SWEEP_FUSED, slab, 0, 1, 0});
+    return c;
+}
+
+static void apply_choice(lattice* L, const TuneChoice& ch) {
+    L->variant = ch.variant;
+    L->slab = ch.slab;
+    L->tile = ch.tile;
+    L->xcd_order = (int)ch.xcd;
+}
+
+static int autotune(lattice* L, int64_t reps, TuneChoice* out) {
+    const auto key = std::make_tuple(L->lx, L->ly, L->lz, L->storage);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            return LAT_OK;
+        }
+    }
+    const std::vector<TuneChoice> cands = tune_candidates(L);
+    if (fused_sweep_supported(L->lh, (uint32_t)L->ly))
+        if (hipError_t e = prepare_fused_sweep()) return hip_fail(e, "fused sweep set-up");
+    const size_t fbytes = round_up(2 * (size_t)L->vh * L->esz, 256);
+    void* scratch = L->mem.alloc(fbytes);
+    void* scratch_alt = L->mem.alloc(round_up((size_t)L->vh * L->esz, 256));
+    if (!scratch || !scratch_alt) {
+        L->mem.release(scratch);
+        L->mem.release(scratch_alt);
+        return set_error(LAT_ERR_ALLOC, "allocation of autotuning scratch failed");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMemsetAsync(scratch, 0, fbytes, L->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    TuneChoice best{LAT_SWEEP_AUTO, 0, 0, 1, 1e30};
+    int rc = LAT_OK;
+    for (size_t i = 0; i < cands.size() && e == hipSuccess && rc == LAT_OK; ++i) {
+        lattice tmp = *L;  // shallow copy: same sizes and streams, scratch field, no charges
+        tmp.field = scratch;
+        tmp.c1alt = scratch_alt;
+        tmp.alt_current = false;
+        tmp.t = 0;
+        tmp.n_meas = 0;
+        apply_choice(&tmp, cands[i]);
+        auto run = [&](int64_t n) {
+            if (tmp.variant == LAT_SWEEP_RESIDENT) return enqueue_resident(&tmp, n, 0, 1);
+            for (int64_t k = 0; k < n; ++k)
+                if (int r = enqueue_sweep(&tmp)) return r;
+            return (int)LAT_OK;
+        };
+        rc = run(1);
+        if (rc == LAT_OK) e = hipEventRecord(e0, L->stream);
+        if (rc == LAT_OK && e == hipSuccess) rc = run(reps);
+        if (rc == LAT_OK && e == hipSuccess) e = hipEventRecord(e1, L->stream);
+        if (rc == LAT_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (rc == LAT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (rc == LAT_OK && e == hipSuccess && ms / reps < 0.97 * best.ms) {
+            best = cands[i];
+            best.ms = ms / reps;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(L->stream);
+    L->mem.release(scratch);
+    L->mem.release(scratch_alt);
+    if (rc != LAT_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotuning");
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    *out = best;
+    return LAT_OK;
+}
+
+extern "C" {
+
+int lattice_autotune(lattice_t* L, int64_t reps, int* variant, int64_t* planes, int* tile, int* xcd_order,
+                     double* ms_per_sweep) {
+    if (int r = check_lattice(L)) return r;
+    if (reps < 1 || reps > 1000) return set_error(LAT_ERR_ARG, "reps must be in [1, 1000]");
+    TuneChoice ch;
+    if (int r = autotune(L, reps, &ch)) return r;
+    if (ch.variant == LAT_SWEEP_FUSED)
+        if (int r = lattice_set_variant(L, LAT_SWEEP_FUSED)) return r;  // allocates the second colour-1 array
+    apply_choice(L, ch);
+    graphs_reset(L);
+    if (variant) *variant = ch.variant;
+    if (planes) *planes = ch.slab;
+    if (tile) *tile = (int)ch.tile;
+    if (xcd_order) *xcd_order = (int)ch.xcd;
+    if (ms_per_sweep) *ms_per_sweep = ch.ms;
+    return LAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// Host side of the sample gather fused into the streaming kernel: the
+// charge list regrouped per colour, tile and walk step, uploaded once per
+// tiling, and the tail that completes a run's last sample.
+
+#include "lattice_impl.hpp"
+
+namespace latcoul {
+
+void fused_gather_release(lattice* L) {
+    L->mem.release(L->fg.d_off);
+    L->mem.release(L->fg.d_key);
+    L->mem.release(L->fg.d_j);
+    L->mem.release(L->fg.d_Q);
+    L->mem.release(L->fg.d_S);
+    L->mem.release(L->fg.d_part);
+    L->fg = lattice::FusedGather();
+}
+
+// Whether samples of this lattice are gathered inside the streaming kernel:
+// one on-lattice charge set and the lists built for the current tiling.
+bool fused_gather_on(const lattice* L) {
+    return L->fg.ready && L->effective_variant() == LAT_SWEEP_STREAM && L->n_sets == 1 && !L->offl &&
+           L->fg.tile == L->resolved_tile(LAT_SWEEP_STREAM) && L->fg.slab == L->resolved_slab(LAT_SWEEP_STREAM);
+}
+
+// Resident workgroups per CU of a kernel with `lds` bytes of LDS and `waves`
+// waves per workgroup (160 KiB of LDS and 32 wave slots per CU).
+static uint32_t workgroups_per_cu(uint32_t lds, uint32_t waves) {
+    return std::min<uint32_t>(lds ? 163840u / lds : 32u, 32u / waves);
+}
+
+// Build the per-tile lists of the fused gather for the current tiling (host
+// sort of the aggregated list, one upload); outside any capture.  Without
+// them (other kernels, several or off-lattice sets, a tile list too long to
+// stage in LDS without costing the sweep kernel a resident workgroup,
+// allocation failure) the samples go through the separate gather.
+int fused_gather_prepare(lattice* L) {
+    const uint32_t tile = L->resolved_tile(LAT_SWEEP_STREAM), slab = L->resolved_slab(LAT_SWEEP_STREAM);
+    if (L->effective_variant() != LAT_SWEEP_STREAM || L->n_sets != 1 || L->offl ||
+        !L->host_charges || L->host_charges->site.size() != L->n_sites)
+        return LAT_OK;
+    if (L->fg.tried && L->fg.tile == tile && L->fg.slab == slab) return LAT_OK;
+    fused_gather_release(L);
+    graphs_reset(L);
+    L->fg.tried = true;
+    L->fg.tile = tile;
+    L->fg.slab = slab;
+    StreamTileShape sh;
+    if (!stream_tile_geometry(tile, L->esz, &sh)) return LAT_OK;
+    const uint32_t tq = sh.quads, ty = sh.rows;
+    const uint32_t nq = L->lh / 4, ly = (uint32_t)L->ly, lz = (uint32_t)L->lz;
+    const uint32_t nbx = (nq + tq - 1) / tq, nby = (ly + ty - 1) / ty, nbz = (lz + slab - 1) / slab;
+    const uint32_t blocks = nbx * nby * nbz;
+    const uint32_t plane = (uint32_t)L->ly * L->lh;
+    const lattice::HostCharges& hc = *L->host_charges;
+    const size_t n = hc.site.size();
+    // sort key of every charged site: its colour, its tile, its plane
+    // staged key: the step of the tile's walk that updates the site's plane
+    // << 16 | byte offset of the site in a ring slot (rows y0-1 .. y0+ty of
+    // tq + 2 quads: halo quad first); a tile's list is sorted by step
+    if (slab > 0xFFFFu) return LAT_OK;
+    const uint32_t row_bytes = (tq + 2u) * 4u * (uint32_t)L->esz;
+    std::vector<uint64_t> key_of(n);
+    std::vector<uint32_t> tile_of(n), j_of(n), packed_of(n);
+    size_t n0 = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const uint32_t c = hc.site[i] >= L->vh ? 1u : 0u;
+        const uint32_t j = hc.site[i] - c * L->vh;
+        const uint32_t z = j / plane, rem = j - z * plane, y = rem / L->lh, jx = rem - y * L->lh;
+        const uint32_t bx = (jx / 4) / tq, by = y / ty, bz = z / slab;
+        tile_of[i] = bx + nbx * (by + nby * bz);
+        j_of[i] = j;
+        const uint32_t off = (y - by * ty + 1u) * row_bytes + (jx - 4u * tq * bx + 4u) * (uint32_t)L->esz;
+        // the step at which the tile's walk updates plane z (odd slabs walk down)
+        const uint32_t z0 = bz * slab, z1 = std::min(z0 + slab, lz);
+        const uint32_t step = kStreamAltZ && (bz & 1u) ? z1 - 1u - z : z - z0;
+        packed_of[i] = (step << 16) | off;
+        key_of[i] = ((uint64_t)c * blocks + tile_of[i]) * lz + step;
+        n0 += c ? 0u : 1u;
+    }
+    std::vector<uint32_t> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key_of[a] < key_of[b]; });
+    // offsets: colour 0 at [0, blocks], colour 1 at [blocks + 1, 2 blocks + 1]
+    std::vector<uint32_t> off(2 * ((size_t)blocks + 1), 0u), key(n), jv(n);
+    std::vector<double> Q(n), S(n);
+    for (size_t k = 0; k < n; ++k) {
+        const uint32_t i = order[k];
+        const size_t c = k < n0 ? 0 : 1;
+        off[c * (blocks + 1) + tile_of[i] + 1] += 1;
+        key[k] = packed_of[i];
+        jv[k] = j_of[i];
+        Q[k] = hc.Q[i];
+        S[k] = hc.S[i];
+    }
+    uint32_t longest = 0;
+    for (size_t t = 0; t < 2 * ((size_t)blocks + 1); ++t) longest = std::max(longest, off[t]);
+    const uint64_t cap = ((uint64_t)longest + 63u) / 64u * 64u;
+    if (cap > 256u) return LAT_OK;  // the kernel holds up to 4 x 64 keys per tile in registers
+    const uint64_t lds = sh.lds + (uint64_t)kGatherEntryBytes * cap;
+    if (lds > 65536u || workgroups_per_cu((uint32_t)lds, sh.waves) < workgroups_per_cu(sh.lds, sh.waves) ||
+        (uint64_t)n * 8u >= (1ull << 32))
+        return LAT_OK;  // the separate gather
+    off[blocks + 1] = (uint32_t)n0;
+    for (size_t c = 0; c < 2; ++c)
+        for (size_t t = 0; t < blocks; ++t) off[c * (blocks + 1) + t + 1] += off[c * (blocks + 1) + t];
+    lattice::FusedGather g = L->fg;
+    g.d_off = static_cast<uint32_t*>(L->mem.alloc(off.size() * 4));
+    g.d_key = static_cast<uint32_t*>(L->mem.alloc(std::max<size_t>(n, 1) * 4));
+    g.d_j = static_cast<uint32_t*>(L->mem.alloc(std::max<size_t>(n, 1) * 4));
+    g.d_Q = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
+    g.d_S = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
+    g.d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * 64));
+    L->fg = g;  // released by fused_gather_release on any failure below
+    if (!g.d_off || !g.d_key || !g.d_j || !g.d_Q || !g.d_S || !g.d_part) {
+        fused_gather_release(L);
+        L->fg.tried = true;  // the separate gather for this tiling
+        L->fg.tile = tile;
+        L->fg.slab = slab;
+        return LAT_OK;
+    }
+    hipError_t e = hipMemcpyAsync(g.d_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_key, key.data(), n * 4, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_j, jv.data(), n * 4, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_Q, Q.data(), n * 8, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_S, S.data(), n * 8, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) {
+        fused_gather_release(L);
+        return hip_fail(e, "fused gather list upload");
+    }
+    L->fg.ready = true;
+    L->fg.tile = tile;
+    L->fg.slab = slab;
+    L->fg.blocks = blocks;
+    L->fg.n = (uint32_t)n;
+    L->fg.cap = (uint32_t)cap;
+    return LAT_OK;
+}
+
+
+// The open sample's colour-1 sites from memory (no sweep follows it), then
+// its finalize as sample m.
+int enqueue_fused_tail(lattice* L, hipStream_t stream, uint32_t m, const uint32_t* mdev) {
+    const lattice::FusedGather& g = L->fg;
+    double* buf = g.d_part + (size_t)(m & 1u) * 4 * g.blocks;  // sample m's partials, colour 0 then 1
+    GatherTailArgs a{L->c1cur(), L->storage, g.blocks, g.d_off + g.blocks + 1, g.d_j, g.d_Q, g.d_S,
+                     buf + 2 * (size_t)g.blocks};
+    hipError_t e = launch_gather_tail(a, stream);
+    if (e == hipSuccess)
+        e = launch_finalize_measure(buf, 2 * g.blocks, 1u, L->d_bins, m, (uint32_t)L->bin_size, mdev,
+                                    L->last_xy(), (uint32_t)L->bin_cap, stream);
+    if (e != hipSuccess) return hip_fail(e, "measure launch");
+    return LAT_OK;
+}
+
+}  // namespace latcoul

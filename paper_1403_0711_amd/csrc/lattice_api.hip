@@ -1,324 +1,25 @@
 // C-ABI runtime of the heat-bath Coulomb-energy estimator: lattice objects,
-// charge upload, sweep scheduling, sample bins and the final estimate.
-// The kernels live in sweep_kernels.hip, fused_sweep.hip, measure_kernels.hip
-// and batch_kernels.hip.
+// charge upload, sweep scheduling, graph capture, sample bins and the final
+// estimate.  The kernels live in stream_sweep.hip, sweep_kernels.hip,
+// fused_sweep.hip, measure_kernels.hip, offlattice_kernels.hip and
+// batch_kernels.hip; the fused gather's host side in fused_gather.hip, the
+// autotuner in autotune.hip.
 
-#include <algorithm>
-#include <cmath>
-#include <cstring>
-#include <map>
-#include <memory>
-#include <mutex>
-#include <string>
-#include <tuple>
-#include <vector>
+#include "lattice_impl.hpp"
 
-#include "kernels.hpp"
-#include "lattice_coulomb.h"
-#include "runtime_common.hpp"
+namespace latcoul {
 
-using namespace latcoul;
-
-// largest box that AUTO runs with the one-workgroup resident kernel
-constexpr uint64_t kResidentMaxSites = 16384;
-constexpr int64_t kMaxChargeSets = 65535;  // charge sets per lattice (a grid dimension of the gather)
-constexpr uint32_t kTileDefault = 0xFFFFFFFFu;  // lattice_set_tuning(tile = -1): library default
-constexpr uint32_t kStreamTileFullRow96 = 9;        // streaming kernel: 96-quad tiles, non-temporal stores
-constexpr uint32_t kStreamTileFullRow96Cached = 6;  // 96-quad tiles, ordinary stores
-constexpr uint32_t kStreamTileCached = 3;           // 32 quads x 8 rows, 6-slot ring, ordinary stores
-
-// Planes per workgroup the slab kernels default to: 16 at FP32, where the
-// sweep is bound by memory traffic and short slabs balance the chip best; 32
-// at 16-bit storage, where arithmetic binds and longer slabs amortise each
-// workgroup's start-up.
-static uint32_t default_slab(size_t esz) { return esz == 4 ? 16u : 32u; }
-
-struct lattice {
-    int64_t lx = 0, ly = 0, lz = 0;
-    uint32_t lh = 0, vh = 0;
-    int storage = 0;
-    size_t esz = 4;
-    uint64_t seed = 0;
-    uint32_t chain = 0;
-    DeviceAllocator mem;
-    hipStream_t stream = nullptr;
-    void* field = nullptr;  // colour 0 then colour 1
-    // second colour-1 array for the fused sweep, which reads colour 1 from one
-    // array and writes the other; alt_current: the current colour 1 is there
-    void* c1alt = nullptr;
-    bool alt_current = false;
-    // charges, aggregated per site
-    int64_t n_raw = 0;
-    uint32_t n_sites = 0;
-    uint32_t* d_site = nullptr;
-    double* d_Q = nullptr;
-    double* d_S = nullptr;
-    double* d_partials = nullptr;
-    uint32_t meas_blocks = 1;
-    // charge sets sharing the chain: set k is list entries set_off[k] ..
-    // set_off[k+1]-1; bins of set k at d_bins + 2 * k * bin_cap
-    uint32_t n_sets = 1;
-    uint32_t* d_set_off = nullptr;
-    double* d_lastxy = nullptr;  // X, Y of the last sample, per set
-    // off-lattice charges (trilinear over the 8 corners of each cell)
-    bool offl = false;
-    uint32_t n_off = 0;
-    double* d_r = nullptr;     // 3 n_off positions
-    double* d_qo = nullptr;    // n_off charges
-    double* d_phit = nullptr;  // 4 n_off scratch (forces only)
-    double* d_fsum = nullptr;  // 3 n_off force sums (null: forces off)
-    double* d_fsq = nullptr;
-    int64_t force_base = 0;    // n_meas when the force sums were last cleared
-    // host copy of the aggregated list of a single on-lattice charge set
-    // (shared: copies of the handle made by the autotuner do not copy it)
-    struct HostCharges {
-        std::vector<uint32_t> site;
-        std::vector<double> Q, S;
-    };
-    std::shared_ptr<const HostCharges> host_charges;
-    // fused gather of the streaming kernel: the list split by colour and
-    // regrouped per tile and by plane, for one tile shape and slab (d_off:
-    // the colour-0 then the colour-1 offset tables, tiles + 1 each, into
-    // d_key / d_Q / d_S; d_part: two buffers, by sample parity, each the
-    // colour-0 then the colour-1 partials of one sample, 2 x tiles pairs)
-    struct FusedGather {
-        bool ready = false;
-        bool tried = false;  // lists considered for (tile, slab): ready, or the separate gather
-        bool last = false;  // the samples of the last sweep_and_measure took this path
-        uint32_t tile = 0, slab = 0, blocks = 0;
-        uint32_t n = 0, cap = 0;  // entries in all; LDS entries staged per workgroup
-        uint32_t* d_off = nullptr;
-        uint32_t* d_key = nullptr;  // staged key: walk step << 16 | ring-slot byte offset
-        uint32_t* d_j = nullptr;    // the site in its colour array (for gather_tail)
-        double* d_Q = nullptr;
-        double* d_S = nullptr;
-        double* d_part = nullptr;
-    } fg;
-    // How the fused gather takes part in one sweep: its colour-0 launch
-    // completes the open sample m (its colour-1 sites), which workgroup 0 of
-    // the colour-1 launch records (sample m + *mdev when captured); the
-    // colour-1 launch opens this sweep's sample m + 1 (its colour-0 sites;
-    // m is the last sample number, modulo 2^32, when none is open).
-    struct FusedStep {
-        bool finish = false, open = false;
-        uint32_t m = 0;
-        const uint32_t* mdev = nullptr;
-    };
-    // misc block: last X, Y (doubles at 64)
-    void* d_misc = nullptr;
-    // samples
-    double* d_bins = nullptr;
-    int64_t bin_cap = 0;
-    int64_t bin_size = 0;
-    int64_t n_meas = 0;
-    int64_t t = 0;
-    // captured chunks of sweeps (hipGraph) for boxes whose sweeps are short
-    struct SweepGraph {
-        hipGraphExec_t exec = nullptr;
-        int64_t K = 0, every = 0, bin_size = 0;
-        int variant = -1;
-        uint32_t slab = 0, tile = 0;
-        int xcd = 0;
-        const void* bins = nullptr;
-        const void* site = nullptr;
-        const void* gather = nullptr;  // per-tile lists of a fused gather, else null
-    };
-    SweepGraph g_therm, g_meas;
-    hipStream_t cap = nullptr;  // private capture stream
-    int graph_mode = 1;         // 0 never, 1 boxes up to 2^24 sites, 2 always
-    int variant = LAT_SWEEP_AUTO;
-    uint32_t slab = 0;       // planes per workgroup for the slab kernels (0: library default)
-    int xcd_order = -1;      // XCD-aware workgroup order for the slab kernels (-1: library default)
-    uint32_t tile = kTileDefault;  // tile configuration of the slab kernels
-
-    // the tile the slab kernel `v` runs: the set one, else the library's
-    // default.  Streaming kernel: at FP32 (bound by memory traffic) a
-    // full-row tile of 96 quads where it divides the row (every plane of a
-    // tile is then one contiguous run of memory), else 32 quads x 8 rows with
-    // a 6-slot ring; non-temporal stores only where one colour array alone
-    // fills the 256 MiB last-level cache (smaller ones keep part of the
-    // written colour there for the next half-sweep).
-    uint32_t resolved_tile(int v) const {
-        if (tile != kTileDefault) return tile;
-        if (v != LAT_SWEEP_STREAM) return 0u;
-        const bool wide = esz == 4 && (lh / 4) % 96 == 0;
-        const bool nt = (size_t)vh * esz >= ((size_t)256 << 20);
-        return wide ? (nt ? kStreamTileFullRow96 : kStreamTileFullRow96Cached) : (nt ? 0u : kStreamTileCached);
-    }
-    // the planes per workgroup and the workgroup order the slab kernel `v`
-    // runs: the set ones, else the library's defaults.  The streaming
-    // kernel's full-row FP32 tile measured fastest with 24 planes and each
-    // XCD taking a band of every slab's tiles, all XCDs moving through the
-    // slabs together (order 2; at 768^3 338 us per half-sweep against 342 us
-    // in the hardware's round-robin order and 354-361 us with a contiguous
-    // run of tiles per XCD); everything else with 16 (FP32) or 32 (16-bit)
-    // planes and a run of tiles per XCD (order 1).
-    bool full_row_default(int v) const {
-        return v == LAT_SWEEP_STREAM && esz == 4 && resolved_tile(v) == kStreamTileFullRow96;
-    }
-    uint32_t resolved_slab(int v) const { return slab ? slab : full_row_default(v) ? 24u : default_slab(esz); }
-    uint32_t resolved_xcd(int v) const { return xcd_order >= 0 ? (uint32_t)xcd_order : full_row_default(v) ? 2u : 1u; }
-    double* last_xy() { return d_lastxy ? d_lastxy : reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
-    uint32_t* counters() { return static_cast<uint32_t*>(d_misc); }  // [0] sweeps, [1] samples
-    void* c1main() const { return static_cast<char*>(field) + (size_t)vh * esz; }
-    void* c1cur() const { return alt_current ? c1alt : c1main(); }
-    int effective_variant() const {
-        if (variant != LAT_SWEEP_AUTO) return variant;
-        // a box one workgroup sweeps in a few microseconds: launch overhead
-        // would dominate, so run the whole call in one launch
-        if ((uint64_t)vh * 2 <= kResidentMaxSites && n_sets == 1 && !offl) return LAT_SWEEP_RESIDENT;
-        if (lh % 4 != 0) return LAT_SWEEP_GENERIC;
-        // boxes that spill out of the 256 MB last-level cache: z-marching slabs
-        // fed through LDS by a producer wave (colour arrays below 2 GiB)
-        const size_t bytes = (size_t)vh * esz;
-        return (2 * bytes >= ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) ? LAT_SWEEP_STREAM : LAT_SWEEP_QUAD;
-    }
-};
-
-static int check_lattice(const lattice* L) {
+int check_lattice(const lattice* L) {
     if (!L) return set_error(LAT_ERR_ARG, "null lattice handle");
     return LAT_OK;
 }
 
-static void graphs_reset(lattice* L);
-
-static void fused_gather_release(lattice* L) {
-    L->mem.release(L->fg.d_off);
-    L->mem.release(L->fg.d_key);
-    L->mem.release(L->fg.d_j);
-    L->mem.release(L->fg.d_Q);
-    L->mem.release(L->fg.d_S);
-    L->mem.release(L->fg.d_part);
-    L->fg = lattice::FusedGather();
-}
-
-// Whether samples of this lattice are gathered inside the streaming kernel:
-// one on-lattice charge set and the lists built for the current tiling.
-static bool fused_gather_on(const lattice* L) {
-    return L->fg.ready && L->effective_variant() == LAT_SWEEP_STREAM && L->n_sets == 1 && !L->offl &&
-           L->fg.tile == L->resolved_tile(LAT_SWEEP_STREAM) && L->fg.slab == L->resolved_slab(LAT_SWEEP_STREAM);
-}
-
-// Resident workgroups per CU of a kernel with `lds` bytes of LDS and `waves`
-// waves per workgroup (160 KiB of LDS and 32 wave slots per CU).
-static uint32_t workgroups_per_cu(uint32_t lds, uint32_t waves) {
-    return std::min<uint32_t>(lds ? 163840u / lds : 32u, 32u / waves);
-}
-
-// Build the per-tile lists of the fused gather for the current tiling (host
-// sort of the aggregated list, one upload); outside any capture.  Without
-// them (other kernels, several or off-lattice sets, a tile list too long to
-// stage in LDS without costing the sweep kernel a resident workgroup,
-// allocation failure) the samples go through the separate gather.
-static int fused_gather_prepare(lattice* L) {
-    const uint32_t tile = L->resolved_tile(LAT_SWEEP_STREAM), slab = L->resolved_slab(LAT_SWEEP_STREAM);
-    if (L->effective_variant() != LAT_SWEEP_STREAM || L->n_sets != 1 || L->offl ||
-        !L->host_charges || L->host_charges->site.size() != L->n_sites)
-        return LAT_OK;
-    if (L->fg.tried && L->fg.tile == tile && L->fg.slab == slab) return LAT_OK;
-    fused_gather_release(L);
-    graphs_reset(L);
-    L->fg.tried = true;
-    L->fg.tile = tile;
-    L->fg.slab = slab;
-    StreamTileShape sh;
-    if (!stream_tile_geometry(tile, L->esz, &sh)) return LAT_OK;
-    const uint32_t tq = sh.quads, ty = sh.rows;
-    const uint32_t nq = L->lh / 4, ly = (uint32_t)L->ly, lz = (uint32_t)L->lz;
-    const uint32_t nbx = (nq + tq - 1) / tq, nby = (ly + ty - 1) / ty, nbz = (lz + slab - 1) / slab;
-    const uint32_t blocks = nbx * nby * nbz;
-    const uint32_t plane = (uint32_t)L->ly * L->lh;
-    const lattice::HostCharges& hc = *L->host_charges;
-    const size_t n = hc.site.size();
-    // sort key of every charged site: its colour, its tile, its plane
-    // staged key: the step of the tile's walk that updates the site's plane
-    // << 16 | byte offset of the site in a ring slot (rows y0-1 .. y0+ty of
-    // tq + 2 quads: halo quad first); a tile's list is sorted by step
-    if (slab > 0xFFFFu) return LAT_OK;
-    const uint32_t row_bytes = (tq + 2u) * 4u * (uint32_t)L->esz;
-    std::vector<uint64_t> key_of(n);
-    std::vector<uint32_t> tile_of(n), j_of(n), packed_of(n);
-    size_t n0 = 0;
-    for (size_t i = 0; i < n; ++i) {
-        const uint32_t c = hc.site[i] >= L->vh ? 1u : 0u;
-        const uint32_t j = hc.site[i] - c * L->vh;
-        const uint32_t z = j / plane, rem = j - z * plane, y = rem / L->lh, jx = rem - y * L->lh;
-        const uint32_t bx = (jx / 4) / tq, by = y / ty, bz = z / slab;
-        tile_of[i] = bx + nbx * (by + nby * bz);
-        j_of[i] = j;
-        const uint32_t off = (y - by * ty + 1u) * row_bytes + (jx - 4u * tq * bx + 4u) * (uint32_t)L->esz;
-        // the step at which the tile's walk updates plane z (odd slabs walk down)
-        const uint32_t z0 = bz * slab, z1 = std::min(z0 + slab, lz);
-        const uint32_t step = kStreamAltZ && (bz & 1u) ? z1 - 1u - z : z - z0;
-        packed_of[i] = (step << 16) | off;
-        key_of[i] = ((uint64_t)c * blocks + tile_of[i]) * lz + step;
-        n0 += c ? 0u : 1u;
-    }
-    std::vector<uint32_t> order(n);
-    for (size_t i = 0; i < n; ++i) order[i] = (uint32_t)i;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key_of[a] < key_of[b]; });
-    // offsets: colour 0 at [0, blocks], colour 1 at [blocks + 1, 2 blocks + 1]
-    std::vector<uint32_t> off(2 * ((size_t)blocks + 1), 0u), key(n), jv(n);
-    std::vector<double> Q(n), S(n);
-    for (size_t k = 0; k < n; ++k) {
-        const uint32_t i = order[k];
-        const size_t c = k < n0 ? 0 : 1;
-        off[c * (blocks + 1) + tile_of[i] + 1] += 1;
-        key[k] = packed_of[i];
-        jv[k] = j_of[i];
-        Q[k] = hc.Q[i];
-        S[k] = hc.S[i];
-    }
-    uint32_t longest = 0;
-    for (size_t t = 0; t < 2 * ((size_t)blocks + 1); ++t) longest = std::max(longest, off[t]);
-    const uint64_t cap = ((uint64_t)longest + 63u) / 64u * 64u;
-    if (cap > 256u) return LAT_OK;  // the kernel holds up to 4 x 64 keys per tile in registers
-    const uint64_t lds = sh.lds + (uint64_t)kGatherEntryBytes * cap;
-    if (lds > 65536u || workgroups_per_cu((uint32_t)lds, sh.waves) < workgroups_per_cu(sh.lds, sh.waves) ||
-        (uint64_t)n * 8u >= (1ull << 32))
-        return LAT_OK;  // the separate gather
-    off[blocks + 1] = (uint32_t)n0;
-    for (size_t c = 0; c < 2; ++c)
-        for (size_t t = 0; t < blocks; ++t) off[c * (blocks + 1) + t + 1] += off[c * (blocks + 1) + t];
-    lattice::FusedGather g = L->fg;
-    g.d_off = static_cast<uint32_t*>(L->mem.alloc(off.size() * 4));
-    g.d_key = static_cast<uint32_t*>(L->mem.alloc(std::max<size_t>(n, 1) * 4));
-    g.d_j = static_cast<uint32_t*>(L->mem.alloc(std::max<size_t>(n, 1) * 4));
-    g.d_Q = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
-    g.d_S = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
-    g.d_part = static_cast<double*>(L->mem.alloc((size_t)blocks * 64));
-    L->fg = g;  // released by fused_gather_release on any failure below
-    if (!g.d_off || !g.d_key || !g.d_j || !g.d_Q || !g.d_S || !g.d_part) {
-        fused_gather_release(L);
-        L->fg.tried = true;  // the separate gather for this tiling
-        L->fg.tile = tile;
-        L->fg.slab = slab;
-        return LAT_OK;
-    }
-    hipError_t e = hipMemcpyAsync(g.d_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, L->stream);
-    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_key, key.data(), n * 4, hipMemcpyHostToDevice, L->stream);
-    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_j, jv.data(), n * 4, hipMemcpyHostToDevice, L->stream);
-    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_Q, Q.data(), n * 8, hipMemcpyHostToDevice, L->stream);
-    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(g.d_S, S.data(), n * 8, hipMemcpyHostToDevice, L->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-    if (e != hipSuccess) {
-        fused_gather_release(L);
-        return hip_fail(e, "fused gather list upload");
-    }
-    L->fg.ready = true;
-    L->fg.tile = tile;
-    L->fg.slab = slab;
-    L->fg.blocks = blocks;
-    L->fg.n = (uint32_t)n;
-    L->fg.cap = (uint32_t)cap;
-    return LAT_OK;
-}
 
 // One sweep on `stream`.  Eager (tdev null): sweep index L->t, which is
 // advanced.  Captured: index tdev[0] + rel, read on the device at run time.
 // fs: the fused gather's part in this sweep (streaming kernel only).
-static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint32_t rel,
-                            const lattice::FusedStep* fs = nullptr) {
+int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint32_t rel,
+                     const lattice::FusedStep* fs) {
     const uint32_t h0 = tdev ? 2u * rel : (uint32_t)(2 * L->t);
     const int v = L->effective_variant();
     hipError_t e;
@@ -376,29 +77,14 @@ static int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev
     return LAT_OK;
 }
 
-static int enqueue_sweep(lattice* L, const lattice::FusedStep* fs = nullptr) {
+int enqueue_sweep(lattice* L, const lattice::FusedStep* fs) {
     if (L->t >= (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_STATE, "sweep counter exhausted (2^31 sweeps)");
     return enqueue_sweep_ex(L, L->stream, nullptr, 0, fs);
 }
 
-// The open sample's colour-1 sites from memory (no sweep follows it), then
-// its finalize as sample m.
-static int enqueue_fused_tail(lattice* L, hipStream_t stream, uint32_t m, const uint32_t* mdev) {
-    const lattice::FusedGather& g = L->fg;
-    double* buf = g.d_part + (size_t)(m & 1u) * 4 * g.blocks;  // sample m's partials, colour 0 then 1
-    GatherTailArgs a{L->c1cur(), L->storage, g.blocks, g.d_off + g.blocks + 1, g.d_j, g.d_Q, g.d_S,
-                     buf + 2 * (size_t)g.blocks};
-    hipError_t e = launch_gather_tail(a, stream);
-    if (e == hipSuccess)
-        e = launch_finalize_measure(buf, 2 * g.blocks, 1u, L->d_bins, m, (uint32_t)L->bin_size, mdev,
-                                    L->last_xy(), (uint32_t)L->bin_cap, stream);
-    if (e != hipSuccess) return hip_fail(e, "measure launch");
-    return LAT_OK;
-}
-
 // The resident path: n_therm unmeasured sweeps then n_meas sweeps with a
 // sample after every `every`-th, all in one launch.
-static int enqueue_resident(lattice* L, int64_t n_therm, int64_t n_meas, int64_t every) {
+int enqueue_resident(lattice* L, int64_t n_therm, int64_t n_meas, int64_t every) {
     if (n_therm + n_meas == 0) return LAT_OK;
     BatchArgs a{};
     a.field = L->field;
@@ -473,7 +159,7 @@ static void graph_reset(lattice::SweepGraph& g) {
     g = lattice::SweepGraph();
 }
 
-static void graphs_reset(lattice* L) {
+void graphs_reset(lattice* L) {
     graph_reset(L->g_therm);
     graph_reset(L->g_meas);
 }
@@ -635,153 +321,9 @@ static int ensure_bins(lattice* L, int64_t n_bins_needed) {
     return LAT_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Autotuner: times every sweep kernel and tuning that can handle a box on
-// scratch memory, keeps the fastest; choices are cached per (box, storage).
-// ---------------------------------------------------------------------------
-struct TuneChoice {
-    int variant;
-    uint32_t slab, tile, xcd;
-    double ms;
-};
-static std::mutex g_tune_mu;
-static std::map<std::tuple<int64_t, int64_t, int64_t, int>, TuneChoice> g_tune_cache;
-
-// Candidates in order of preference: the first is the library default for
-// the box; a later one replaces the current best only if it is more than 3%
-// faster, so that choices do not flip on timing noise.
-static std::vector<TuneChoice> tune_candidates(const lattice* L) {
-    std::vector<TuneChoice> c;
-    const uint64_t V = (uint64_t)L->vh * 2;
-    const bool resident_ok = L->n_sets == 1 && !L->offl;  // the resident kernel measures one on-lattice set
-    if (V <= kResidentMaxSites && resident_ok) c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
-    if (L->lh % 4 != 0) {
-        if (V > kResidentMaxSites && V <= (uint64_t)1 << 18 && resident_ok)
-            c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
-        c.push_back({LAT_SWEEP_GENERIC, 0, 0, 1, 0});
-        return c;
-    }
-    const bool slab_ok = (size_t)L->vh * L->esz < ((size_t)1 << 31);
-    if (slab_ok && (size_t)2 * L->vh * L->esz >= ((size_t)256 << 20)) {
-        lattice d = *L;  // the library's own choice for the box
-        d.slab = 0;
-        d.tile = kTileDefault;
-        d.xcd_order = -1;
-        c.push_back({LAT_SWEEP_STREAM, d.resolved_slab(LAT_SWEEP_STREAM), d.resolved_tile(LAT_SWEEP_STREAM),
-                     d.resolved_xcd(LAT_SWEEP_STREAM), 0});
-    }
-    c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
-    if (V > kResidentMaxSites && V <= (uint64_t)1 << 18 && resident_ok)
-        c.push_back({LAT_SWEEP_RESIDENT, 0, 0, 1, 0});
-    if (slab_ok)
-        for (uint32_t tile = 0; tile < (uint32_t)kStreamTiles; ++tile)
-            for (uint32_t slab : {16u, 24u, 32u, 48u})
-                for (uint32_t xcd : {1u, 2u, 0u})
-                    if (slab <= L->lz) c.push_back({LAT_SWEEP_STREAM, slab, tile, xcd, 0});
-    if (slab_ok)
-        for (uint32_t tile : {0u, 1u, 7u})
-            for (uint32_t slab : {8u, 16u, 32u})
-                if (slab <= L->lz) c.push_back({LAT_SWEEP_ZSLAB, slab, tile, 1, 0});
-    if (fused_sweep_supported(L->lh, (uint32_t)L->ly))
-        for (uint32_t slab : {16u, 32u})
-            if (slab <= L->lz) c.push_back({LAT_SWEEP_FUSED, slab, 0, 1, 0});
-    return c;
-}
-
-static void apply_choice(lattice* L, const TuneChoice& ch) {
-    L->variant = ch.variant;
-    L->slab = ch.slab;
-    L->tile = ch.tile;
-    L->xcd_order = (int)ch.xcd;
-}
-
-static int autotune(lattice* L, int64_t reps, TuneChoice* out) {
-    const auto key = std::make_tuple(L->lx, L->ly, L->lz, L->storage);
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            *out = it->second;
-            return LAT_OK;
-        }
-    }
-    const std::vector<TuneChoice> cands = tune_candidates(L);
-    if (fused_sweep_supported(L->lh, (uint32_t)L->ly))
-        if (hipError_t e = prepare_fused_sweep()) return hip_fail(e, "fused sweep set-up");
-    const size_t fbytes = round_up(2 * (size_t)L->vh * L->esz, 256);
-    void* scratch = L->mem.alloc(fbytes);
-    void* scratch_alt = L->mem.alloc(round_up((size_t)L->vh * L->esz, 256));
-    if (!scratch || !scratch_alt) {
-        L->mem.release(scratch);
-        L->mem.release(scratch_alt);
-        return set_error(LAT_ERR_ALLOC, "allocation of autotuning scratch failed");
-    }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMemsetAsync(scratch, 0, fbytes, L->stream);
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    TuneChoice best{LAT_SWEEP_AUTO, 0, 0, 1, 1e30};
-    int rc = LAT_OK;
-    for (size_t i = 0; i < cands.size() && e == hipSuccess && rc == LAT_OK; ++i) {
-        lattice tmp = *L;  // shallow copy: same sizes and streams, scratch field, no charges
-        tmp.field = scratch;
-        tmp.c1alt = scratch_alt;
-        tmp.alt_current = false;
-        tmp.t = 0;
-        tmp.n_meas = 0;
-        apply_choice(&tmp, cands[i]);
-        auto run = [&](int64_t n) {
-            if (tmp.variant == LAT_SWEEP_RESIDENT) return enqueue_resident(&tmp, n, 0, 1);
-            for (int64_t k = 0; k < n; ++k)
-                if (int r = enqueue_sweep(&tmp)) return r;
-            return (int)LAT_OK;
-        };
-        rc = run(1);
-        if (rc == LAT_OK) e = hipEventRecord(e0, L->stream);
-        if (rc == LAT_OK && e == hipSuccess) rc = run(reps);
-        if (rc == LAT_OK && e == hipSuccess) e = hipEventRecord(e1, L->stream);
-        if (rc == LAT_OK && e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (rc == LAT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (rc == LAT_OK && e == hipSuccess && ms / reps < 0.97 * best.ms) {
-            best = cands[i];
-            best.ms = ms / reps;
-        }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)hipStreamSynchronize(L->stream);
-    L->mem.release(scratch);
-    L->mem.release(scratch_alt);
-    if (rc != LAT_OK) return rc;
-    if (e != hipSuccess) return hip_fail(e, "autotuning");
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        g_tune_cache[key] = best;
-    }
-    *out = best;
-    return LAT_OK;
-}
+}  // namespace latcoul
 
 extern "C" {
-
-int lattice_autotune(lattice_t* L, int64_t reps, int* variant, int64_t* planes, int* tile, int* xcd_order,
-                     double* ms_per_sweep) {
-    if (int r = check_lattice(L)) return r;
-    if (reps < 1 || reps > 1000) return set_error(LAT_ERR_ARG, "reps must be in [1, 1000]");
-    TuneChoice ch;
-    if (int r = autotune(L, reps, &ch)) return r;
-    if (ch.variant == LAT_SWEEP_FUSED)
-        if (int r = lattice_set_variant(L, LAT_SWEEP_FUSED)) return r;  // allocates the second colour-1 array
-    apply_choice(L, ch);
-    graphs_reset(L);
-    if (variant) *variant = ch.variant;
-    if (planes) *planes = ch.slab;
-    if (tile) *tile = (int)ch.tile;
-    if (xcd_order) *xcd_order = (int)ch.xcd;
-    if (ms_per_sweep) *ms_per_sweep = ch.ms;
-    return LAT_OK;
-}
 
 int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t seed, uint32_t chain_id,
                    const lat_allocator* alloc, void* hip_stream, lattice_t** out) {
