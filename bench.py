@@ -225,7 +225,9 @@ def precision_coupled(sweeps, torch, lattice, workloads):
     move together, so the per-sweep difference of a 16-bit chain's sample from
     the FP32 chain's measures its bias with an error far below the chains' own
     statistical error; with equal statistics, time to a given error scales as
-    the cost per sweep."""
+    the cost per sweep.  Each storage format runs the sweep configuration the
+    library's autotuner picks for it on this machine (kernel choice does not
+    change the chain: every kernel computes the same update)."""
     name = "gaussian_blob_384"
     spec = workloads.WORKLOADS[name]
     cs = spec["make"]()
@@ -233,6 +235,7 @@ def precision_coupled(sweeps, torch, lattice, workloads):
     for st in ("fp32", "bf16", "fp16"):
         lat = lattice.Lattice(cs.shape, st, seed=spec["philox_seed"])
         lat.set_charges(cs.xyz, cs.q)
+        lat.autotune(3)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lat.sweep_and_measure(sweeps, 1, 1)
@@ -240,7 +243,7 @@ def precision_coupled(sweeps, torch, lattice, workloads):
         dt = time.perf_counter() - t0
         _, n, bins = lat.get_state()
         series[st] = bins[:, 0] - bins[:, 1]  # one sample per bin
-        out[st] = {"ms_per_sweep": 1e3 * dt / sweeps, "mean_O": float(series[st].mean())}
+        out[st] = {"ms_per_sweep": 1e3 * dt / sweeps, "mean_O": float(series[st].mean()), "tuning": lat.tuning()}
         lat.close()
     out["sd_O"] = float(series["fp32"].std())
     nblk = 10

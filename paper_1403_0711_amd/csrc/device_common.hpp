@@ -173,11 +173,24 @@ struct StoreF32 {
     __device__ static __forceinline__ float4 round4(float4 v) { return v; }
 };
 
-__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;  // finite inputs only
-}
 __device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+// The FP32 value v as a register: the rounding to FP16 that follows cannot
+// be folded into the FMA that produced v (a mixed-precision FMA rounds once,
+// from the exact result), so every kernel stores the FP32 update rounded to
+// the storage format, and a value recomputed elsewhere rounds the same way.
+__device__ __forceinline__ float fp32_reg(float v) {
+    asm("" : "+v"(v));
+    return v;
+}
+// Two values rounded to nearest even to BF16 and packed (a in the low half):
+// gfx950's v_cvt_pk_bf16_f32, one instruction per pair instead of an integer
+// rounding sequence per value; finite inputs only.
+__device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const f32x2 v = {fp32_reg(a), fp32_reg(b)};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
 
 struct StoreBF16 {
     using T = uint16_t;
@@ -190,16 +203,18 @@ struct StoreBF16 {
     }
     __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) {
         uint2 w;
-        w.x = bf16_rne_bits(v.x) | (bf16_rne_bits(v.y) << 16);
-        w.y = bf16_rne_bits(v.z) | (bf16_rne_bits(v.w) << 16);
+        w.x = bf16x2_rne(v.x, v.y);
+        w.y = bf16x2_rne(v.z, v.w);
         at<uint2>(p, i) = w;
     }
     __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v) {
         typedef uint32_t u2 __attribute__((ext_vector_type(2)));
-        const u2 w = {bf16_rne_bits(v.x) | (bf16_rne_bits(v.y) << 16), bf16_rne_bits(v.z) | (bf16_rne_bits(v.w) << 16)};
+        const u2 w = {bf16x2_rne(v.x, v.y), bf16x2_rne(v.z, v.w)};
         __builtin_nontemporal_store(w, &at<u2>(p, i));
     }
-    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<uint16_t>(p, i) = (T)bf16_rne_bits(v); }
+    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) {
+        at<uint16_t>(p, i) = (T)(bf16x2_rne(v, 0.0f) & 0xFFFFu);
+    }
     __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
         return make_float4(__uint_as_float(w[0] << 16), __uint_as_float(w[0] & 0xFFFF0000u),
@@ -209,19 +224,12 @@ struct StoreBF16 {
         return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
     }
     __device__ static __forceinline__ float4 round4(float4 v) {
-        return make_float4(bf16_to_f32(bf16_rne_bits(v.x)), bf16_to_f32(bf16_rne_bits(v.y)),
-                           bf16_to_f32(bf16_rne_bits(v.z)), bf16_to_f32(bf16_rne_bits(v.w)));
+        const uint32_t a = bf16x2_rne(v.x, v.y), b = bf16x2_rne(v.z, v.w);
+        return make_float4(__uint_as_float(a << 16), __uint_as_float(a & 0xFFFF0000u), __uint_as_float(b << 16),
+                           __uint_as_float(b & 0xFFFF0000u));
     }
 };
 
-// The FP32 value v as a register: the rounding to FP16 that follows cannot
-// be folded into the FMA that produced v (a mixed-precision FMA rounds once,
-// from the exact result), so every kernel stores the FP32 update rounded to
-// FP16, and a value recomputed elsewhere rounds the same way.
-__device__ __forceinline__ float fp32_reg(float v) {
-    asm("" : "+v"(v));
-    return v;
-}
 __device__ __forceinline__ _Float16 to_f16(float v) { return (_Float16)fp32_reg(v); }
 
 struct StoreF16 {
