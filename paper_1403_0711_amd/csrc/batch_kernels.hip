@@ -16,8 +16,9 @@ namespace latcoul {
 
 constexpr int kBatchThreads = 1024;
 
-// One half-sweep of colour c over a whole chain by one workgroup: 4 compact
-// sites of one row per iteration when lh % 4 == 0, else one site.
+// One half-sweep of colour c over a whole chain by one workgroup: when
+// lh % 4 == 0, two quads (4 compact sites of a row each) per thread and
+// iteration, whose loads are all issued before either update, else one site.
 template <class St>
 __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const BatchChainDesc& d, uint32_t c,
                                                 uint32_t h, uint32_t k0, uint32_t k1) {
@@ -28,14 +29,25 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
     const float sixth = 1.0f / 6.0f;
     if ((lh & 3u) == 0) {
         const uint32_t nq = lh >> 2, nquads = d.vh >> 2;
-        for (uint32_t qi = threadIdx.x; qi < nquads; qi += kBatchThreads) {
-            const uint32_t q = qi % nq, rowi = qi / nq;
-            const uint32_t y = rowi % ly, z = rowi / ly;
-            const uint32_t p = (c + y + z) & 1u;
-            const uint32_t j0 = rowi * lh + 4u * q;
-            const float4 out = quad_update_global<St>(other, j0, lh, plane, y > 0, y + 1 < ly, z > 0, z + 1 < lz,
-                                                      p == 0 ? q > 0 : q + 1 < nq, p, h, d.chain_id, k0, k1);
-            St::st4(own, j0, out);
+        for (uint32_t q0 = threadIdx.x; q0 < nquads; q0 += 2u * kBatchThreads) {
+            uint32_t j0[2], p[2];
+            bool in[2];
+            QuadNeighbours<St> nb[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const uint32_t qi = q0 + (uint32_t)u * kBatchThreads;
+                in[u] = qi < nquads;
+                const uint32_t qc = in[u] ? qi : q0;  // a lane past the end loads its first quad again
+                const uint32_t q = qc % nq, rowi = qc / nq;
+                const uint32_t y = rowi % ly, z = rowi / ly;
+                p[u] = (c + y + z) & 1u;
+                j0[u] = rowi * lh + 4u * q;
+                nb[u] = quad_load_global<St>(other, j0[u], lh, plane, y > 0, y + 1 < ly, z > 0, z + 1 < lz,
+                                             p[u] == 0 ? q > 0 : q + 1 < nq, p[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (in[u]) St::st4(own, j0[u], quad_update_from<St>(nb[u], p[u], j0[u], h, d.chain_id, k0, k1));
         }
     } else {
         for (uint32_t j = threadIdx.x; j < d.vh; j += kBatchThreads) {

@@ -328,35 +328,64 @@ __device__ __forceinline__ float4 heatbath_quad_f16(u32x2 bm, u32x2 bc, u32x2 bn
     return out;
 }
 
-// The update of the quad at compact index j0 of a row, read straight from
-// the other colour's array (0 beyond the box faces; p and the quad's
-// position decide which x-neighbour beyond the quad is read).  FP16 storage
-// takes the raw halves.
+// The neighbours of the quad at compact index j0 of a row, read straight
+// from the other colour's array (0 beyond the box faces; p and the quad's
+// position decide which x-neighbour beyond the quad is read), and the
+// update computed from them.  FP16 storage keeps the raw halves.  Split so
+// that a thread can have the loads of several quads in flight.
+template <class St>
+struct QuadNeighbours {
+    float4 cen, ym, yp, zm, zp;
+    float e;
+};
+template <>
+struct QuadNeighbours<StoreF16> {
+    u32x2 cen, ym, yp, zm, zp;
+    uint32_t e;
+};
+
+template <class St>
+__device__ __forceinline__ QuadNeighbours<St> quad_load_global(const typename St::T* other, uint32_t j0, uint32_t lh,
+                                                              uint32_t plane, bool ym_in, bool yp_in, bool zm_in,
+                                                              bool zp_in, bool e_in, uint32_t p) {
+    const uint32_t je = p == 0 ? j0 - 1u : j0 + 4u;  // the x-neighbour beyond the quad
+    QuadNeighbours<St> nb;
+    if constexpr (std::is_same<St, StoreF16>::value) {
+        const u32x2 zero = {0u, 0u};
+        nb.cen = at<u32x2>(other, j0);
+        nb.ym = ym_in ? at<u32x2>(other, j0 - lh) : zero;
+        nb.yp = yp_in ? at<u32x2>(other, j0 + lh) : zero;
+        nb.zm = zm_in ? at<u32x2>(other, j0 - plane) : zero;
+        nb.zp = zp_in ? at<u32x2>(other, j0 + plane) : zero;
+        nb.e = e_in ? (uint32_t)at<uint16_t>(other, je) : 0u;
+    } else {
+        const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+        nb.cen = St::ld4(other, j0);
+        nb.ym = ym_in ? St::ld4(other, j0 - lh) : zero;
+        nb.yp = yp_in ? St::ld4(other, j0 + lh) : zero;
+        nb.zm = zm_in ? St::ld4(other, j0 - plane) : zero;
+        nb.zp = zp_in ? St::ld4(other, j0 + plane) : zero;
+        nb.e = e_in ? St::ld(other, je) : 0.f;
+    }
+    return nb;
+}
+
+template <class St>
+__device__ __forceinline__ float4 quad_update_from(const QuadNeighbours<St>& nb, uint32_t p, uint32_t j0, uint32_t h,
+                                                   uint32_t chain, uint32_t k0, uint32_t k1) {
+    if constexpr (std::is_same<St, StoreF16>::value)
+        return heatbath_quad_f16(nb.zm, nb.cen, nb.zp, nb.ym, nb.yp, nb.e, p, j0, h, chain, k0, k1);
+    else
+        return heatbath_quad(nb.zm, nb.cen, nb.zp, nb.ym, nb.yp, nb.e, p, j0, h, chain, k0, k1);
+}
+
 template <class St>
 __device__ __forceinline__ float4 quad_update_global(const typename St::T* other, uint32_t j0, uint32_t lh,
                                                      uint32_t plane, bool ym_in, bool yp_in, bool zm_in, bool zp_in,
                                                      bool e_in, uint32_t p, uint32_t h, uint32_t chain, uint32_t k0,
                                                      uint32_t k1) {
-    const uint32_t je = p == 0 ? j0 - 1u : j0 + 4u;  // the x-neighbour beyond the quad
-    if constexpr (std::is_same<St, StoreF16>::value) {
-        const u32x2 zero = {0u, 0u};
-        const u32x2 cen = at<u32x2>(other, j0);
-        const u32x2 ym = ym_in ? at<u32x2>(other, j0 - lh) : zero;
-        const u32x2 yp = yp_in ? at<u32x2>(other, j0 + lh) : zero;
-        const u32x2 zm = zm_in ? at<u32x2>(other, j0 - plane) : zero;
-        const u32x2 zp = zp_in ? at<u32x2>(other, j0 + plane) : zero;
-        const uint32_t e = e_in ? (uint32_t)at<uint16_t>(other, je) : 0u;
-        return heatbath_quad_f16(zm, cen, zp, ym, yp, e, p, j0, h, chain, k0, k1);
-    } else {
-        const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 cen = St::ld4(other, j0);
-        const float4 ym = ym_in ? St::ld4(other, j0 - lh) : zero;
-        const float4 yp = yp_in ? St::ld4(other, j0 + lh) : zero;
-        const float4 zm = zm_in ? St::ld4(other, j0 - plane) : zero;
-        const float4 zp = zp_in ? St::ld4(other, j0 + plane) : zero;
-        const float e = e_in ? St::ld(other, je) : 0.f;
-        return heatbath_quad(zm, cen, zp, ym, yp, e, p, j0, h, chain, k0, k1);
-    }
+    return quad_update_from<St>(quad_load_global<St>(other, j0, lh, plane, ym_in, yp_in, zm_in, zp_in, e_in, p), p,
+                                j0, h, chain, k0, k1);
 }
 
 // ---------------------------------------------------------------------------
