@@ -19,6 +19,8 @@ constexpr int kBatchThreads = 1024;
 // One half-sweep of colour c over a whole chain by one workgroup: when
 // lh % 4 == 0, two quads (4 compact sites of a row each) per thread and
 // iteration, whose loads are all issued before either update, else one site.
+// A lane whose second quad lies past the end loads quad 0's centre (in
+// range) with every face load switched off, and stores nothing.
 template <class St>
 __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const BatchChainDesc& d, uint32_t c,
                                                 uint32_t h, uint32_t k0, uint32_t k1) {
@@ -29,21 +31,37 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
     const float sixth = 1.0f / 6.0f;
     if ((lh & 3u) == 0) {
         const uint32_t nq = lh >> 2, nquads = d.vh >> 2;
-        for (uint32_t q0 = threadIdx.x; q0 < nquads; q0 += 2u * kBatchThreads) {
+        // the thread's quad (q, y, z), advanced kBatchThreads quads at a time
+        // with carries: one division per half-sweep instead of two per quad
+        const uint32_t t = threadIdx.x, r0 = t / nq;
+        uint32_t qi = t, q = t - r0 * nq, y = r0 % ly, z = r0 / ly;
+        const uint32_t drow = kBatchThreads / nq, dq = kBatchThreads - drow * nq;
+        const uint32_t dz = drow / ly, dy = drow - dz * ly;
+        auto advance = [&]() {
+            qi += kBatchThreads;
+            q += dq;
+            const uint32_t cq = q >= nq ? 1u : 0u;
+            q -= cq * nq;
+            y += dy + cq;
+            const uint32_t cy = y >= ly ? 1u : 0u;
+            y -= cy * ly;
+            z += dz + cy;
+        };
+        while (qi < nquads) {
             uint32_t j0[2], p[2];
             bool in[2];
             QuadNeighbours<St> nb[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const uint32_t qi = q0 + (uint32_t)u * kBatchThreads;
                 in[u] = qi < nquads;
-                const uint32_t qc = in[u] ? qi : q0;  // a lane past the end loads its first quad again
-                const uint32_t q = qc % nq, rowi = qc / nq;
-                const uint32_t y = rowi % ly, z = rowi / ly;
                 p[u] = (c + y + z) & 1u;
-                j0[u] = rowi * lh + 4u * q;
-                nb[u] = quad_load_global<St>(other, j0[u], lh, plane, y > 0, y + 1 < ly, z > 0, z + 1 < lz,
-                                             p[u] == 0 ? q > 0 : q + 1 < nq, p[u]);
+                j0[u] = (z * ly + y) * lh + 4u * q;
+                // a lane past the end loads in-range quads again (its first), and stores nothing
+                const uint32_t jl = in[u] ? j0[u] : 0u;
+                nb[u] = quad_load_global<St>(other, jl, lh, plane, in[u] && y > 0, in[u] && y + 1 < ly,
+                                             in[u] && z > 0, in[u] && z + 1 < lz,
+                                             in[u] && (p[u] == 0 ? q > 0 : q + 1 < nq), p[u]);
+                advance();
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u)
