@@ -255,8 +255,6 @@ static int graph_capture(lattice* L, lattice::SweepGraph& g, int64_t K, int64_t 
     return LAT_OK;
 }
 
-static int settle_colour1(lattice* L);
-
 // n sweeps with a sample after every `every`-th (every = 0: no samples):
 // whole chunks as graph replays where that pays, the rest launch by launch.
 static int run_sweeps(lattice* L, int64_t n, int64_t every) {
