@@ -350,13 +350,28 @@ def cpu_baseline(cs, storage: str, seed: int):
     ch = oracle.OracleChain(cs.shape, storage=storage, seed=seed)
     ch.set_charges(cs.xyz, cs.q)
     V = int(np.prod(cs.shape))
+    cores = int(lib.orc_max_threads())
     t0 = time.perf_counter()
     ch.sweeps(1, 1)
     dt = time.perf_counter() - t0
-    return {"value": V / dt, "unit": "site updates/s", "cores": int(lib.orc_max_threads()),
+    del ch
+    # the same oracle on one thread, on a smaller box of the same kind (one
+    # unmeasured sweep of 192^3, a few seconds)
+    small = (192, 192, 192)
+    lib.orc_set_threads(1)
+    try:
+        one = oracle.OracleChain(small, storage=storage, seed=seed)
+        t1 = time.perf_counter()
+        one.sweeps(1, 0)
+        dt1 = time.perf_counter() - t1
+    finally:
+        lib.orc_set_threads(cores)
+    return {"value": V / dt, "unit": "site updates/s", "cores": cores,
             "kind": "oracle",
             "sample": f"1 measured sweep of the full {cs.shape[0]}x{cs.shape[1]}x{cs.shape[2]} "
-                      f"box with all {cs.n} charges ({dt:.1f} s)"}
+                      f"box with all {cs.n} charges ({dt:.1f} s)",
+            "single_thread": {"value": int(np.prod(small)) / dt1, "unit": "site updates/s",
+                              "sample": f"1 sweep of a {small[0]}^3 box on 1 thread ({dt1:.1f} s)"}}
 
 
 def main():
