@@ -5,7 +5,7 @@ One step = one measured sweep of the whole path: both red-black half-sweeps
 lattice, then the gather of X = sum q phi and Y = sum q^2 phi^2 over the
 charges, O = X^2 - Y and its compensated accumulation into a bin.
 
-Default workload: the largest one-GPU machine, 768^3 sites (FP32 field 1.69 GiB),
+Default workload: the largest lattice one GPU holds here, 768^3 sites (FP32 field 1.69 GiB),
 1.1e6 charges (1e6 of +-1, 1e5 drawn from N(0, 0.5^2)), seeded synthetic
 input (the paper's tests use synthetic charge placements only).
 
@@ -377,7 +377,7 @@ def cpu_baseline(cs, storage: str, seed: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the lattice is one GPU's "
+        print(json.dumps({"error": "this library runs on one GPU only: the lattice is one GPU's "
                           "subdomain; multi-GPU sharding is not implemented"}))
         sys.exit(2)
     import torch

@@ -155,7 +155,7 @@ def gaussian_blob(seed: int = 0, L: int = 384, n: int = 200_000, sigma: float = 
 
 def largest_subdomain(seed: int = 0, L: int = 768, n_pm: int = 1_000_000,
                       n_gauss: int = 100_000, gauss_sd: float = 0.5) -> ChargeSet:
-    """Largest one-GPU machine: ``n_pm`` charges of +-1 (half each) plus
+    """Largest single-GPU lattice: ``n_pm`` charges of +-1 (half each) plus
     ``n_gauss`` charges drawn from ``N(0, gauss_sd^2)`` (not shifted), all at
     distinct uniform sites of ``L^3`` (default 768^3, 1.1e6 charges)."""
     rng = np.random.default_rng(seed)

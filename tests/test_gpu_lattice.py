@@ -375,7 +375,7 @@ def test_sampled_parity_large(lat_mod, variant):
 
 
 def test_sampled_parity_largest_box(lat_mod):
-    """768^3 (the largest one-GPU machine benchmarked), with the kernel and launch
+    """768^3 (the largest single-GPU lattice benchmarked), with the kernel and launch
     configuration the benchmark times (library default)."""
     print("[gpu] sampled parity 768^3", flush=True)
     _sampled_sweep_parity(lat_mod, (768, 768, 768), "auto", n_samples=2048)
