@@ -257,6 +257,72 @@ def precision_coupled(sweeps, torch, lattice, workloads):
     return out
 
 
+def time_to_1pct_measured(torch, lattice, workloads, chains=256, call_s=5.0, cap_s=60.0):
+    """Time to a 1% statistical error on E_N on the 16^3 neutral workload (8
+    charges of +-1, E_lat = 0.029, so about 1e8 samples): `chains`
+    independent chains of the same system in one batched launch, run until
+    the error of their pooled mean (spread of the chains' means over
+    sqrt(chains)) is below 1% of |E_exact|, timed by wall clock; against one
+    chain (the plain sweep) timed over a bounded run and extrapolated as
+    t_run (error / 1%)^2 from its binned error.  Both after 1e3
+    thermalisation sweeps.  Sweeps go in calls of at most `call_s` seconds,
+    sized from the rate measured so far, each reported on stderr."""
+    name = "small_neutral_16"
+    cs = workloads.WORKLOADS[name]["make"]()
+    E = exact_energy(name)
+    if not E:
+        return None
+    target, bin_size = 0.01 * abs(E), 1000
+
+    lat = lattice.Lattice(cs.shape, "fp32", seed=0)
+    lat.set_charges(cs.xyz, cs.q)
+    lat.thermalise(1000)
+    torch.cuda.synchronize()
+    n_plain = 200 * bin_size
+    t0 = time.perf_counter()
+    lat.sweep_and_measure(n_plain, 1, bin_size)
+    mean, se, _, _ = lat.energy_estimate()
+    dt = time.perf_counter() - t0
+    lat.close()
+    plain = {"seconds_run": dt, "sweeps": n_plain, "mean": mean, "stderr": se,
+             "time_to_1pct_s": dt * (se / target) ** 2, "kind": "extrapolated"}
+    print(f"time to 1% (16^3): one chain, {n_plain} sweeps in {dt:.2f} s, stderr {se:.3g}",
+          file=sys.stderr, flush=True)
+
+    b = lattice.Batch([cs.shape] * chains, "fp32", seed=0, chain_ids=list(range(1, chains + 1)))
+    for k in range(chains):
+        b.set_charges(k, cs.xyz, cs.q)
+    b.run(1000, 0, bin_size)
+    torch.cuda.synchronize()
+
+    def pooled():
+        means = np.array([b.energy_estimate(k)[0] for k in range(chains)])
+        return float(means.mean()), float(means.std(ddof=1) / math.sqrt(chains))
+
+    t0 = time.perf_counter()
+    done, step = 0, 2 * bin_size
+    while True:
+        t1 = time.perf_counter()
+        b.run(0, step, bin_size)
+        torch.cuda.synchronize()
+        rate = step / (time.perf_counter() - t1)  # sweeps per chain and second
+        done += step
+        mean_b, se_b = pooled()
+        print(f"time to 1% (16^3): {chains} chains, {done} sweeps each, stderr {se_b:.3g}",
+              file=sys.stderr, flush=True)
+        if se_b <= target or time.perf_counter() - t0 > cap_s:
+            break
+        need = int(done * (se_b / target) ** 2 * 1.1) - done
+        step = max(bin_size, min(need, int(rate * call_s)) // bin_size * bin_size)
+    batched = {"seconds": time.perf_counter() - t0, "sweeps_per_chain": done, "chains": chains, "mean": mean_b,
+               "stderr": se_b, "reached": se_b <= target, "kind": "measured"}
+    b.close()
+    out = {"workload": name, "E_exact": E, "target_stderr": target, "plain": plain, "batched": batched}
+    if batched["reached"]:
+        out["batched_speedup"] = plain["time_to_1pct_s"] / batched["seconds"]
+    return out
+
+
 def charge_sets_comparison(cs, spec, workloads, steps, bin_size, torch, lattice, n_sets=4):
     """Several charge sets on one field chain: the workload's set plus
     n_sets - 1 more drawn with other seeds, every set sampled every sweep.
@@ -472,6 +538,7 @@ def main():
                 f16["speedup_vs_fp32"] = ms_per_step / f16["ms_per_step"]
                 out["fp16_storage"] = f16
             out["batched_512"] = batched_comparison(200, torch, lattice, workloads)
+            out["time_to_1pct_16"] = time_to_1pct_measured(torch, lattice, workloads)
             out["precision_coupled"] = precision_coupled(args.coupled_sweeps, torch, lattice, workloads)
             out["figures_128"] = figures_comparison(args.figures_sweeps)
             if args.storage == "fp32":
