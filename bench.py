@@ -15,7 +15,8 @@ pick with --variant tuned) from HIP events around its own launches on the
 library's stream, the time to a 1% statistical error on E_N
 (extrapolated from the measured binned error and the exact lattice energy
 stored in tests/golden/exact_energies.json), the same sweep with FP16 field
-storage and the 512-chain batched workload for comparison, and the CPU oracle
+storage, the 512-chain batched workload and the time to a 1% error on the 16^3
+workload (256 batched chains against one chain) for comparison, and the CPU oracle
 timed on a bounded sample of the same workload; with extras, also a coupled
 FP32 / BF16 / FP16 comparison on the 384^3 Gaussian blob (bias of the 16-bit
 chains and their cost per sweep), four charge sets sampled on one chain, the
