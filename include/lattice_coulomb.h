@@ -139,8 +139,12 @@ int lattice_set_charge_sets(lattice_t *lat, int64_t n_sets, const int64_t *count
  * accumulates, at every sample, dO/dr_i = 2 q_i grad phi~_i (X - q_i phi~_i)
  * (the gradient of the interpolant within the cell), whose mean is dE/dr_i
  * (read with lattice_force_estimate; E sums ordered pairs, so the physical
- * force on charge i is -(1/2) dE/dr_i).  Replaces all charge sets; resets
- * the bins and force sums; the field and sweep counter are kept.  Errors:
+ * force on charge i is -(1/2) dE/dr_i).  The library keeps the charges
+ * sorted by cell (nearby charges then read shared cache lines close in
+ * time); lattice_force_estimate returns them in the caller's order, and only
+ * the order of the FP64 sums X and Y follows the sorted one.  Replaces all
+ * charge sets; resets the bins and force sums; the field and sweep counter
+ * are kept.  Errors:
  * LAT_ERR_ARG for a position outside the box, a box edge below 2, a
  * non-finite q or the variant LAT_SWEEP_RESIDENT (on-lattice charges only);
  * LAT_ERR_ALLOC. */

@@ -489,6 +489,7 @@ static void release_offlattice(lattice* L) {
     L->offl = false;
     L->n_off = 0;
     L->force_base = 0;
+    L->off_order.reset();
 }
 
 int lattice_set_charge_sets(lattice_t* L, int64_t n_sets, const int64_t* counts, const int32_t* xyz,
@@ -686,6 +687,22 @@ int lattice_set_offlattice_charges(lattice_t* L, int64_t n, const double* r, con
                 return set_error(LAT_ERR_ARG, "position outside [0, L - 1] on some axis");
         }
     }
+    // order by cell (z, then y, then x of the cell origin), ties by input order
+    auto order = std::make_shared<std::vector<uint32_t>>((size_t)n);
+    std::vector<uint64_t> cell((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t b[3];
+        for (int d = 0; d < 3; ++d) b[d] = (uint64_t)std::min(std::floor(r[3 * i + d]), hi[d] - 1.0);
+        cell[(size_t)i] = (b[2] * (uint64_t)L->ly + b[1]) * (uint64_t)L->lx + b[0];
+        (*order)[(size_t)i] = (uint32_t)i;
+    }
+    std::stable_sort(order->begin(), order->end(), [&](uint32_t a, uint32_t b) { return cell[a] < cell[b]; });
+    std::vector<double> rs((size_t)n * 3), qs((size_t)n);
+    for (size_t k = 0; k < (size_t)n; ++k) {
+        const uint32_t i = (*order)[k];
+        for (int d = 0; d < 3; ++d) rs[3 * k + d] = r[3 * (size_t)i + d];
+        qs[k] = q[i];
+    }
     const size_t cap = (size_t)std::max<int64_t>(n, 1);
     const uint32_t blocks = measure_blocks((uint32_t)n);
     double* d_r = static_cast<double*>(L->mem.alloc(cap * 24));
@@ -713,8 +730,8 @@ int lattice_set_offlattice_charges(lattice_t* L, int64_t n, const double* r, con
     }
     hipError_t e = hipSuccess;
     if (n > 0) {
-        e = hipMemcpyAsync(d_r, r, (size_t)n * 24, hipMemcpyHostToDevice, L->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(d_q, q, (size_t)n * 8, hipMemcpyHostToDevice, L->stream);
+        e = hipMemcpyAsync(d_r, rs.data(), (size_t)n * 24, hipMemcpyHostToDevice, L->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_q, qs.data(), (size_t)n * 8, hipMemcpyHostToDevice, L->stream);
     }
     if (e == hipSuccess) e = hipMemsetAsync(d_xy, 0, 16, L->stream);
     if (e == hipSuccess && forces) e = hipMemsetAsync(d_fsum, 0, cap * 24, L->stream);
@@ -747,6 +764,7 @@ int lattice_set_offlattice_charges(lattice_t* L, int64_t n, const double* r, con
     L->d_fsq = d_fsq;
     L->offl = true;
     L->n_off = (uint32_t)n;
+    L->off_order = std::move(order);
     L->n_sites = 0;
     L->n_raw = n;
     L->meas_blocks = blocks;
@@ -778,11 +796,12 @@ int lattice_force_estimate(lattice_t* L, double* dE_dr, double* stderr_naive, in
     if (e != hipSuccess) return hip_fail(e, "force readback");
     if (M < 2) return set_error(LAT_ERR_STATE, "fewer than 2 force samples");
     for (size_t i = 0; i < k; ++i) {
+        const size_t o = 3 * (size_t)(*L->off_order)[i / 3] + i % 3;  // the caller's order
         const double mean = s[i] / (double)M;
-        if (dE_dr) dE_dr[i] = mean;
+        if (dE_dr) dE_dr[o] = mean;
         if (stderr_naive) {
             const double var = std::max(0.0, (s2[i] - (double)M * mean * mean) / (double)(M - 1));
-            stderr_naive[i] = std::sqrt(var / (double)M);
+            stderr_naive[o] = std::sqrt(var / (double)M);
         }
     }
     return LAT_OK;

@@ -71,6 +71,10 @@ struct lattice {
     double* d_fsum = nullptr;  // 3 n_off force sums (null: forces off)
     double* d_fsq = nullptr;
     int64_t force_base = 0;    // n_meas when the force sums were last cleared
+    // off-lattice charges are stored sorted by cell (neighbouring charges then
+    // share the cache lines of their corners); off_order[k] = the caller's
+    // index of stored charge k
+    std::shared_ptr<const std::vector<uint32_t>> off_order;
     // host copy of the aggregated list of a single on-lattice charge set
     // (shared: copies of the handle made by the autotuner do not copy it)
     struct HostCharges {
