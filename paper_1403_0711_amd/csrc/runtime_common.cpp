@@ -89,7 +89,7 @@ EstimateResult estimate_from_bins(const double* bins, int64_t used_bins, int64_t
         s = t;
     }
     r.mean = n_samples > 0 ? s / (double)n_samples : 0.0;
-    const int64_t nf = n_samples / bin_size;
+    const int64_t nf = std::min<int64_t>(n_samples / bin_size, used_bins);  // full bins that are present
     r.full_bins = nf;
     if (nf < 2) {
         r.stderr_binned = NAN;
