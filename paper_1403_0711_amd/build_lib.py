@@ -55,7 +55,9 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, srcs))
-    cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", LIB + ".tmp"]
+    # roctx: named ranges around the runtime's calls for rocprofv3 --marker-trace
+    cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-lrocprofiler-sdk-roctx", "-o",
+           LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

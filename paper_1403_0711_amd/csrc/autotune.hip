@@ -136,6 +136,7 @@ extern "C" {
 
 int lattice_autotune(lattice_t* L, int64_t reps, int* variant, int64_t* planes, int* tile, int* xcd_order,
                      double* ms_per_sweep) {
+    TraceRange tr("autotune");
     if (int r = check_lattice(L)) return r;
     if (reps < 1 || reps > 1000) return set_error(LAT_ERR_ARG, "reps must be in [1, 1000]");
     TuneChoice ch;

@@ -197,6 +197,7 @@ int batch_set_charges(lattice_batch_t* B, int64_t chain, int64_t n, const int32_
 }
 
 int batch_run(lattice_batch_t* B, int64_t n_therm, int64_t n_meas, int64_t bin_size) {
+    TraceRange tr("batch_run");
     if (int r = check_batch(B)) return r;
     if (n_therm < 0 || n_meas < 0) return set_error(LAT_ERR_ARG, "negative sweep count");
     if (bin_size < 1) return set_error(LAT_ERR_ARG, "bin_size < 1");

@@ -494,6 +494,7 @@ static void release_offlattice(lattice* L) {
 
 int lattice_set_charge_sets(lattice_t* L, int64_t n_sets, const int64_t* counts, const int32_t* xyz,
                             const double* q) {
+    TraceRange tr("set_charges");
     if (int r = check_lattice(L)) return r;
     if (n_sets < 1 || n_sets > kMaxChargeSets) return set_error(LAT_ERR_ARG, "n_sets must be in [1, 65535]");
     if (!counts) return set_error(LAT_ERR_ARG, "counts is NULL");
@@ -609,6 +610,7 @@ int set_charges(lattice_t* L, int64_t n, const int32_t* xyz, const double* q) {
 }
 
 int thermalise(lattice_t* L, int64_t n_sweeps) {
+    TraceRange tr("thermalise");
     if (int r = check_lattice(L)) return r;
     if (n_sweeps < 0) return set_error(LAT_ERR_ARG, "n_sweeps < 0");
     if (L->t + n_sweeps > (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_ARG, "sweep counter would exceed 2^31");
@@ -617,6 +619,7 @@ int thermalise(lattice_t* L, int64_t n_sweeps) {
 }
 
 int sweep_and_measure(lattice_t* L, int64_t n_sweeps, int64_t measure_every, int64_t bin_size) {
+    TraceRange tr("sweep_and_measure");
     if (int r = check_lattice(L)) return r;
     if (n_sweeps < 0) return set_error(LAT_ERR_ARG, "n_sweeps < 0");
     if (measure_every < 1) return set_error(LAT_ERR_ARG, "measure_every < 1");
@@ -645,6 +648,7 @@ int sweep_and_measure(lattice_t* L, int64_t n_sweeps, int64_t measure_every, int
 
 int lattice_energy_estimate_set(lattice_t* L, int64_t set, double* mean, double* stderr_binned,
                                 int64_t* n_samples, int64_t* n_bins) {
+    TraceRange tr("energy_estimate");
     if (int r = check_lattice(L)) return r;
     if (set < 0 || set >= (int64_t)L->n_sets) return set_error(LAT_ERR_ARG, "no such charge set");
     const int64_t M = L->n_meas;
@@ -671,6 +675,7 @@ int energy_estimate(lattice_t* L, double* mean, double* stderr_binned, int64_t* 
 }
 
 int lattice_set_offlattice_charges(lattice_t* L, int64_t n, const double* r, const double* q, int forces) {
+    TraceRange tr("set_offlattice_charges");
     if (int r_ = check_lattice(L)) return r_;
     if (n < 0 || n >= (int64_t)0xFFFFFFFF) return set_error(LAT_ERR_ARG, "bad charge count");
     if (n > 0 && (!r || !q)) return set_error(LAT_ERR_ARG, "r or q is NULL");

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include <string>
@@ -17,6 +18,16 @@ int set_error(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* where);
 
 inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// A named roctx range for the lifetime of the object (a runtime call as seen
+// by rocprofv3 --marker-trace; nothing is recorded without a profiler).
+class TraceRange {
+  public:
+    explicit TraceRange(const char* name) { roctxRangePush(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Device memory from the caller's provider, or hipMalloc/hipFree.
 class DeviceAllocator {
