@@ -433,7 +433,14 @@ def cpu_baseline(cs, storage: str, seed: int):
         dt1 = time.perf_counter() - t1
     finally:
         lib.orc_set_threads(cores)
-    return {"value": V / dt, "unit": "site updates/s", "cores": cores,
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    return {"value": V / dt, "unit": "site updates/s", "cores": cores, "host_cpu": model,
+            "host_cpus_online": os.cpu_count(),
             "kind": "oracle",
             "sample": f"1 measured sweep of the full {cs.shape[0]}x{cs.shape[1]}x{cs.shape[2]} "
                       f"box with all {cs.n} charges ({dt:.1f} s)",

@@ -283,6 +283,28 @@ def test_empty_charges_and_edge_cases(lat_mod):
     assert M == 3 and nb == 1 and np.isnan(se)
 
 
+def test_non_finite_sample_is_detected(lat_mod):
+    """A corrupted checkpoint with a non-finite bin (the host can force
+    nothing else: fields and charges are checked on entry) is caught by the
+    estimate's finite check: LAT_ERR_STATE, and later samples still add."""
+    print("[gpu] non-finite sample", flush=True)
+    lat = lat_mod.Lattice((8, 8, 8), seed=1)
+    lat.set_charges([[1, 1, 1], [5, 5, 5]], [1.0, -1.0])
+    lat.sweep_and_measure(8, 1, 2)
+    t, n, bins = lat.get_state()
+    assert n == 8 and bins.shape == (4, 2)
+    bad = bins.copy()
+    bad[1, 0] = np.nan
+    lat.set_state(t, n, 2, bad)
+    with pytest.raises(lat_mod.LatticeError) as ei:
+        lat.energy_estimate()
+    assert ei.value.code == 2 and "non-finite" in str(ei.value)
+    lat.set_state(t, n, 2, bins)  # the intact checkpoint restores a finite estimate
+    lat.sweep_and_measure(4, 1, 2)
+    m, se, M, nb = lat.energy_estimate()
+    assert M == 12 and nb == 6 and np.isfinite(m) and np.isfinite(se)
+
+
 def test_argument_errors(lat_mod):
     print("[gpu] argument errors", flush=True)
     lat = lat_mod.Lattice((8, 6, 4), seed=1)
