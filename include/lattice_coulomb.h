@@ -248,8 +248,15 @@ int lattice_use_graphs(lattice_t *lat, int mode);
 /* Autotuner: time every sweep kernel and tuning that can handle this box
  * (reps sweeps each, after one warm-up sweep) on scratch memory of the
  * handle's size, so the chain itself is not advanced; select the fastest on
- * the handle and cache it per (box, storage) for the process.  Outputs (any
- * may be NULL): the chosen variant, planes, tile, XCD order and the measured
+ * the handle and cache it per (device architecture, box, storage, whether
+ * the single-workgroup kernel may run: one on-lattice charge set) for the
+ * process.  If the environment variable LATCOUL_TUNE_CACHE names a file, the
+ * choices it holds are used too (read once per process; a choice that names
+ * a kernel or tuning this library lacks for the box is ignored) and new
+ * choices are appended to it, one line "arch lx ly lz storage single variant
+ * planes tile xcd_order ms" each; a file that cannot be read or written is
+ * ignored.  Outputs (any may be NULL): the chosen variant, planes, tile, XCD
+ * order and the measured
  * ms per sweep.  Synchronises the stream.  Errors: LAT_ERR_ARG for reps
  * outside [1, 1000]; LAT_ERR_ALLOC if the scratch cannot be allocated. */
 int lattice_autotune(lattice_t *lat, int64_t reps, int *variant, int64_t *planes, int *tile,

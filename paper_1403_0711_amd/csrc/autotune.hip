@@ -1,20 +1,65 @@
 // The autotuner: times every sweep kernel and tuning that can handle a box
-// on scratch memory and keeps the fastest; choices are cached per (box,
-// storage).
+// on scratch memory and keeps the fastest.  Choices are cached per (device
+// architecture, box, storage, whether the single-workgroup kernel may run)
+// for the process, and, when LATCOUL_TUNE_CACHE names a file, in that file
+// across processes (one line per choice, appended).
 
 #include "lattice_impl.hpp"
 
-// ---------------------------------------------------------------------------
-// Autotuner: times every sweep kernel and tuning that can handle a box on
-// scratch memory, keeps the fastest; choices are cached per (box, storage).
-// ---------------------------------------------------------------------------
+#include <cstdio>
+#include <cstdlib>
+
 struct TuneChoice {
     int variant;
     uint32_t slab, tile, xcd;
     double ms;
 };
+using TuneKey = std::tuple<std::string, int64_t, int64_t, int64_t, int, int>;
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int64_t, int64_t, int64_t, int>, TuneChoice> g_tune_cache;
+static std::map<TuneKey, TuneChoice> g_tune_cache;
+static bool g_tune_file_read = false;
+
+// Whether a choice (from the file, so possibly from another build) names a
+// kernel and tuning this library has for the box.
+static bool choice_valid(const lattice* L, const TuneChoice& c, bool resident_ok) {
+    StreamTileShape sh;
+    if (c.xcd > 2 || c.slab > (uint64_t)L->lz || !(c.ms >= 0.0)) return false;
+    switch (c.variant) {
+        case LAT_SWEEP_GENERIC: return true;
+        case LAT_SWEEP_QUAD: return L->lh % 4 == 0;
+        case LAT_SWEEP_RESIDENT: return resident_ok && (uint64_t)L->vh * 2 <= ((uint64_t)1 << 18);
+        case LAT_SWEEP_ZSLAB: return L->lh % 4 == 0 && c.tile < (uint32_t)kZslabTiles;
+        case LAT_SWEEP_STREAM: return L->lh % 4 == 0 && stream_tile_geometry(c.tile, L->esz, &sh);
+        case LAT_SWEEP_FUSED: return L->lh % 4 == 0 && fused_sweep_supported(L->lh, (uint32_t)L->ly);
+        default: return false;
+    }
+}
+
+// Lines "arch lx ly lz storage resident_ok variant slab tile xcd ms"; lines
+// that do not parse are skipped.  Called with g_tune_mu held.
+static void read_tune_file(const char* path) {
+    g_tune_file_read = true;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[128];
+    long long lx, ly, lz;
+    int storage, rok, variant;
+    unsigned slab, tile, xcd;
+    double ms;
+    while (std::fscanf(f, "%127s %lld %lld %lld %d %d %d %u %u %u %lf", arch, &lx, &ly, &lz, &storage, &rok,
+                       &variant, &slab, &tile, &xcd, &ms) == 11)
+        g_tune_cache[TuneKey(arch, lx, ly, lz, storage, rok)] = TuneChoice{variant, slab, tile, xcd, ms};
+    std::fclose(f);
+}
+
+static void append_tune_file(const char* path, const TuneKey& k, const TuneChoice& c) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;  // the cache file is an optimisation: an unwritable one is ignored
+    std::fprintf(f, "%s %lld %lld %lld %d %d %d %u %u %u %.6f\n", std::get<0>(k).c_str(), (long long)std::get<1>(k),
+                 (long long)std::get<2>(k), (long long)std::get<3>(k), std::get<4>(k), std::get<5>(k), c.variant,
+                 c.slab, c.tile, c.xcd, c.ms);
+    std::fclose(f);
+}
 
 // Candidates in order of preference: the first is the library default for
 // the box; a later one replaces the current best only if it is more than 3%
@@ -65,11 +110,22 @@ static void apply_choice(lattice* L, const TuneChoice& ch) {
 }
 
 static int autotune(lattice* L, int64_t reps, TuneChoice* out) {
-    const auto key = std::make_tuple(L->lx, L->ly, L->lz, L->storage);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t pe = hipGetDevice(&dev);
+    if (pe == hipSuccess) pe = hipGetDeviceProperties(&prop, dev);
+    if (pe != hipSuccess) return hip_fail(pe, "device properties");
+    std::string arch(prop.gcnArchName);
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    const bool resident_ok = L->n_sets == 1 && !L->offl;
+    const TuneKey key(arch, L->lx, L->ly, L->lz, L->storage, resident_ok ? 1 : 0);
+    const char* path = std::getenv("LATCOUL_TUNE_CACHE");
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
+        if (path && *path && !g_tune_file_read) read_tune_file(path);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
+        if (it != g_tune_cache.end() && choice_valid(L, it->second, resident_ok)) {
             *out = it->second;
             return LAT_OK;
         }
@@ -127,6 +183,7 @@ static int autotune(lattice* L, int64_t reps, TuneChoice* out) {
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         g_tune_cache[key] = best;
+        if (path && *path) append_tune_file(path, key, best);
     }
     *out = best;
     return LAT_OK;

@@ -12,12 +12,17 @@ Tolerances:
     tests.
 """
 
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 from oracle import exact as ex
 from paper_1403_0711_amd import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.gpu
 
@@ -471,6 +476,46 @@ def test_autotune_does_not_advance_the_chain(lat_mod):
     # cached: a second lattice of the same box gets the same choice
     again = lat_mod.Lattice(shape, seed=4).autotune(reps=2)
     assert again["variant"] == choice["variant"] and again["planes"] == choice["planes"]
+
+
+def test_autotune_cache_respects_charge_sets(lat_mod):
+    """A small box tuned with one charge set may run the single-workgroup
+    kernel; the same box with two sets is tuned apart and never gets it."""
+    print("[gpu] autotune cache key", flush=True)
+    shape = (16, 16, 16)
+    one = lat_mod.Lattice(shape, seed=1)
+    one.set_charges([[1, 1, 1], [9, 9, 9]], [1.0, -1.0])
+    c1 = one.autotune(reps=2)
+    two = lat_mod.Lattice(shape, seed=1)
+    two.set_charge_sets([([[1, 1, 1]], [1.0]), ([[9, 9, 9]], [-1.0])])
+    c2 = two.autotune(reps=2)
+    assert c2["variant"] != "resident"
+    two.sweep_and_measure(20, 1, 5)
+    assert two.energy_estimate(charge_set=1)[2] == 20
+    assert c1["variant"] in ("resident", "quad", "generic", "zslab", "stream", "fused")
+
+
+def test_autotune_cache_file(lat_mod, tmp_path):
+    """LATCOUL_TUNE_CACHE: a fresh process tunes and appends its choice; a
+    second one reads it back without tuning again."""
+    import subprocess
+    import sys
+
+    print("[gpu] autotune cache file", flush=True)
+    cache = tmp_path / "tune.txt"
+    code = ("import json; from paper_1403_0711_amd import lattice; lattice.load_library(); "
+            "print(json.dumps(lattice.Lattice((32, 24, 20), seed=1).autotune(reps=2)))")
+    env = dict(os.environ, LATCOUL_TUNE_CACHE=str(cache))
+    runs = []
+    for _ in range(2):
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=180, env=env,
+                           cwd=ROOT)
+        assert r.returncode == 0, r.stderr
+        runs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:4] == ["32", "24", "20"]
+    ms = [r.pop("ms_per_sweep") for r in runs]
+    assert runs[0] == runs[1] and abs(ms[0] - ms[1]) <= 1e-6  # the same choice and its stored time
 
 
 @pytest.mark.parametrize("variant", ["quad", "zslab", "fused", "generic", "stream"])
