@@ -41,14 +41,15 @@ static void read_tune_file(const char* path) {
     g_tune_file_read = true;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    char arch[128];
+    char line[512], arch[128];
     long long lx, ly, lz;
     int storage, rok, variant;
     unsigned slab, tile, xcd;
     double ms;
-    while (std::fscanf(f, "%127s %lld %lld %lld %d %d %d %u %u %u %lf", arch, &lx, &ly, &lz, &storage, &rok,
-                       &variant, &slab, &tile, &xcd, &ms) == 11)
-        g_tune_cache[TuneKey(arch, lx, ly, lz, storage, rok)] = TuneChoice{variant, slab, tile, xcd, ms};
+    while (std::fgets(line, sizeof line, f))
+        if (std::sscanf(line, "%127s %lld %lld %lld %d %d %d %u %u %u %lf", arch, &lx, &ly, &lz, &storage, &rok,
+                        &variant, &slab, &tile, &xcd, &ms) == 11)
+            g_tune_cache[TuneKey(arch, lx, ly, lz, storage, rok)] = TuneChoice{variant, slab, tile, xcd, ms};
     std::fclose(f);
 }
 

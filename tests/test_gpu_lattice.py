@@ -514,6 +514,12 @@ def test_autotune_cache_file(lat_mod, tmp_path):
         runs.append(json.loads(r.stdout.strip().splitlines()[-1]))
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and lines[0].split()[1:4] == ["32", "24", "20"]
+    # a malformed line and a choice this library lacks are skipped; the good line still serves
+    cache.write_text("not a cache line\n" + lines[0].split()[0] + " 32 24 20 0 1 6 16 99 1 0.1\n" + lines[0] + "\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=180, env=env, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    third = json.loads(r.stdout.strip().splitlines()[-1])
+    assert third["variant"] == runs[0]["variant"] and len(cache.read_text().splitlines()) == 3
     ms = [r.pop("ms_per_sweep") for r in runs]
     assert runs[0] == runs[1] and abs(ms[0] - ms[1]) <= 1e-6  # the same choice and its stored time
 
