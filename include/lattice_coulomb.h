@@ -78,7 +78,9 @@ enum { LAT_FP32 = 0, LAT_BF16 = 1, LAT_FP16 = 2 }; /* field storage format */
 
 /* Sweep kernel selection for lattice_set_variant. */
 enum {
-    LAT_SWEEP_AUTO = 0,    /* library choice                                       */
+    LAT_SWEEP_AUTO = 0,    /* library choice: resident (<= 16,384 sites, one on-lattice
+                              set), generic (lx % 8 != 0), stream (fields >= 256 MB),
+                              zslab (FP32/BF16 from 2^23 sites), else quad             */
     LAT_SWEEP_QUAD = 1,    /* 4 sites per thread, one pass per half-sweep (lx % 8 == 0) */
     LAT_SWEEP_GENERIC = 2, /* 1 site per thread, any even lx                        */
     LAT_SWEEP_ZSLAB = 3,   /* z-marching slabs, plane staged in LDS (lx % 8 == 0)   */
@@ -202,11 +204,12 @@ int lattice_set_variant(lattice_t *lat, int variant);
 /* Tuning of the slab kernels (LAT_SWEEP_ZSLAB, LAT_SWEEP_STREAM, and the
  * planes of LAT_SWEEP_FUSED): planes of the box one workgroup walks along z
  * (0 = library default: 24 for the streaming kernel's full-row FP32 tile 9,
- * else 16 at FP32 and 32 at 16-bit storage; at most lz); tile configuration
+ * 8 for the z-slab kernel when the library chose it (LAT_SWEEP_AUTO), else
+ * 16 at FP32 and 32 at 16-bit storage; at most lz); tile configuration
  * (-1 = library default: for LAT_SWEEP_STREAM 96-quad tiles at FP32 where
  * they divide the rows, else 32-quad tiles, with non-temporal stores where a
- * colour array is at least 256 MiB: tiles 9 / 6 / 0 / 3; tile 0 for the
- * other kernels): 0..7 for LAT_SWEEP_ZSLAB (workgroup tile width x rows and
+ * colour array is at least 256 MiB: tiles 9 / 6 / 0 / 3; tile 7 for the
+ * z-slab kernel the library chose; tile 0 for the other kernels): 0..7 for LAT_SWEEP_ZSLAB (workgroup tile width x rows and
  * register budget), 0..9 for LAT_SWEEP_STREAM (tile width 128..512 sites,
  * rows, depth of the LDS plane ring, non-temporal stores); xcd_order, the
  * order of workgroups over the chip's 8 XCDs: 0 the hardware's round-robin

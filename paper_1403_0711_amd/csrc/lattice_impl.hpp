@@ -34,6 +34,8 @@ constexpr uint32_t kStreamTileCached = 3;           // 32 quads x 8 rows, 6-slot
 // at 16-bit storage, where arithmetic binds and longer slabs amortise each
 // workgroup's start-up.
 inline uint32_t default_slab(size_t esz) { return esz == 4 ? 16u : 32u; }
+constexpr uint64_t kZslabAutoMinSites = (uint64_t)1 << 23;  // 8.4e6 sites: between 192^3 and 208^3
+constexpr uint32_t kZslabTileAuto = 7;
 
 struct lattice {
     int64_t lx = 0, ly = 0, lz = 0;
@@ -146,6 +148,7 @@ struct lattice {
     // written colour there for the next half-sweep).
     uint32_t resolved_tile(int v) const {
         if (tile != kTileDefault) return tile;
+        if (v == LAT_SWEEP_ZSLAB && auto_zslab()) return kZslabTileAuto;
         if (v != LAT_SWEEP_STREAM) return 0u;
         const bool wide = esz == 4 && (lh / 4) % 96 == 0;
         const bool nt = (size_t)vh * esz >= ((size_t)256 << 20);
@@ -162,7 +165,11 @@ struct lattice {
     bool full_row_default(int v) const {
         return v == LAT_SWEEP_STREAM && esz == 4 && resolved_tile(v) == kStreamTileFullRow96;
     }
-    uint32_t resolved_slab(int v) const { return slab ? slab : full_row_default(v) ? 24u : default_slab(esz); }
+    uint32_t resolved_slab(int v) const {
+        if (slab) return slab;
+        if (v == LAT_SWEEP_ZSLAB && auto_zslab()) return 8u;
+        return full_row_default(v) ? 24u : default_slab(esz);
+    }
     uint32_t resolved_xcd(int v) const { return xcd_order >= 0 ? (uint32_t)xcd_order : full_row_default(v) ? 2u : 1u; }
     double* last_xy() { return d_lastxy ? d_lastxy : reinterpret_cast<double*>(static_cast<char*>(d_misc) + 64); }
     uint32_t* counters() { return static_cast<uint32_t*>(d_misc); }  // [0] sweeps, [1] samples
@@ -177,8 +184,22 @@ struct lattice {
         // boxes that spill out of the 256 MB last-level cache: z-marching slabs
         // fed through LDS by a producer wave (colour arrays below 2 GiB)
         const size_t bytes = (size_t)vh * esz;
-        return (2 * bytes >= ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) ? LAT_SWEEP_STREAM : LAT_SWEEP_QUAD;
+        if (2 * bytes >= ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) return LAT_SWEEP_STREAM;
+        // cache-resident boxes from about 200^3 sites: the z-slab kernel keeps
+        // each plane in LDS (measured per sweep against the quad kernel, FP32:
+        // -27% at 208^3, -36% at 240^3, equal at 256^3, -34% at 264^3 .. 304^3,
+        // -18% at 320^3, -4% at 384^3; BF16: equal at 208^3 and 256^3, -9% to
+        // -18% from 240^3 to 448^3).  FP16 storage, whose quad kernel adds
+        // neighbours in mixed-precision FMAs, and smaller boxes (quad -20% at
+        // 192^3, -55% at 128^3) stay with the quad kernel
+        if (esz == 4 || storage == LAT_BF16)
+            if ((uint64_t)vh * 2 >= kZslabAutoMinSites) return LAT_SWEEP_ZSLAB;
+        return LAT_SWEEP_QUAD;
     }
+    // the library chose the z-slab kernel for a cache-resident box: its
+    // tuning there is 16 x 16 tiles with 4 planes per step (tile 7), 8 planes
+    // per workgroup
+    bool auto_zslab() const { return variant == LAT_SWEEP_AUTO && effective_variant() == LAT_SWEEP_ZSLAB; }
 };
 
 

@@ -451,7 +451,17 @@ def test_default_tuning_resolution(lat_mod):
     lat.set_variant("zslab")
     assert lat.tuning()["tile"] == 0
     lat.close()
-    assert lat_mod.Lattice((384, 384, 384)).tuning()["variant"] == "quad"  # 2 x 113 MB
+    # cache-resident boxes from ~200^3 sites at FP32 and BF16: the z-slab kernel, 16 x 16 tiles, 8 planes
+    auto_zslab = {"variant": "zslab", "planes": 8, "tile": 7, "xcd_order": True}
+    assert lat_mod.Lattice((384, 384, 384)).tuning() == auto_zslab  # 2 x 113 MB
+    assert lat_mod.Lattice((448, 448, 448), "bf16").tuning() == auto_zslab  # 2 x 90 MB
+    assert lat_mod.Lattice((384, 384, 384), "fp16").tuning()["variant"] == "quad"  # mixed-precision adds
+    assert lat_mod.Lattice((256, 256, 256)).tuning() == auto_zslab
+    assert lat_mod.Lattice((192, 192, 192)).tuning()["variant"] == "quad"
+    z = lat_mod.Lattice((384, 384, 384))
+    z.set_variant("zslab")  # chosen explicitly: that kernel's own defaults
+    assert z.tuning() == {"variant": "zslab", "planes": 16, "tile": 0, "xcd_order": True}
+    z.close()
     assert lat_mod.Lattice((64, 64, 64)).tuning()["variant"] == "quad"
     assert lat_mod.Lattice((16, 16, 16)).tuning()["variant"] == "resident"
 
