@@ -77,13 +77,15 @@ static std::vector<TuneChoice> tune_candidates(const lattice* L) {
         return c;
     }
     const bool slab_ok = (size_t)L->vh * L->esz < ((size_t)1 << 31);
-    if (slab_ok && (size_t)2 * L->vh * L->esz >= ((size_t)256 << 20)) {
-        lattice d = *L;  // the library's own choice for the box
+    if (slab_ok) {
+        lattice d = *L;  // the library's own choice for the box, when it is a slab kernel
+        d.variant = LAT_SWEEP_AUTO;
         d.slab = 0;
         d.tile = kTileDefault;
         d.xcd_order = -1;
-        c.push_back({LAT_SWEEP_STREAM, d.resolved_slab(LAT_SWEEP_STREAM), d.resolved_tile(LAT_SWEEP_STREAM),
-                     d.resolved_xcd(LAT_SWEEP_STREAM), 0});
+        const int v = d.effective_variant();
+        if (v == LAT_SWEEP_STREAM || v == LAT_SWEEP_ZSLAB)
+            c.push_back({v, d.resolved_slab(v), d.resolved_tile(v), d.resolved_xcd(v), 0});
     }
     c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
     if (V > kResidentMaxSites && V <= (uint64_t)1 << 18 && resident_ok)
