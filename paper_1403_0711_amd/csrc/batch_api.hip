@@ -18,6 +18,7 @@ struct lattice_batch {
     int64_t n = 0;
     int storage = 0;
     size_t esz = 4;
+    size_t field_bytes = 0;  // all chains' fields
     uint64_t seed = 0;
     DeviceAllocator mem;
     hipStream_t stream = nullptr;
@@ -147,6 +148,7 @@ int batch_create(int64_t n_chains, const int64_t* edges, const uint32_t* chain_i
     B->n = n_chains;
     B->storage = storage;
     B->esz = esz;
+    B->field_bytes = (size_t)off * esz;
     B->seed = seed;
     B->mem = DeviceAllocator(alloc);
     B->stream = static_cast<hipStream_t>(hip_stream);
@@ -238,6 +240,9 @@ int batch_run(lattice_batch_t* B, int64_t n_therm, int64_t n_meas, int64_t bin_s
     a.k0 = (uint32_t)B->seed;
     a.k1 = (uint32_t)(B->seed >> 32);
     a.storage = B->storage;
+    // fields that fill the 256 MiB last-level cache: the chains wait on memory,
+    // where the half-sweep through an LDS ring is faster
+    a.ring = B->field_bytes >= ((size_t)256 << 20);
     a.single = false;
     e = launch_batch(a, B->stream);
     if (e != hipSuccess) return hip_fail(e, "batch launch");

@@ -176,6 +176,7 @@ struct BatchArgs {
     uint32_t n_therm, n_meas, every, bin_size;
     uint32_t k0, k1;
     int storage;
+    bool ring;                   // batch: the LDS-ring half-sweep where a chain's planes allow it
     bool single;                 // one lattice: descriptor passed by value
     BatchChainDesc single_desc;
     double* last_xy;             // single: X, Y of the last sample (or null)

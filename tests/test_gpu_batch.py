@@ -67,6 +67,50 @@ def test_batch_matches_single_lattices(lat_mod):
         assert b.energy_estimate(k)[2] == 30
 
 
+# chains past the single-workgroup size, so that the single lattices run the
+# quad kernel: at most 1024 quads per plane (the LDS ring path; 128 x 64 at
+# the ring's full span of 1024, 48 x 40 over eight chunks with a ragged last
+# one) and wider planes (136 x 64: 1088 quads, the two-quads-per-thread path)
+RING_EDGES = [(128, 64, 4), (136, 64, 3), (48, 40, 30), (32, 32, 32)]
+
+
+# 64^3 chains that bring a batch's fields to the 256 MiB at which the batch
+# sweeps through the LDS ring (two 64^3 colour arrays: 1 MiB at FP32)
+def _fillers(storage):
+    return [(64, 64, 64)] * (256 if storage == "fp32" else 512)
+
+
+@pytest.mark.parametrize("storage,filled", [("fp32", False), ("fp32", True), ("bf16", True), ("fp16", True)])
+def test_batch_ring_matches_quad_kernel(lat_mod, storage, filled):
+    """Batched chains equal single lattices swept by the quad kernel, bit for
+    bit: in a small batch (the half-sweep from memory) and in batches filled
+    to the size that takes the LDS ring, in every storage format, on both
+    sides of the ring's plane limit."""
+    print(f"[gpu] batch vs quad kernel {storage} filled={filled}", flush=True)
+    seed = 777
+    ids = [3, 11, 0, 42]
+    edges = RING_EDGES + (_fillers(storage) if filled else [])
+    b = lat_mod.Batch(edges, storage, seed=seed, chain_ids=ids + list(range(100, 100 + len(edges) - 4)))
+    singles = []
+    for k, e in enumerate(RING_EDGES):
+        xyz, q = _charges(e, 8, 100 + k)
+        b.set_charges(k, xyz, q)
+        s = lat_mod.Lattice(e, storage, seed=seed, chain_id=ids[k])
+        s.set_variant("quad")
+        s.set_charges(xyz, q)
+        singles.append(s)
+    b.run(3, 6, 3)
+    for s in singles:
+        s.thermalise(3)
+        s.sweep_and_measure(6, 1, 3)
+    for k, s in enumerate(singles):
+        assert np.array_equal(b.get_field(k), s.get_field()), (storage, RING_EDGES[k])
+        mb, Mb = b.energy_estimate(k)[0], b.energy_estimate(k)[2]
+        ms, Ms = s.energy_estimate()[0], s.energy_estimate()[2]
+        assert Mb == Ms == 6
+        assert abs(mb - ms) <= 1e-9 * max(1.0, abs(ms)), (storage, RING_EDGES[k])
+
+
 def test_batch_chain_matches_oracle(lat_mod):
     print("[gpu] batch chain vs oracle", flush=True)
     seed = 99
