@@ -15,7 +15,7 @@ pick with --variant tuned) from HIP events around its own launches on the
 library's stream, the time to a 1% statistical error on E_N
 (extrapolated from the measured binned error and the exact lattice energy
 stored in tests/golden/exact_energies.json), the same sweep with FP16 field
-storage, the 512-chain batched workload and the time to a 1% error on the 16^3
+storage, the 512-chain batched workload, a dense batch (256 chains of 64^3), the time to a 1% error on the 16^3
 workload (256 batched chains against one chain) for comparison, and the CPU oracle
 timed on a bounded sample of the same workload; with extras, also a coupled
 FP32 / BF16 / FP16 comparison on the 384^3 Gaussian blob (bias of the 16-bit
@@ -204,6 +204,23 @@ def batched_comparison(sweeps, torch, lattice, workloads):
     sites = sum(int(np.prod(c.shape)) for c in chains)
     b.close()
     return {"chains": len(chains), "sites": sites, "sweeps": sweeps, "seconds": dt,
+            "site_updates_per_s": sites * sweeps / dt}
+
+
+def dense_batch(sweeps, torch, lattice):
+    """256 chains of 64^3 with no charges (1 MiB of FP32 field each, 256 MiB
+    in all: the size from which a batch sweeps through the LDS ring)."""
+    shapes = [(64, 64, 64)] * 256
+    b = lattice.Batch(shapes, "fp32", seed=0)
+    b.run(2, 10, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(0, sweeps, 10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    sites = 256 * 64 ** 3
+    return {"chains": 256, "edge": 64, "sweeps": sweeps, "ms_per_sweep": 1e3 * dt / sweeps,
             "site_updates_per_s": sites * sweeps / dt}
 
 
@@ -552,6 +569,7 @@ def main():
                 f16["speedup_vs_fp32"] = ms_per_step / f16["ms_per_step"]
                 out["fp16_storage"] = f16
             out["batched_512"] = batched_comparison(200, torch, lattice, workloads)
+            out["batched_256x64"] = dense_batch(100, torch, lattice)
             out["time_to_1pct_16"] = time_to_1pct_measured(torch, lattice, workloads)
             out["precision_coupled"] = precision_coupled(args.coupled_sweeps, torch, lattice, workloads)
             out["figures_128"] = figures_comparison(args.figures_sweeps)
