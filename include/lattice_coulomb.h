@@ -310,7 +310,7 @@ int batch_set_charges(lattice_batch_t *b, int64_t chain, int64_t n, const int32_
 
 /* Enqueue n_therm sweeps then n_meas measured sweeps (one sample per sweep,
  * bins of bin_size) for every chain, in one persistent launch.  Batches whose
- * fields fill the 256 MiB last-level cache sweep chains of at most 1024 quads
+ * fields fill the 256 MiB last-level cache sweep chains of at most 3072 quads
  * (4 compact sites) per plane through an LDS ring, each value loaded from
  * memory once per half-sweep; the chains' fields are the same either way. */
 int batch_run(lattice_batch_t *b, int64_t n_therm, int64_t n_meas, int64_t bin_size);

@@ -18,8 +18,11 @@ constexpr int kBatchThreads = 1024;
 // LDS ring of the other colour's quads, indexed by quad number modulo its
 // size: a chunk of kBatchThreads quads reads one plane (qpp quads) on either
 // side of it while the next chunk's new quads are written, so 2 * 1024 + 2 *
-// qpp <= 4096 holds every chain with at most 1024 quads per plane
-constexpr uint32_t kRingQuads = 4096;
+// qpp <= 8192 holds every chain with at most 3072 quads per plane.  128 KiB
+// at FP32, within gfx950's 160 KiB per workgroup; the kernel's registers
+// allow one 1024-thread workgroup per CU in any case.
+constexpr uint32_t kRingQuads = 8192;
+constexpr uint32_t kRingMaxPlaneQuads = (kRingQuads - 2u * kBatchThreads) / 2u;
 
 // One raw quad (4 elements) of a storage format
 template <class St>
@@ -55,15 +58,16 @@ __device__ __forceinline__ QuadNeighbours<St> quad_load_ring(const typename St::
 }
 
 // One half-sweep of colour c over a whole chain by one workgroup, in one of
-// three forms.  use_ring, lh % 4 == 0 and at most 1024 quads (4 compact sites
+// three forms.  use_ring, lh % 4 == 0 and at most 3072 quads (4 compact sites
 // of a row each) per plane: chunks of 1024 consecutive quads, one per thread, whose
 // neighbours are read from an LDS ring of the other colour (each quad loaded
 // from memory once per half-sweep); the load of the thread's quad of the next
 // chunk is in flight while it updates this one, and a workgroup barrier ends
-// each chunk.  The quads chunk 0 reads (the first 1024 + qpp) are the ones
-// chunks 0 and 1 of the previous half-sweep updated: each thread keeps its two
-// results and writes them into the ring after its last chunk, so that only
-// the first half-sweep of a launch (seeded false) loads them from memory.
+// each chunk.  The quads chunk 0 reads (the first 1024 + qpp) are, up to
+// 2048 of them, the ones chunks 0 and 1 of the previous half-sweep updated:
+// each thread keeps its two results and writes them into the ring after its
+// last chunk, so that only the first half-sweep of a launch (seeded false)
+// loads them from memory (planes over 1024 quads load the rest each time).
 // The ring pays where the chains wait on memory (fields that fill the
 // last-level cache: 256 chains of 64^3 sweep 12% faster); a chain bound by
 // its CU's arithmetic runs 10% slower with it (the ring's address arithmetic
@@ -83,14 +87,17 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
     T* own = field + (size_t)c * d.vh;
     const uint32_t lh = d.lh, ly = d.ly, lz = d.lz, plane = ly * lh;
     const float sixth = 1.0f / 6.0f;
-    if (use_ring && (lh & 3u) == 0 && (lh >> 2) * ly <= (uint32_t)kBatchThreads) {
+    if (use_ring && (lh & 3u) == 0 && (lh >> 2) * ly <= kRingMaxPlaneQuads) {
         using Raw = RawQuad<St>;
         const uint32_t nq = lh >> 2, qpp = nq * ly, nquads = d.vh >> 2;
         auto el = [](uint32_t k) { return (k & (kRingQuads - 1u)) << 2; };
-        // the quads chunk 0 reads: [0, 1024 + qpp) within the box
+        // the quads chunk 0 reads: [0, 1024 + qpp) within the box (at most
+        // four per thread); a seeded ring already holds the first 2048
         const uint32_t pro = min((uint32_t)kBatchThreads + qpp, nquads);
-        if (!seeded) {
-            for (uint32_t g = threadIdx.x; g < pro; g += kBatchThreads) at<Raw>(ring, el(g)) = at<Raw>(other, g << 2);
+        const uint32_t from = seeded ? min(2u * (uint32_t)kBatchThreads, pro) : 0u;
+        if (from < pro) {
+            for (uint32_t g = from + threadIdx.x; g < pro; g += kBatchThreads)
+                at<Raw>(ring, el(g)) = at<Raw>(other, g << 2);
             __syncthreads();
         }
         const uint32_t t = threadIdx.x, r0 = t / nq;
@@ -127,9 +134,10 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
             z += dz + cy;
             __syncthreads();
         }
-        // the next half-sweep's first window: this colour's quads [0, pro),
-        // stored in the ring in the storage format, as in memory (the caller's
-        // barrier orders these writes before the next half-sweep's reads)
+        // the next half-sweep's first window: this colour's quads [0, pro)
+        // below 2048, stored in the ring in the storage format, as in memory
+        // (the caller's barrier orders these writes before the next
+        // half-sweep's reads)
         if (t < pro) St::st4(ring, el(t), keep0);
         if (t + (uint32_t)kBatchThreads < pro) St::st4(ring, el(t + (uint32_t)kBatchThreads), keep1);
     } else if ((lh & 3u) == 0) {

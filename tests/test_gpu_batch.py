@@ -68,10 +68,12 @@ def test_batch_matches_single_lattices(lat_mod):
 
 
 # chains past the single-workgroup size, so that the single lattices run the
-# quad kernel: at most 1024 quads per plane (the LDS ring path; 128 x 64 at
-# the ring's full span of 1024, 48 x 40 over eight chunks with a ragged last
-# one) and wider planes (136 x 64: 1088 quads, the two-quads-per-thread path)
-RING_EDGES = [(128, 64, 4), (136, 64, 3), (48, 40, 30), (32, 32, 32)]
+# quad kernel: at most 3072 quads per plane (the LDS ring path; 128 x 64 with
+# a first window of exactly the two kept chunks, 136 x 64 one past them,
+# 192 x 128 at the ring's full span of 3072, 48 x 40 over eight chunks with a
+# ragged last one) and wider planes (200 x 128: 3200 quads, the
+# two-quads-per-thread path)
+RING_EDGES = [(128, 64, 4), (136, 64, 3), (48, 40, 30), (32, 32, 32), (192, 128, 2), (200, 128, 2)]
 
 
 # 64^3 chains that bring a batch's fields to the 256 MiB at which the batch
@@ -88,9 +90,10 @@ def test_batch_ring_matches_quad_kernel(lat_mod, storage, filled):
     sides of the ring's plane limit."""
     print(f"[gpu] batch vs quad kernel {storage} filled={filled}", flush=True)
     seed = 777
-    ids = [3, 11, 0, 42]
+    ids = [3, 11, 0, 42, 7, 8]
     edges = RING_EDGES + (_fillers(storage) if filled else [])
-    b = lat_mod.Batch(edges, storage, seed=seed, chain_ids=ids + list(range(100, 100 + len(edges) - 4)))
+    b = lat_mod.Batch(edges, storage, seed=seed,
+                      chain_ids=ids + list(range(100, 100 + len(edges) - len(ids))))
     singles = []
     for k, e in enumerate(RING_EDGES):
         xyz, q = _charges(e, 8, 100 + k)
