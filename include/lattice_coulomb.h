@@ -312,7 +312,9 @@ int batch_set_charges(lattice_batch_t *b, int64_t chain, int64_t n, const int32_
  * bins of bin_size) for every chain, in one persistent launch.  Batches whose
  * fields fill the 256 MiB last-level cache sweep chains of at most 3072 quads
  * (4 compact sites) per plane through an LDS ring, each value loaded from
- * memory once per half-sweep; the chains' fields are the same either way. */
+ * memory once per half-sweep; chains of at most 8192 sites (lx / 8 * ly * lz
+ * quads <= 1024) keep their whole field in LDS in any batch.  The chains'
+ * fields are the same either way. */
 int batch_run(lattice_batch_t *b, int64_t n_therm, int64_t n_meas, int64_t bin_size);
 
 /* Estimate of one chain (as energy_estimate). */

@@ -58,7 +58,7 @@ __device__ __forceinline__ QuadNeighbours<St> quad_load_ring(const typename St::
 }
 
 // One half-sweep of colour c over a whole chain by one workgroup, in one of
-// three forms.  use_ring, lh % 4 == 0 and at most 3072 quads (4 compact sites
+// four forms.  use_ring, lh % 4 == 0 and at most 3072 quads (4 compact sites
 // of a row each) per plane: chunks of 1024 consecutive quads, one per thread, whose
 // neighbours are read from an LDS ring of the other colour (each quad loaded
 // from memory once per half-sweep); the load of the thread's quad of the next
@@ -72,6 +72,8 @@ __device__ __forceinline__ QuadNeighbours<St> quad_load_ring(const typename St::
 // last-level cache: 256 chains of 64^3 sweep 12% faster); a chain bound by
 // its CU's arithmetic runs 10% slower with it (the ring's address arithmetic
 // and a barrier per chunk), so the host asks for it only for such batches.
+// A chain of at most 1024 quads keeps its whole other colour in the ring in
+// any batch: one chunk, nothing loaded after the first half-sweep.
 // Otherwise, lh % 4 == 0: two quads per thread and
 // iteration read from memory, whose loads are all issued before either
 // update (a lane whose second quad lies past the end loads quad 0's centre,
@@ -87,7 +89,27 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
     T* own = field + (size_t)c * d.vh;
     const uint32_t lh = d.lh, ly = d.ly, lz = d.lz, plane = ly * lh;
     const float sixth = 1.0f / 6.0f;
-    if (use_ring && (lh & 3u) == 0 && (lh >> 2) * ly <= kRingMaxPlaneQuads) {
+    if ((lh & 3u) == 0 && d.vh <= 4u * kBatchThreads) {
+        // a chain of at most 1024 quads: the whole other colour is in the
+        // ring (after the first half-sweep of a launch: the threads' own
+        // results of the previous half-sweep), one quad per thread, no load
+        const uint32_t nq = lh >> 2, qpp = nq * ly, nquads = d.vh >> 2, t = threadIdx.x;
+        auto el = [](uint32_t k) { return (k & (kRingQuads - 1u)) << 2; };
+        if (!seeded) {
+            if (t < nquads) at<RawQuad<St>>(ring, el(t)) = at<RawQuad<St>>(other, t << 2);
+            __syncthreads();
+        }
+        if (t < nquads) {
+            const uint32_t r = t / nq, q = t - r * nq, y = r % ly, z = r / ly;
+            const uint32_t p = (c + y + z) & 1u;
+            const QuadNeighbours<St> nb = quad_load_ring<St>(ring, t, nq, qpp, y > 0, y + 1 < ly, z > 0, z + 1 < lz,
+                                                             p == 0 ? q > 0 : q + 1 < nq, p);
+            keep0 = quad_update_from<St>(nb, p, t << 2, h, d.chain_id, k0, k1);
+            St::st4(own, t << 2, keep0);
+        }
+        __syncthreads();  // every ring read done before the ring takes this colour
+        if (t < nquads) St::st4(ring, el(t), keep0);
+    } else if (use_ring && (lh & 3u) == 0 && (lh >> 2) * ly <= kRingMaxPlaneQuads) {
         using Raw = RawQuad<St>;
         const uint32_t nq = lh >> 2, qpp = nq * ly, nquads = d.vh >> 2;
         auto el = [](uint32_t k) { return (k & (kRingQuads - 1u)) << 2; };
