@@ -60,7 +60,11 @@ def parse():
                    choices=["auto", "tuned", "quad", "generic", "zslab", "stream", "fused", "resident"],
                    help="auto: the library's default kernel and tuning for the box; "
                         "tuned: the library's autotuner picks kernel, slab depth and tile")
-    p.add_argument("--bin-size", type=int, default=50)
+    p.add_argument("--bin-size", type=int, default=None,
+                   help="samples per bin of the headline estimate (default: a tenth of the samples, so that "
+                        "the binned error exists)")
+    p.add_argument("--therm", type=int, default=None,
+                   help="thermalisation sweeps before the warmup (default: the workload recipe's)")
     p.add_argument("--no-extras", action="store_true", help="skip the FP16 and batched comparisons")
     p.add_argument("--planes", type=int, default=None, help="slab kernels: planes per workgroup")
     p.add_argument("--tile", type=int, default=-1, help="slab kernels: tile configuration (-1: library default)")
@@ -503,17 +507,24 @@ def main():
     tuning = lat.tuning()  # what runs: library defaults or the autotuner's choice, resolved
     variant = tuning["variant"]
     lat.set_charges(cs.xyz, cs.q)
+    # the workload's thermalisation (untimed; the chain starts from phi = 0),
+    # enqueued right before the warmup: the GPU runs from the thermalisation
+    # into the timed steps without an idle gap (after one, its clocks take
+    # ~25 ms to settle and a short timed region would measure that)
+    therm = spec["therm"] if args.therm is None else args.therm
+    lat.thermalise(therm)
 
     # warmup: W measured sweeps (untimed).  Boxes of at most 2^24 sites run
     # their sweeps as replays of a captured hipGraph chunk (32 sweeps): the
     # warmup then covers two chunks, so that the one-off capture is not timed
     warmup = args.warmup if V > (1 << 24) else max(args.warmup, 64)
-    lat.sweep_and_measure(warmup, 1, args.bin_size)
+    bin_size = args.bin_size or max(1, (warmup + args.steps) // 10)
+    lat.sweep_and_measure(warmup, 1, bin_size)
     torch.cuda.synchronize()
 
     # timed: exactly K steps
     t0 = time.perf_counter()
-    lat.sweep_and_measure(args.steps, 1, args.bin_size)
+    lat.sweep_and_measure(args.steps, 1, bin_size)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -543,7 +554,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": list(cs.shape), "charges": cs.n,
                    "storage": args.storage, "variant": variant, "tuning": tuning,
-                   "measure_every": 1, "bin_size": args.bin_size, "philox_seed": seed},
+                   "measure_every": 1, "bin_size": bin_size, "thermalisation": therm,
+                   "philox_seed": seed},
         "hbm_gbps": achieved,
         "sweep_ms": sweep_ms,
         "measure_ms": measure_ms,
@@ -564,7 +576,7 @@ def main():
             out["copy_same_bytes"] = copy_reference(bytes_per_launch // 2, torch)
             out["copy_same_bytes"]["kernel_vs_copy"] = out["copy_same_bytes"]["ms"] / launch_ms
             if args.storage == "fp32":
-                f16 = fp16_comparison(cs, seed, min(args.steps, 200), args.bin_size, torch, lattice,
+                f16 = fp16_comparison(cs, seed, min(args.steps, 200), bin_size, torch, lattice,
                                       args.variant == "tuned")
                 f16["speedup_vs_fp32"] = ms_per_step / f16["ms_per_step"]
                 out["fp16_storage"] = f16
@@ -574,11 +586,11 @@ def main():
             out["precision_coupled"] = precision_coupled(args.coupled_sweeps, torch, lattice, workloads)
             out["figures_128"] = figures_comparison(args.figures_sweeps)
             if args.storage == "fp32":
-                sets = charge_sets_comparison(cs, spec, workloads, min(args.steps, 200), args.bin_size, torch,
+                sets = charge_sets_comparison(cs, spec, workloads, min(args.steps, 200), bin_size, torch,
                                               lattice)
                 sets["set_samples_vs_one_set"] = sets["set_samples_per_s"] / (1e3 / ms_per_step)
                 out["charge_sets"] = sets
-                off = offlattice_comparison(cs, spec, min(args.steps, 200), args.bin_size, torch, lattice)
+                off = offlattice_comparison(cs, spec, min(args.steps, 200), bin_size, torch, lattice)
                 off["cost_vs_on_lattice"] = off["ms_per_step"] / ms_per_step
                 out["offlattice_forces"] = off
         except Exception as exc:  # comparisons must not hide the headline line

@@ -274,6 +274,15 @@ int lattice_get_field(lattice_t *lat, float *host_out);
  * format.  Errors: LAT_ERR_ARG for non-finite values. */
 int lattice_set_field(lattice_t *lat, const float *host_in);
 
+/* The heat-bath noise of the device for the grid points k = k_first ..
+ * k_first + n - 1 of the uniform r = (k + 1/2) 2^-24: dev_out (device memory
+ * of n floats, the caller's) receives erfinv(2r - 1)/sqrt(3) as every sweep
+ * kernel computes it (the Gaussian term of Eq. phi).  Enqueued on hip_stream
+ * (NULL = null stream), not synchronised.  Errors: LAT_ERR_ARG unless
+ * 0 <= k_first and k_first + n <= 2^24, or for a NULL dev_out with n > 0.
+ * Paper: Eq. (hb1) inverted as Eq. (phi). */
+int lattice_noise_values(int64_t k_first, int64_t n, float *dev_out, void *hip_stream);
+
 /* The (X, Y) of the most recent sample (charge set 0). */
 int lattice_last_measure(lattice_t *lat, double *X, double *Y);
 

@@ -27,7 +27,7 @@ import os
 import numpy as np
 
 __all__ = ["OracleChain", "load", "philox4x32_10", "inv_norm_cdf", "round_storage",
-           "site_uniform", "estimate", "gather_offlattice", "force_sample", "STORAGE"]
+           "site_uniform", "noise_grid", "estimate", "gather_offlattice", "force_sample", "STORAGE"]
 
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
 
@@ -62,6 +62,8 @@ def load() -> ctypes.CDLL:
     lib.orc_round_storage.restype = _d
     lib.orc_site_uniform.argtypes = [_i64, _i64, _i64, _i64, _i64, _u64, _u32, _u32]
     lib.orc_site_uniform.restype = _d
+    lib.orc_site_value.argtypes = [_p, _i64, _i64, _i64, _i64, _i64, _i64, _u64, _u32, _u32]
+    lib.orc_site_value.restype = _d
     lib.orc_halfsweep.argtypes = [_p, _i64, _i64, _i64, ctypes.c_int, _u64, _u32, _u32]
     lib.orc_halfsweep.restype = None
     lib.orc_gather.argtypes = [_p, _i64, _i64, _i64, _i64, _p, _p, _p]
@@ -73,6 +75,8 @@ def load() -> ctypes.CDLL:
     lib.orc_run.restype = _i64
     lib.orc_site_values_f32.argtypes = [_p, _i64, _i64, _i64, _i64, _p, _u64, _u32, _u32, _p]
     lib.orc_site_values_f32.restype = None
+    lib.orc_noise_grid.argtypes = [_i64, _i64, _p]
+    lib.orc_noise_grid.restype = None
     lib.orc_max_threads.argtypes = []
     lib.orc_max_threads.restype = ctypes.c_int
     lib.orc_set_threads.argtypes = [ctypes.c_int]
@@ -203,6 +207,14 @@ def site_values_f32(phi32: np.ndarray, sites: np.ndarray, seed: int, chain: int,
     out = np.zeros(s.shape[0], dtype=np.float64)
     load().orc_site_values_f32(_ptr(f), lx, ly, lz, s.shape[0], _ptr(s), int(seed), int(chain),
                                int(h), _ptr(out))
+    return out
+
+
+def noise_grid(k_first: int, n: int) -> np.ndarray:
+    """Heat-bath noise Phi^{-1}(r)/sqrt(6) (FP64) at the grid points
+    k_first .. k_first + n - 1 of r = (k + 1/2) 2^-24."""
+    out = np.zeros(int(n), dtype=np.float64)
+    load().orc_noise_grid(int(k_first), int(n), _ptr(out))
     return out
 
 

@@ -296,6 +296,16 @@ void orc_site_values_f32(const float *phi, int64_t lx, int64_t ly, int64_t lz, i
     }
 }
 
+/*
+ * The heat-bath noise Phi^{-1}(r)/sqrt(6) of Eq. (phi) at the grid points
+ * k = k_first .. k_first + n - 1 of the uniform r = (k + 1/2) 2^-24.
+ */
+void orc_noise_grid(int64_t k_first, int64_t n, double *out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = orc_inv_norm_cdf(((double)(k_first + i) + 0.5) * 0x1p-24) / sqrt(6.0);
+}
+
 int orc_max_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

@@ -600,7 +600,11 @@ int lattice_set_charge_sets(lattice_t* L, int64_t n_sets, const int64_t* counts,
         e = hipMemsetAsync(L->d_bins, 0, sizeof(double) * 2 * (size_t)L->bin_cap * L->n_sets, L->stream);
         if (e != hipSuccess) return hip_fail(e, "bin reset");
     }
-    return LAT_OK;
+    // the fused gather's per-tile lists for the current tiling, built here
+    // where the host waits anyway, so that later calls only enqueue (the
+    // GPU then runs thermalisation and measured sweeps back to back); a
+    // later change of kernel or tiling rebuilds them at the next measured call
+    return fused_gather_prepare(L);
 }
 
 int set_charges(lattice_t* L, int64_t n, const int32_t* xyz, const double* q) {

@@ -86,6 +86,7 @@ def load_library() -> ctypes.CDLL:
         "lattice_get_field": (_int, [_p, _p]),
         "lattice_set_field": (_int, [_p, _p]),
         "lattice_last_measure": (_int, [_p, _pd, _pd]),
+        "lattice_noise_values": (_int, [_i64, _i64, _p, _p]),
         "lattice_get_state": (_int, [_p, _pi64, _pi64, _p, _i64, _pi64]),
         "lattice_set_state": (_int, [_p, _i64, _i64, _i64, _p, _i64]),
         "batch_create": (_int, [_i64, _p, _p, _int, _u64, _p, _p, _p]),
@@ -149,6 +150,20 @@ def _device_and_stream(device, stream):
     if stream is None:
         stream = torch.cuda.current_stream(dev)
     return dev, stream
+
+
+def noise_values(k_first: int, n: int, device=None):
+    """The device's heat-bath noise erfinv(2r - 1)/sqrt(3) at the grid points
+    k_first .. k_first + n - 1 of r = (k + 1/2) 2^-24 (test hook): a float32
+    numpy array of n values."""
+    import torch
+
+    load_library()
+    dev, stream = _device_and_stream(device, None)
+    out = torch.empty(int(n), dtype=torch.float32, device=dev)
+    _check(_lib.lattice_noise_values(int(k_first), int(n), ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(stream.cuda_stream)))
+    return out.cpu().numpy()
 
 
 class Lattice:

@@ -182,3 +182,59 @@ def test_batched_workload_estimates(lat_mod):
     s.sweep_and_measure(200, 1, 20)
     assert np.abs(b.get_field(0) - s.get_field()).max() <= 1e-6 * np.abs(s.get_field()).max()
     assert abs(ests[0][0] - s.energy_estimate()[0]) <= 1e-6 * max(1.0, abs(ests[0][0]))
+
+
+def test_batched_workload_edges_vs_oracle(lat_mod):
+    """The 512-chain workload in one launch: the first chain of each edge
+    (24, 32, 40, 48, 64) against the oracle chain with the same seed and
+    chain id, sweep for sweep (fields within 1e-5 of max |phi|) and sample
+    for sample (O within the field tolerance propagated to the sample)."""
+    print("[gpu] batched workload edges vs oracle", flush=True)
+    chains = workloads.batched_chains(seed=0)
+    b = lat_mod.Batch([c.shape for c in chains], "fp32", seed=0)
+    for k, c in enumerate(chains):
+        b.set_charges(k, c.xyz, c.q)
+    b.run(3, 2, 1)
+    picks = {}
+    for k, c in enumerate(chains):
+        picks.setdefault(c.shape[0], k)
+    assert sorted(picks) == [24, 32, 40, 48, 64]
+    for L, k in sorted(picks.items()):
+        c = chains[k]
+        ref = oracle.OracleChain(c.shape, seed=0, chain=k)
+        ref.set_charges(c.xyz, c.q)
+        ref.sweeps(3)
+        s = ref.sweeps(2, 1)
+        phi = b.get_field(k).astype(np.float64)
+        pmax = np.abs(ref.phi).max()
+        assert np.abs(phi - ref.phi).max() <= 1e-5 * pmax, L
+        m, se, M, nb = b.energy_estimate(k)
+        assert M == 2 and nb == 2
+        d = 1e-5 * pmax
+        dX = d * np.sum(np.abs(c.q))
+        dO = 2 * np.abs(s[:, 0]).max() * dX + dX ** 2 + np.sum(c.q ** 2) * (2 * pmax * d + d * d)
+        assert abs(m - s[:, 2].mean()) <= dO, (L, m, s[:, 2].mean(), dO)
+
+
+def test_sharp_energy_batched_16(lat_mod):
+    """Unbiasedness of Eq. (nsum2) at a sharp error: 256 independent chains
+    of the 16^3 workload (8 charges of +-1, chain ids 1..256) in one batched
+    launch, 1e3 thermalisation + 1.5e5 measured sweeps each.  The pooled mean
+    (spread of the chains' means over sqrt(256)) lies within 3 sigma of the
+    exact lattice energy (dense Cholesky of the 4096 x 4096 Laplacian), and
+    sigma is below 2% of |E|."""
+    print("[gpu] sharp energy, 256 batched 16^3 chains", flush=True)
+    from oracle import exact as ex
+
+    c = workloads.small_neutral(seed=0)
+    e_exact = ex.energy_dense(c.shape, c.xyz, c.q)
+    n = 256
+    b = lat_mod.Batch([c.shape] * n, "fp32", seed=0, chain_ids=list(range(1, n + 1)))
+    for k in range(n):
+        b.set_charges(k, c.xyz, c.q)
+    b.run(1000, 150000, 1000)
+    means = np.array([b.energy_estimate(k)[0] for k in range(n)])
+    mean, sigma = means.mean(), means.std(ddof=1) / np.sqrt(n)
+    print(f"[gpu] pooled {mean:.6f} +- {sigma:.6f}, exact {e_exact:.6f}", flush=True)
+    assert sigma < 0.02 * abs(e_exact), (sigma, e_exact)
+    assert abs(mean - e_exact) < 3 * sigma, (mean, sigma, e_exact)

@@ -211,7 +211,22 @@ def test_fused_gather_full_size(lat_mod):
     assert a.sample_path() == "fused"
     sa = a.get_state()
     Xa, Ya = a.last_measure()
+    # the oracle's gather of the read-back field (values at the charges'
+    # sites passed as a one-row lattice): recursive FP64 sums of n terms
+    # differ from any other order by at most (n - 1) 2^-53 sum |terms|, and
+    # the per-term products (q phi, (q phi)^2 against S phi^2) by a few ulps
+    phi = a.get_field()
     a.close()
+    v = np.ascontiguousarray(phi[xyz[:, 2], xyz[:, 1], xyz[:, 0]], dtype=np.float64)
+    del phi
+    n = v.shape[0]
+    line = oracle.OracleChain((n, 1, 1), seed=0)
+    line.phi = v.reshape(1, 1, n)
+    line.set_charges(np.stack([np.arange(n), np.zeros(n), np.zeros(n)], axis=1), q)
+    Xo, Yo = line.gather()
+    tol = (n + 4) * 2.0 ** -53
+    assert abs(Xa - Xo) <= tol * np.sum(np.abs(q * v)), (Xa, Xo)
+    assert abs(Ya - Yo) <= tol * Yo, (Ya, Yo)
     b = lat_mod.Lattice(shape, seed=77)
     b.set_variant("zslab")
     b.set_charges(xyz, q)

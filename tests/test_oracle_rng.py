@@ -99,6 +99,19 @@ def test_inverse_cdf_matches_scipy_on_grid(orc):
     np.testing.assert_array_equal(sym, -got[:500])
 
 
+def test_noise_grid_matches_scipy_everywhere(orc):
+    """The heat-bath noise Phi^{-1}(r)/sqrt(6) at every one of the 2^24 grid
+    points (the reference the device transform is checked against), against
+    scipy's ndtri over sqrt(6); odd about the grid's centre."""
+    z = orc.noise_grid(0, 1 << 24)
+    r = (np.arange(1 << 24) + 0.5) * 2.0**-24
+    ref = scipy.special.ndtri(r) / np.sqrt(6.0)
+    assert np.max(np.abs(z - ref) / np.abs(ref)) <= 4e-15
+    np.testing.assert_array_equal(z[::-1], -z)
+    part = orc.noise_grid(12345, 100)
+    np.testing.assert_array_equal(part, z[12345:12445])
+
+
 def test_grid_extremes(orc):
     """Largest |z| on the grid is Phi^{-1}(2^-25) = -5.41998..., and the
     grid has no r = 0 or 1 (no infinities)."""
