@@ -182,6 +182,25 @@ int sweep_and_measure(lattice_t *lat, int64_t n_sweeps, int64_t measure_every,
 int energy_estimate(lattice_t *lat, double *mean, double *stderr_binned, int64_t *n_samples,
                     int64_t *n_bins);
 
+/* sweep_and_measure for callers that cannot allocate device memory: code
+ * under HIP stream capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, same samples and field as sweep_and_measure
+ * (bit for bit; sample sums up to FP64 summation order); no hipMalloc,
+ * hipFree, allocator callback or graph capture happens in the call.  The
+ * partial sums of the sample gather live in a static device array of 1 MiB
+ * per GPU (held until the process ends) instead of the lattice's buffers;
+ * sweeps are launched one by one.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (several host threads, or several
+ * streams) race on it.
+ * Needs: charges placed; bins with room for every sample of the call (bins
+ * grow only in sweep_and_measure, to at least 64 bins, doubling); the sample
+ * lists of the current tiling built (set_charges builds them; a change of
+ * kernel or tiling needs a sweep_and_measure to rebuild them).
+ * Errors: as sweep_and_measure; LAT_ERR_STATE when one of the needs is not
+ * met; LAT_ERR_ARG when this lattice's partial sums exceed the 1 MiB array. */
+int sweep_and_measure_noalloc(lattice_t *lat, int64_t n_sweeps, int64_t measure_every,
+                              int64_t bin_size);
+
 /* The estimate of charge set `set` (as energy_estimate; energy_estimate is
  * set 0).  LAT_ERR_ARG for a set that does not exist. */
 int lattice_energy_estimate_set(lattice_t *lat, int64_t set, double *mean, double *stderr_binned,

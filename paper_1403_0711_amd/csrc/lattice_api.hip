@@ -256,10 +256,11 @@ static int graph_capture(lattice* L, lattice::SweepGraph& g, int64_t K, int64_t 
 }
 
 // n sweeps with a sample after every `every`-th (every = 0: no samples):
-// whole chunks as graph replays where that pays, the rest launch by launch.
-static int run_sweeps(lattice* L, int64_t n, int64_t every) {
+// whole chunks as graph replays where that pays (not when eager), the rest
+// launch by launch.
+int run_sweeps(lattice* L, int64_t n, int64_t every, bool eager) {
     int64_t done = 0;
-    const int64_t K = graph_chunk(L, every);
+    const int64_t K = eager ? 0 : graph_chunk(L, every);
     if (K > 0 && n >= K) {
         lattice::SweepGraph& g = every > 0 ? L->g_meas : L->g_therm;
         if (!graph_matches(L, g, K, every))
@@ -297,7 +298,7 @@ static int run_sweeps(lattice* L, int64_t n, int64_t every) {
 
 // Bin arrays of every charge set, each with room for n_bins_needed bins
 // (grown geometrically; each set's bins keep their place in its array).
-static int ensure_bins(lattice* L, int64_t n_bins_needed) {
+int ensure_bins(lattice* L, int64_t n_bins_needed) {
     if (n_bins_needed <= L->bin_cap) return LAT_OK;
     int64_t cap = std::max<int64_t>({n_bins_needed, 2 * L->bin_cap, 64});
     const size_t pitch = sizeof(double) * 2 * (size_t)cap;
@@ -346,6 +347,10 @@ int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t see
     L->chain = chain_id;
     L->mem = DeviceAllocator(alloc);
     L->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipError_t e = hipGetDevice(&L->device)) {
+        delete L;
+        return hip_fail(e, "current device");
+    }
     const size_t fbytes = round_up(2 * (size_t)L->vh * L->esz, 256);
     L->field = L->mem.alloc(fbytes);
     L->d_misc = L->mem.alloc(256);

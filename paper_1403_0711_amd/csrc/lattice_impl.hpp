@@ -45,6 +45,7 @@ struct lattice {
     uint64_t seed = 0;
     uint32_t chain = 0;
     DeviceAllocator mem;
+    int device = 0;  // the device current at creation (the field's)
     hipStream_t stream = nullptr;
     void* field = nullptr;  // colour 0 then colour 1
     // second colour-1 array for the fused sweep, which reads colour 1 from one
@@ -217,5 +218,11 @@ int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint3
                      const lattice::FusedStep* fs = nullptr);
 int enqueue_sweep(lattice* L, const lattice::FusedStep* fs = nullptr);
 int enqueue_resident(lattice* L, int64_t n_therm, int64_t n_meas, int64_t every);
+// n sweeps with a sample after every `every`-th (0: none); eager: launch by
+// launch only, never capturing a graph (a capture creates a stream and
+// instantiates a graph, which allocate)
+int run_sweeps(lattice* L, int64_t n, int64_t every, bool eager = false);
+// sample bins with room for n_bins_needed bins per charge set (grown)
+int ensure_bins(lattice* L, int64_t n_bins_needed);
 
 }  // namespace latcoul

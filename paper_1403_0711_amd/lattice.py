@@ -68,6 +68,7 @@ def load_library() -> ctypes.CDLL:
         "set_charges": (_int, [_p, _i64, _p, _p]),
         "thermalise": (_int, [_p, _i64]),
         "sweep_and_measure": (_int, [_p, _i64, _i64, _i64]),
+        "sweep_and_measure_noalloc": (_int, [_p, _i64, _i64, _i64]),
         "energy_estimate": (_int, [_p, _pd, _pd, _pi64, _pi64]),
         "lattice_set_charge_sets": (_int, [_p, _i64, _p, _p, _p]),
         "lattice_energy_estimate_set": (_int, [_p, _i64, _pd, _pd, _pi64, _pi64]),
@@ -124,7 +125,10 @@ class _TorchMemory:
         self.device = device
         self.stream = stream
 
+        self.n_alloc = 0  # allocator calls made through this handle's callbacks
+
         def _alloc(ctx, nbytes):
+            self.n_alloc += 1
             try:
                 return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
             except Exception:  # out of memory -> NULL -> LAT_ERR_ALLOC
@@ -269,6 +273,10 @@ class Lattice:
 
     def sweep_and_measure(self, n_sweeps: int, measure_every: int = 1, bin_size: int = 100):
         self._call(self.lib.sweep_and_measure, int(n_sweeps), int(measure_every), int(bin_size))
+
+    def sweep_and_measure_noalloc(self, n_sweeps: int, measure_every: int = 1, bin_size: int = 100):
+        """As ``sweep_and_measure``, allocating nothing (bins must have room)."""
+        self._call(self.lib.sweep_and_measure_noalloc, int(n_sweeps), int(measure_every), int(bin_size))
 
     def energy_estimate(self, allow_few_bins: bool = False, charge_set: int = 0):
         """Returns ``(mean, stderr, n_samples, n_bins)`` of one charge set."""
