@@ -43,6 +43,17 @@ if ROOT not in sys.path:
 
 METRIC = "site updates/s + HBM GB/s; time to E_N at 1% stat error vs plain FP32 sweep"
 HBM_PEAK_GBPS = 8000.0
+# Vector ALU peak: 256 CUs x 128 lanes per clock x 2.4 GHz = 78.6e12 lane
+# slots/s at the FP32 FMA rate (157.3 TFLOP/s at 2 flops per FMA).  Measured
+# on gfx950, 32-bit integer ops (multiply, three-input xor, convert) issue at
+# half that rate and v_log_f32 at a quarter, so they count 2 and 4 slots.
+ALU_PEAK_TSLOTS = 256 * 128 * 2.4e9 / 1e12
+# Algorithmic slots per site update: the stencil sum and update (5 adds + 1
+# FMA = 6), the inverse-CDF noise (grid value: 2 integer ops = 4, scale and
+# 1 - s^2: 2, log: 4, w and the degree-8 polynomial: 9, times s: 1 = 20)
+# and a quarter of a Philox4x32-10 call (10 rounds x (2 multiplies + 2
+# three-input xors) / 4 = 10 integer ops = 20).
+ALU_SLOTS_PER_SITE = 6 + 20 + 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 EXACT_FILE = os.path.join(ROOT, "tests", "golden", "exact_energies.json")
 
@@ -57,7 +68,7 @@ def parse():
                             "small_neutral_16"])
     p.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
     p.add_argument("--variant", default="auto",
-                   choices=["auto", "tuned", "quad", "generic", "zslab", "stream", "fused", "resident"],
+                   choices=["auto", "tuned", "quad", "generic", "zslab", "stream", "fused", "resident", "blocked"],
                    help="auto: the library's default kernel and tuning for the box; "
                         "tuned: the library's autotuner picks kernel, slab depth and tile")
     p.add_argument("--bin-size", type=int, default=None,
@@ -87,7 +98,8 @@ def parse():
 # are unchanged (host-side launch structs are not part of a kernel's code).
 _COMMON_SOURCES = ["device_common.hpp", "erfinv_coeffs.h"]
 KERNEL_SOURCES = {
-    "halfsweep_stream": ["stream_sweep.hip"],
+    "sweep_blocked": ["blocked_sweep.hip", "lds_pipe.hpp"],
+    "halfsweep_stream": ["stream_sweep.hip", "lds_pipe.hpp"],
     "halfsweep_zslab": ["sweep_kernels.hip"],
     "halfsweep_quad": ["sweep_kernels.hip"],
     "halfsweep_generic": ["sweep_kernels.hip"],
@@ -116,10 +128,9 @@ def sources_hash(kname: str) -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kname: str, key: str):
-    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE and
-    WRITE_SIZE, scaled by a copy kernel of known size), if taken on the
-    kernel's current sources."""
+def stored_entry(kname: str, key: str):
+    """The stored rocprofv3 --pmc record of a kernel configuration, if taken
+    on the kernel's current sources."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
@@ -128,7 +139,33 @@ def stored_traffic(kname: str, key: str):
     e = d.get(key)
     if not e or e.get("sources_hash") != sources_hash(kname):
         return None
-    return e.get("bytes_per_launch")
+    return e
+
+
+def stored_traffic(kname: str, key: str):
+    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE and
+    WRITE_SIZE, scaled by a copy kernel of known size), if taken on the
+    kernel's current sources."""
+    e = stored_entry(kname, key)
+    return e.get("bytes_per_launch") if e else None
+
+
+def roofline(kname: str, V: int, launch_ms: float, gbps: float, bytes_per_launch: int, traffic, stored):
+    """The dominant kernel against its ceiling.  The blocked sweep moves 4 B
+    per FP32 site update (half the plain sweep's): it is bound by the vector
+    ALU, reported in algorithmic slots per second with its HBM rate beside
+    it; the other kernels are bound by HBM."""
+    hbm = {"achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+           "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms, "traffic": traffic}
+    if kname != "sweep_blocked":
+        return {"bound": "hbm", "kernel": kname, **hbm}
+    slots = ALU_SLOTS_PER_SITE * V / (launch_ms * 1e-3) / 1e12
+    out = {"bound": "alu", "kernel": kname, "achieved": slots, "peak": ALU_PEAK_TSLOTS, "unit": "Tslot/s",
+           "frac": slots / ALU_PEAK_TSLOTS, "slots_per_site_update": ALU_SLOTS_PER_SITE,
+           "site_updates_per_launch": V, "launch_ms": launch_ms, "traffic": traffic, "hbm": hbm}
+    if stored and "valu" in stored:
+        out["valu_counters"] = stored["valu"]
+    return out
 
 
 def exact_energy(workload: str):
@@ -164,6 +201,8 @@ def kernel_roofline(lat, stream, V: int, esz: int, variant: str, reps: int, torc
     sweep_ms = ev0.elapsed_time(ev1) / reps
     if variant == "fused":
         return sweep_ms, sweep_ms, 3 * (V // 2) * esz, "fused_sweep"  # read colour 1, write both colours
+    if variant == "blocked":  # read colour 1, write colour 1 (colour 0 stays on chip)
+        return sweep_ms, sweep_ms, 2 * (V // 2) * esz, "sweep_blocked"
     if variant == "resident":
         return sweep_ms, sweep_ms, 2 * (V // 2) * 2 * esz, "resident_chain"
     return sweep_ms, sweep_ms / 2.0, (V // 2) * 2 * esz, f"halfsweep_{variant}"  # read other colour, write own
@@ -563,10 +602,8 @@ def main():
         "estimate": {"mean": m, "stderr": se if math.isfinite(se) else None, "bins": nb,
                      "E_exact": e_exact},
         "time_to_1pct": time_to_1pct(ms_per_step * 1e-3 * M, se, e_exact),
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms,
-                     "traffic": traffic},
+        "roofline": roofline(kname, V, launch_ms, achieved, bytes_per_launch, traffic,
+                             stored_entry(kname, kernel_key(kname, tuning, args.workload, args.storage))),
     }
     lat.close()
     del lat

@@ -86,8 +86,11 @@ enum {
     LAT_SWEEP_ZSLAB = 3,   /* z-marching slabs, plane staged in LDS (lx % 8 == 0)   */
     LAT_SWEEP_FUSED = 4,   /* both half-sweeps in one pass (lx % 8 == 0)             */
     LAT_SWEEP_RESIDENT = 5, /* small boxes: one workgroup runs every sweep of a call in one launch */
-    LAT_SWEEP_STREAM = 6    /* z-marching slabs fed by a producer wave through an LDS ring
+    LAT_SWEEP_STREAM = 6,   /* z-marching slabs fed by a producer wave through an LDS ring
                                (lx % 8 == 0, each colour array below 2 GiB)         */
+    LAT_SWEEP_BLOCKED = 7   /* both half-sweeps per pass over memory, colour 0 kept in LDS:
+                               full-row tiles walking z-slabs (lx % 8 == 0; 16-bit storage
+                               lx % 16 == 0; rows of at most ~2300 sites at FP32) */
 };
 
 /* ------------------------------------------------------------------ */
@@ -249,15 +252,26 @@ int lattice_set_tuning(lattice_t *lat, int64_t planes, int tile, int xcd_order);
 int lattice_get_tuning(const lattice_t *lat, int *variant, int64_t *planes, int *tile, int *xcd_order);
 
 /* How the samples of the most recent sweep_and_measure were gathered:
- * *fused = 1 if the streaming sweep kernel summed X and Y of each sample
- * from its LDS plane ring (the charged colour-0 sites while it updated
- * colour 1 of the measured sweep, the colour-1 sites while it updated colour
- * 0 of the next sweep), which needs one on-lattice charge set,
- * LAT_SWEEP_STREAM and a per-tile charge list short enough to stage in LDS
- * without lowering the kernel's occupancy; 0 if a separate gather kernel
- * read the field after each measured sweep.  The two give the same samples
- * up to the order of the FP64 partial sums. */
+ * *fused = 1 if the sweep kernel summed X and Y of each sample from its LDS
+ * rings: the streaming sweep (LAT_SWEEP_STREAM) the charged colour-0 sites
+ * while it updated colour 1 of the measured sweep and the colour-1 sites
+ * while it updated colour 0 of the next sweep; the blocked sweep
+ * (LAT_SWEEP_BLOCKED) the colour-0 sites in the measured sweep's launch and
+ * the colour-1 sites in the next launch.  This needs one on-lattice charge
+ * set and per-tile charge lists that can be staged in LDS (streaming: short
+ * enough not to lower the kernel's occupancy; blocked: in at most 8 parts);
+ * *fused = 0 if a separate gather kernel read the field after each measured
+ * sweep.  The two give the same samples up to the order of the FP64 partial
+ * sums. */
 int lattice_get_sample_path(const lattice_t *lat, int *fused);
+
+/* Staging of the blocked sweep's fused gather: each tile's charge lists are
+ * staged into LDS in *parts parts of at most *part_entries entries each (the
+ * fewest parts that leave room for the deepest plane ring; the environment
+ * variable LATCOUL_GATHER_PART_CAP, read when the lists are built, bounds
+ * the entries of a part further).  Both 0 when the current kernel does not
+ * gather inside the blocked sweep.  Either pointer may be NULL. */
+int lattice_get_gather_parts(const lattice_t *lat, int *parts, int *part_entries);
 
 /* Graph capture of the multi-launch sweep path: runs of sweeps (with their
  * samples) are recorded once as a hipGraph of K-sweep chunks whose kernels

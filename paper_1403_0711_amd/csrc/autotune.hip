@@ -31,6 +31,11 @@ static bool choice_valid(const lattice* L, const TuneChoice& c, bool resident_ok
         case LAT_SWEEP_ZSLAB: return L->lh % 4 == 0 && c.tile < (uint32_t)kZslabTiles;
         case LAT_SWEEP_STREAM: return L->lh % 4 == 0 && stream_tile_geometry(c.tile, L->esz, &sh);
         case LAT_SWEEP_FUSED: return L->lh % 4 == 0 && fused_sweep_supported(L->lh, (uint32_t)L->ly);
+        case LAT_SWEEP_BLOCKED: {
+            BlockedShape bs;
+            return L->lh % 4 == 0 && c.slab >= 1 && (size_t)L->vh * L->esz < ((size_t)1 << 31) &&
+                   blocked_geometry(L->lh, (uint32_t)L->esz, c.tile, 4u, &bs);
+        }
         default: return false;
     }
 }
@@ -84,7 +89,7 @@ static std::vector<TuneChoice> tune_candidates(const lattice* L) {
         d.tile = kTileDefault;
         d.xcd_order = -1;
         const int v = d.effective_variant();
-        if (v == LAT_SWEEP_STREAM || v == LAT_SWEEP_ZSLAB)
+        if (v == LAT_SWEEP_STREAM || v == LAT_SWEEP_ZSLAB || v == LAT_SWEEP_BLOCKED)
             c.push_back({v, d.resolved_slab(v), d.resolved_tile(v), d.resolved_xcd(v), 0});
     }
     c.push_back({LAT_SWEEP_QUAD, 0, 0, 1, 0});
@@ -102,6 +107,20 @@ static std::vector<TuneChoice> tune_candidates(const lattice* L) {
     if (fused_sweep_supported(L->lh, (uint32_t)L->ly))
         for (uint32_t slab : {16u, 32u})
             if (slab <= L->lz) c.push_back({LAT_SWEEP_FUSED, slab, 0, 1, 0});
+    // the blocked sweep: the library's rows per tile and one fewer, over a
+    // range of slab depths
+    if (slab_ok) {
+        lattice d = *L;
+        d.slab = 0;
+        d.tile = kTileDefault;
+        const uint32_t rows = d.blocked_choice().first;
+        for (uint32_t k : {rows, rows - 1u}) {
+            BlockedShape bs;
+            if (k == 0 || !blocked_geometry(L->lh, (uint32_t)L->esz, k, 4u, &bs)) continue;
+            for (uint32_t slab : {32u, 48u, 64u, 96u, 128u})
+                if (slab <= L->lz) c.push_back({LAT_SWEEP_BLOCKED, slab, k, 2, 0});
+        }
+    }
     return c;
 }
 
@@ -136,6 +155,11 @@ static int autotune(lattice* L, int64_t reps, TuneChoice* out) {
     const std::vector<TuneChoice> cands = tune_candidates(L);
     if (fused_sweep_supported(L->lh, (uint32_t)L->ly))
         if (hipError_t e = prepare_fused_sweep()) return hip_fail(e, "fused sweep set-up");
+    for (const TuneChoice& ch : cands)
+        if (ch.variant == LAT_SWEEP_BLOCKED) {
+            if (hipError_t e = prepare_blocked_sweep()) return hip_fail(e, "blocked sweep set-up");
+            break;
+        }
     const size_t fbytes = round_up(2 * (size_t)L->vh * L->esz, 256);
     void* scratch = L->mem.alloc(fbytes);
     void* scratch_alt = L->mem.alloc(round_up((size_t)L->vh * L->esz, 256));
@@ -201,8 +225,8 @@ int lattice_autotune(lattice_t* L, int64_t reps, int* variant, int64_t* planes, 
     if (reps < 1 || reps > 1000) return set_error(LAT_ERR_ARG, "reps must be in [1, 1000]");
     TuneChoice ch;
     if (int r = autotune(L, reps, &ch)) return r;
-    if (ch.variant == LAT_SWEEP_FUSED)
-        if (int r = lattice_set_variant(L, LAT_SWEEP_FUSED)) return r;  // allocates the second colour-1 array
+    if (ch.variant == LAT_SWEEP_FUSED || ch.variant == LAT_SWEEP_BLOCKED)
+        if (int r = lattice_set_variant(L, ch.variant)) return r;  // allocates the second colour-1 array
     apply_choice(L, ch);
     graphs_reset(L);
     if (variant) *variant = ch.variant;

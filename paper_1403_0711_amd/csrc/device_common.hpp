@@ -32,6 +32,10 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
+    // the round keys are formed here by scalar adds: without this the
+    // compiler keeps all twenty of them in scalar registers for the whole
+    // kernel, which pushes other wave-uniform values out to vector lanes
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         // one 32x32->64 product per word: lowers to a single v_mad_u64_u32
@@ -66,21 +70,25 @@ __device__ __forceinline__ float grid_s(uint32_t u) {
     return (float)(int)v * 0x1p-31f;
 }
 
+// The central polynomial is evaluated in every lane (its value at a tail
+// lane's w is finite and discarded); the tail polynomial only in waves where
+// some lane needs it, which is one wave branch instead of an if/else that
+// splits the wave's lanes (the same arithmetic, so the same bits).
 __device__ __forceinline__ float heatbath_noise(uint32_t u) {
     const float s = grid_s(u);
     const float omx2 = fmaf(-s, s, 1.0f);  // 1 - s^2, one rounding
     // v_log_f32 is log2: w - 2.5 = -ln(1 - s^2) - 2.5 in one fma
     const float wm = fmaf(__builtin_amdgcn_logf(omx2), -0.69314718055994531f, -2.5f);
-    float p;
-    if (wm < LATCOUL_ERFINV_W_SPLIT - 2.5f) {
-        p = kErfinvP[8];
+    float p = kErfinvP[8];
 #pragma unroll
-        for (int i = 7; i >= 0; --i) p = fmaf(p, wm, kErfinvP[i]);
-    } else {
+    for (int i = 7; i >= 0; --i) p = fmaf(p, wm, kErfinvP[i]);
+    const bool tail = !(wm < LATCOUL_ERFINV_W_SPLIT - 2.5f);
+    if (__builtin_amdgcn_ballot_w64(tail) != 0) {  // wave-uniform: about one wave in five
         const float x = __builtin_amdgcn_sqrtf(wm + 2.5f) - 3.0f;
-        p = kErfinvQ[8];
+        float q = kErfinvQ[8];
 #pragma unroll
-        for (int i = 7; i >= 0; --i) p = fmaf(p, x, kErfinvQ[i]);
+        for (int i = 7; i >= 0; --i) q = fmaf(q, x, kErfinvQ[i]);
+        p = tail ? q : p;
     }
     return p * s;
 }

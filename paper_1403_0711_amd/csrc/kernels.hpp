@@ -97,6 +97,61 @@ struct FusedArgs {
 hipError_t launch_fused_sweep(const FusedArgs& a, hipStream_t stream);
 hipError_t prepare_fused_sweep();  // once, before fused launches and outside capture
 
+// Parts the blocked sweep's fused-gather lists are staged in, at most.
+constexpr uint32_t kBlockedMaxParts = 8;
+
+// Both half-sweeps of sweep t in one pass with colour 0 kept in LDS (the
+// streaming temporally blocked sweep): colour 1 read from c1_in, written to
+// c1_out (a different array), colour 0 stored to c0_out only if it is set.
+// Full-row tiles of kty rows walking zc planes; lh % 4 == 0 and the rows a
+// whole number of 16-byte chunks (16-bit storage: lx % 16 == 0).
+struct BlockedArgs {
+    const void* c1_in;
+    void* c1_out;
+    void* c0_out;      // null: colour 0 not stored
+    uint32_t lh, ly, lz;
+    uint32_t kty, zc;  // rows per tile, planes per workgroup
+    uint32_t ring;     // old-plane slots: 4 or 5
+    uint32_t nt;       // non-temporal stores of colour 1
+    uint32_t h0;       // 2t: colour 0 uses h0, colour 1 h0 + 1
+    uint32_t k0, k1, chain;
+    uint32_t xcd_order;
+    const uint32_t* tdev;  // if set, h0 += 2 * tdev[0]
+    int storage;
+    // fused gather (g_key set): per tile (by + nby bz) a list of its charged
+    // colour-0 sites and one of its charged colour-1 sites, each sorted by the
+    // step that gathers it; entry key = step << 16 | byte offset in a ring
+    // slot (colour 0: a colour-0 slot; colour 1: an old-plane slot).  g_cap
+    // entries of each list are staged in LDS (a multiple of 64).  part0: the
+    // (X, Y) pair per tile of this sweep's colour-0 sites (null: this sweep is
+    // not sampled); part1: the pair of the previous sweep's colour-1 sites
+    // (null: it was not sampled).  fin: the sample two sweeps back, recorded
+    // by workgroup 0.
+    const uint32_t* g_off = nullptr;
+    const uint32_t* g_key = nullptr;
+    const double* g_Q = nullptr;
+    const double* g_S = nullptr;
+    uint32_t g_n = 0, g_cap = 0;
+    // the lists are staged in g_parts parts of g_stride steps each (part p:
+    // steps 1 + p g_stride .. (p + 1) g_stride); g_off holds, per colour c
+    // and tile t, the g_parts + 1 part bounds at (c tiles + t)(g_parts + 1)
+    uint32_t g_parts = 1, g_stride = 0;  // g_parts <= kBlockedMaxParts
+    double* part0 = nullptr;
+    double* part1 = nullptr;
+    SampleFinalize fin;
+};
+struct BlockedShape {
+    uint32_t lds;              // dynamic LDS bytes per workgroup
+    uint32_t tasks_total;      // wave-tasks of a step (both colours)
+    uint32_t tasks_per_wave;   // wave-tasks of a compute wave per step
+    uint32_t loads_per_plane;  // load instructions of the producer per plane
+};
+// g_cap: fused-gather entries staged per list (0: no fused gather)
+bool blocked_geometry(uint32_t lh, uint32_t esz, uint32_t kty, uint32_t ring, BlockedShape* out,
+                      uint32_t g_cap = 0);
+hipError_t launch_blocked_sweep(const BlockedArgs& a, hipStream_t stream);
+hipError_t prepare_blocked_sweep();  // once per process (also done by the first launch)
+
 // Gather of the charge-weighted correlator after a sweep (Eq. nsum2):
 // X = sum_s Q_s phi_s, Y = sum_s S_s phi_s^2 over the site-aggregated charge
 // list, O = X^2 - Y compensated-added into bins[2*bin], bins[2*bin+1]; for

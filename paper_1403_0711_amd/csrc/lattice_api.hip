@@ -19,11 +19,58 @@ int check_lattice(const lattice* L) {
 // advanced.  Captured: index tdev[0] + rel, read on the device at run time.
 // fs: the fused gather's part in this sweep (streaming kernel only).
 int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint32_t rel,
-                     const lattice::FusedStep* fs) {
+                     const lattice::FusedStep* fs, bool c0_needed) {
     const uint32_t h0 = tdev ? 2u * rel : (uint32_t)(2 * L->t);
     const int v = L->effective_variant();
     hipError_t e;
-    if (v == LAT_SWEEP_FUSED) {
+    if (v == LAT_SWEEP_BLOCKED) {
+        BlockedArgs a{};
+        a.c1_in = L->c1cur();
+        a.c1_out = L->alt_current ? L->c1main() : L->c1alt;
+        a.c0_out = c0_needed ? L->field : nullptr;
+        a.lh = L->lh;
+        a.ly = (uint32_t)L->ly;
+        a.lz = (uint32_t)L->lz;
+        a.kty = L->blocked_rows();
+        a.zc = L->resolved_slab(v);
+        a.ring = L->blocked_ring();
+        a.nt = (size_t)L->vh * L->esz >= ((size_t)256 << 20) ? 1u : 0u;
+        a.h0 = h0;
+        a.k0 = (uint32_t)L->seed;
+        a.k1 = (uint32_t)(L->seed >> 32);
+        a.chain = L->chain;
+        a.xcd_order = L->resolved_xcd(v);
+        a.tdev = tdev;
+        a.storage = L->storage;
+        if (fs && (fs->open || fs->finish || fs->record)) {  // the fused gather's part in this sweep
+            const lattice::FusedGather& g = L->fg;
+            auto buf = [&](uint32_t k) { return g.d_part + (size_t)(k % 3u) * 4 * g.blocks; };
+            if (fs->open || fs->finish) {
+                a.g_off = g.d_off + 2 * ((size_t)g.blocks + 1);  // the part bounds
+                a.g_key = g.d_key;
+                a.g_Q = g.d_Q;
+                a.g_S = g.d_S;
+                a.g_n = g.n;
+                a.g_cap = g.cap;
+                a.g_parts = g.parts;
+                a.g_stride = g.stride;
+                a.ring = L->blocked_ring(g.cap);
+            }
+            if (fs->open) a.part0 = buf(fs->m + 1u);                               // colour-0 pairs
+            if (fs->finish) a.part1 = buf(fs->m) + 2 * (size_t)g.blocks;           // colour-1 pairs
+            if (fs->record) {
+                a.fin.part = buf(fs->m_rec);
+                a.fin.n = 2 * g.blocks;
+                a.fin.bins = L->d_bins;
+                a.fin.m = fs->m_rec;
+                a.fin.bin_size = (uint32_t)L->bin_size;
+                a.fin.mdev = fs->mdev;
+                a.fin.last_xy = L->last_xy();
+            }
+        }
+        e = launch_blocked_sweep(a, stream);
+        if (e == hipSuccess) L->alt_current = !L->alt_current;
+    } else if (v == LAT_SWEEP_FUSED) {
         void* out = L->alt_current ? L->c1main() : L->c1alt;
         FusedArgs a{L->field, L->c1cur(), out, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, h0,
                     (uint32_t)L->seed, (uint32_t)(L->seed >> 32), L->chain, L->storage, L->resolved_slab(v),
@@ -77,15 +124,16 @@ int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint3
     return LAT_OK;
 }
 
-int enqueue_sweep(lattice* L, const lattice::FusedStep* fs) {
+int enqueue_sweep(lattice* L, const lattice::FusedStep* fs, bool c0_needed) {
     if (L->t >= (int64_t)0x7FFFFFFF) return set_error(LAT_ERR_STATE, "sweep counter exhausted (2^31 sweeps)");
-    return enqueue_sweep_ex(L, L->stream, nullptr, 0, fs);
+    return enqueue_sweep_ex(L, L->stream, nullptr, 0, fs, c0_needed);
 }
 
 // The resident path: n_therm unmeasured sweeps then n_meas sweeps with a
 // sample after every `every`-th, all in one launch.
 int enqueue_resident(lattice* L, int64_t n_therm, int64_t n_meas, int64_t every) {
     if (n_therm + n_meas == 0) return LAT_OK;
+    if (int r = settle_colour1(L)) return r;
     BatchArgs a{};
     a.field = L->field;
     a.site = L->d_site;
@@ -144,9 +192,11 @@ static int enqueue_measure_ex(lattice* L, hipStream_t stream, const uint32_t* md
 
 static int enqueue_measure(lattice* L) { return enqueue_measure_ex(L, L->stream, nullptr, 0); }
 
-// After fused sweeps colour 1 may sit in the second array: copy it home so
-// that every other path sees colour 0 then colour 1 in `field`.
-static int settle_colour1(lattice* L) {
+// After blocked or fused sweeps colour 1 may sit in the second array (the
+// kernels that alternate the two read and write it there): copy it home
+// before a kernel that reads colour 1 at field + vh, and before graph
+// replays, which are captured with colour 1 at home.
+int settle_colour1(lattice* L) {
     if (!L->alt_current) return LAT_OK;
     hipError_t e = hipMemcpyAsync(L->c1main(), L->c1alt, (size_t)L->vh * L->esz, hipMemcpyDeviceToDevice, L->stream);
     if (e != hipSuccess) return hip_fail(e, "colour-1 copy");
@@ -206,10 +256,26 @@ static int graph_capture(lattice* L, lattice::SweepGraph& g, int64_t K, int64_t 
     int rc = LAT_OK;
     uint32_t m = 0;
     const bool fused = graph_gather_key(L, every) != nullptr;
+    const bool blocked = L->effective_variant() == LAT_SWEEP_BLOCKED;
     bool open = false;  // fused: sample m - 1 awaits its colour-1 sites
+    bool mp2 = false;   // blocked: the sweep before the previous one was sampled (sample kp2)
+    uint32_t kp2 = 0;
     for (int64_t s = 0; s < K && rc == LAT_OK; ++s) {
         const bool measured = every > 0 && (s + 1) % every == 0;
-        if (fused) {
+        if (fused && blocked) {
+            lattice::FusedStep fs;
+            fs.finish = open;
+            fs.open = measured;
+            fs.m = m - 1u;
+            fs.mdev = L->counters() + 1;
+            fs.record = mp2;
+            fs.m_rec = kp2;
+            rc = enqueue_sweep_ex(L, L->cap, L->counters(), (uint32_t)s, &fs, s + 1 == K);
+            mp2 = open;
+            kp2 = m - 1u;
+            open = measured;
+            m += measured ? 1u : 0u;
+        } else if (fused) {
             lattice::FusedStep fs;
             fs.finish = open;
             fs.open = measured;
@@ -219,11 +285,14 @@ static int graph_capture(lattice* L, lattice::SweepGraph& g, int64_t K, int64_t 
             open = measured;
             m += measured ? 1u : 0u;
         } else {
-            rc = enqueue_sweep_ex(L, L->cap, L->counters(), (uint32_t)s);
+            rc = enqueue_sweep_ex(L, L->cap, L->counters(), (uint32_t)s, nullptr, measured || s + 1 == K);
             if (rc == LAT_OK && measured) rc = enqueue_measure_ex(L, L->cap, L->counters() + 1, m++);
         }
     }
-    if (rc == LAT_OK && open) rc = enqueue_fused_tail(L, L->cap, m - 1u, L->counters() + 1);
+    if (rc == LAT_OK && fused && blocked && (open || mp2))
+        rc = enqueue_blocked_tail(L, L->cap, mp2, kp2, open, m - 1u, L->counters() + 1);
+    else if (rc == LAT_OK && open)
+        rc = enqueue_fused_tail(L, L->cap, m - 1u, L->counters() + 1);
     if (rc == LAT_OK) {
         e = launch_advance_counters(L->counters(), (uint32_t)K, m, L->cap);
         if (e != hipSuccess) rc = hip_fail(e, "capture");
@@ -261,6 +330,9 @@ static int graph_capture(lattice* L, lattice::SweepGraph& g, int64_t K, int64_t 
 int run_sweeps(lattice* L, int64_t n, int64_t every, bool eager) {
     int64_t done = 0;
     const int64_t K = eager ? 0 : graph_chunk(L, every);
+    const int v = L->effective_variant();
+    if (L->alt_current && ((K > 0 && n >= K) || (v != LAT_SWEEP_BLOCKED && v != LAT_SWEEP_FUSED)))
+        if (int r = settle_colour1(L)) return r;
     if (K > 0 && n >= K) {
         lattice::SweepGraph& g = every > 0 ? L->g_meas : L->g_therm;
         if (!graph_matches(L, g, K, every))
@@ -274,10 +346,28 @@ int run_sweeps(lattice* L, int64_t n, int64_t every, bool eager) {
         if (every > 0) L->n_meas += done / every;
     }
     const bool fused = every > 0 && fused_gather_on(L);
+    const bool blocked = L->effective_variant() == LAT_SWEEP_BLOCKED;
     bool open = false;  // fused: sample L->n_meas - 1 awaits its colour-1 sites
+    bool mp2 = false;   // blocked: the sweep before the previous one was sampled (sample kp2)
+    uint32_t kp2 = 0;
     for (int64_t s = done; s < n; ++s) {
         const bool measured = every > 0 && (s + 1) % every == 0;
-        if (fused) {
+        if (fused && blocked) {
+            // colour-0 sites in this launch, colour-1 sites in the next, the
+            // sample recorded in the one after; only the call's last sweep
+            // stores colour 0
+            lattice::FusedStep fs;
+            fs.finish = open;
+            fs.open = measured;
+            fs.m = (uint32_t)(L->n_meas - 1);
+            fs.record = mp2;
+            fs.m_rec = kp2;
+            if (int r = enqueue_sweep(L, &fs, s + 1 == n)) return r;
+            mp2 = open;
+            kp2 = (uint32_t)(L->n_meas - 1);
+            open = measured;
+            L->n_meas += measured ? 1 : 0;
+        } else if (fused) {
             lattice::FusedStep fs;
             fs.finish = open;
             fs.open = measured;
@@ -286,14 +376,21 @@ int run_sweeps(lattice* L, int64_t n, int64_t every, bool eager) {
             open = measured;
             L->n_meas += measured ? 1 : 0;
         } else {
-            if (int r = enqueue_sweep(L)) return r;
+            // a sweep that keeps colour 0 on chip stores it for a sample read
+            // from memory and at the end of the call
+            if (int r = enqueue_sweep(L, nullptr, measured || s + 1 == n)) return r;
             if (measured)
                 if (int r = enqueue_measure(L)) return r;
         }
     }
-    if (open)
+    if (fused && blocked) {
+        if (open || mp2)
+            if (int r = enqueue_blocked_tail(L, L->stream, mp2, kp2, open, (uint32_t)(L->n_meas - 1), nullptr))
+                return r;
+    } else if (open) {
         if (int r = enqueue_fused_tail(L, L->stream, (uint32_t)(L->n_meas - 1), nullptr)) return r;
-    return settle_colour1(L);
+    }
+    return LAT_OK;
 }
 
 // Bin arrays of every charge set, each with room for n_bins_needed bins
@@ -347,10 +444,14 @@ int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t see
     L->chain = chain_id;
     L->mem = DeviceAllocator(alloc);
     L->stream = static_cast<hipStream_t>(hip_stream);
-    if (hipError_t e = hipGetDevice(&L->device)) {
+    int ncu = 0;
+    hipError_t de = hipGetDevice(&L->device);
+    if (de == hipSuccess) de = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, L->device);
+    if (de != hipSuccess) {
         delete L;
-        return hip_fail(e, "current device");
+        return hip_fail(de, "current device");
     }
+    if (ncu > 0) L->cus = (uint32_t)ncu;
     const size_t fbytes = round_up(2 * (size_t)L->vh * L->esz, 256);
     L->field = L->mem.alloc(fbytes);
     L->d_misc = L->mem.alloc(256);
@@ -363,6 +464,21 @@ int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t see
     if (e != hipSuccess) {
         lattice_destroy(L);
         return hip_fail(e, "field initialisation");
+    }
+    // FP32 boxes beyond the last-level cache: the library's choice is the
+    // blocked sweep, which needs a second colour-1 array (without it, the
+    // streaming sweep)
+    const size_t cbytes = (size_t)L->vh * L->esz;
+    if (L->esz == 4 && L->lh % 4 == 0 && 2 * cbytes >= ((size_t)256 << 20) && cbytes < ((size_t)1 << 31) &&
+        L->blocked_rows() != 0) {
+        L->c1alt = L->mem.alloc(round_up(cbytes, 256));
+        if (L->c1alt && prepare_blocked_sweep() == hipSuccess) {
+            L->auto_blocked = true;
+        } else {
+            (void)hipGetLastError();
+            L->mem.release(L->c1alt);
+            L->c1alt = nullptr;
+        }
     }
     *out = L;
     return LAT_OK;
@@ -395,6 +511,7 @@ void lattice_destroy(lattice_t* L) {
 // Tile configurations the variant's kernel has; for the other variants (the
 // library's choice among them included) a tile every slab kernel has.
 static uint32_t tiles_of(int variant) {
+    if (variant == LAT_SWEEP_BLOCKED) return 65;  // rows per tile, 1 .. 64
     if (variant == LAT_SWEEP_ZSLAB) return kZslabTiles;
     if (variant == LAT_SWEEP_STREAM) return kStreamTiles;
     return (uint32_t)std::min(kZslabTiles, kStreamTiles);
@@ -430,6 +547,24 @@ int lattice_set_variant(lattice_t* L, int variant) {
             if (L->tile != kTileDefault && L->tile >= tiles_of(variant))
                 return set_error(LAT_ERR_ARG, "the selected tile configuration does not exist for this kernel");
             break;
+        case LAT_SWEEP_BLOCKED: {
+            if (L->lh % 4) return set_error(LAT_ERR_ARG, "this sweep kernel needs lx % 8 == 0");
+            if ((size_t)L->vh * L->esz >= ((size_t)1 << 31))
+                return set_error(LAT_ERR_ARG, "the blocked sweep needs each colour array below 2 GiB");
+            const uint32_t keep = L->tile;
+            if (L->tile == 0 || (L->tile != kTileDefault && L->tile > 64)) L->tile = kTileDefault;
+            const bool fits = L->blocked_rows() != 0;
+            L->tile = keep;
+            if (!fits)
+                return set_error(LAT_ERR_ARG, "the blocked sweep needs rows of whole 16-byte chunks that fit in LDS "
+                                              "(16-bit storage: lx % 16 == 0)");
+            if (!L->c1alt) {
+                L->c1alt = L->mem.alloc(round_up((size_t)L->vh * L->esz, 256));
+                if (!L->c1alt) return set_error(LAT_ERR_ALLOC, "allocation of the second colour-1 array failed");
+            }
+            if (hipError_t e = prepare_blocked_sweep()) return hip_fail(e, "blocked sweep set-up");
+            break;
+        }
         case LAT_SWEEP_FUSED:
             if (L->lh % 4) return set_error(LAT_ERR_ARG, "fused sweep needs lx % 8 == 0");
             if (!fused_sweep_supported(L->lh, (uint32_t)L->ly))
@@ -463,6 +598,14 @@ int lattice_get_sample_path(const lattice_t* L, int* fused) {
     return LAT_OK;
 }
 
+int lattice_get_gather_parts(const lattice_t* L, int* parts, int* part_entries) {
+    if (int r = check_lattice(L)) return r;
+    const bool on = latcoul::fused_gather_on(L) && L->fg.variant == LAT_SWEEP_BLOCKED;
+    if (parts) *parts = on ? (int)L->fg.parts : 0;
+    if (part_entries) *part_entries = on ? (int)L->fg.cap : 0;
+    return LAT_OK;
+}
+
 int lattice_use_graphs(lattice_t* L, int mode) {
     if (int r = check_lattice(L)) return r;
     if (mode < 0 || mode > 2) return set_error(LAT_ERR_ARG, "graph mode must be 0, 1 or 2");
@@ -477,6 +620,11 @@ int lattice_set_tuning(lattice_t* L, int64_t planes, int tile, int xcd_order) {
     if (xcd_order > 2) return set_error(LAT_ERR_ARG, "xcd_order must be -1, 0, 1 or 2");
     if (tile < -1 || (tile >= 0 && (uint32_t)tile >= tiles_of(L->variant)))
         return set_error(LAT_ERR_ARG, "unknown tile configuration for the selected sweep kernel");
+    if (L->variant == LAT_SWEEP_BLOCKED && tile >= 0) {
+        BlockedShape sh;
+        if (!blocked_geometry(L->lh, (uint32_t)L->esz, (uint32_t)tile, 4u, &sh))
+            return set_error(LAT_ERR_ARG, "these rows per tile do not fit the blocked sweep's LDS");
+    }
     L->slab = (uint32_t)planes;
     L->tile = tile < 0 ? kTileDefault : (uint32_t)tile;
     L->xcd_order = xcd_order < 0 ? -1 : xcd_order;
@@ -824,9 +972,11 @@ int lattice_force_estimate(lattice_t* L, double* dE_dr, double* stderr_naive, in
 int lattice_get_field(lattice_t* L, float* host_out) {
     if (int r = check_lattice(L)) return r;
     if (!host_out) return set_error(LAT_ERR_ARG, "host_out is NULL");
-    std::vector<unsigned char> buf(2 * (size_t)L->vh * L->esz);
+    const size_t half = (size_t)L->vh * L->esz;
+    std::vector<unsigned char> buf(2 * half);
     hipError_t e = hipStreamSynchronize(L->stream);
-    if (e == hipSuccess) e = hipMemcpy(buf.data(), L->field, buf.size(), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(buf.data(), L->field, half, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(buf.data() + half, L->c1cur(), half, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "field readback");
     compact_to_natural(buf.data(), L->storage, L->lx, L->ly, L->lz, L->vh, host_out);
     return LAT_OK;
@@ -843,6 +993,7 @@ int lattice_set_field(lattice_t* L, const float* host_in) {
     hipError_t e = hipStreamSynchronize(L->stream);
     if (e == hipSuccess) e = hipMemcpy(L->field, buf.data(), buf.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "field upload");
+    L->alt_current = false;  // both colours now at home
     return LAT_OK;
 }
 

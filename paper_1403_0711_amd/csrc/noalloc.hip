@@ -47,7 +47,7 @@ static int scratch_address(int dev, void** out) {
 
 // Bytes of partial sums a measured sweep of L uses on its current path.
 static size_t partial_bytes(const lattice* L) {
-    if (fused_gather_on(L)) return (size_t)L->fg.blocks * 64u;  // two samples x two colours
+    if (fused_gather_on(L)) return (size_t)L->fg.blocks * 32u * L->fg.nbuf;  // samples x two colours x (X, Y)
     return (size_t)L->meas_blocks * 16u * (L->offl ? 1u : L->n_sets);
 }
 
@@ -76,9 +76,8 @@ extern "C" int sweep_and_measure_noalloc(lattice_t* L, int64_t n_sweeps, int64_t
     }
     // the fused gather's lists are built outside (set_charges, or the first
     // sweep_and_measure after a change of kernel or tiling)
-    const uint32_t tile = L->resolved_tile(LAT_SWEEP_STREAM), slab = L->resolved_slab(LAT_SWEEP_STREAM);
-    if (v == LAT_SWEEP_STREAM && L->n_sets == 1 && !L->offl && L->host_charges &&
-        !(L->fg.tried && L->fg.tile == tile && L->fg.slab == slab))
+    if ((v == LAT_SWEEP_STREAM || v == LAT_SWEEP_BLOCKED) && L->n_sets == 1 && !L->offl && L->host_charges &&
+        !fused_gather_current(L))
         return set_error(LAT_ERR_STATE, "the sample lists of the current tiling are not built (set_charges or "
                                         "sweep_and_measure builds them)");
     const size_t need = partial_bytes(L);

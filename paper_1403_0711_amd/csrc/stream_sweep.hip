@@ -52,6 +52,7 @@
 
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "lds_pipe.hpp"
 
 #include <type_traits>
 
@@ -90,34 +91,6 @@ struct Stream {
     }
 };
 
-typedef __attribute__((address_space(3))) void* lds_ptr_t;
-
-// Direct buffer-to-LDS loads: each lane's `bytes` go to dst + lane * bytes.
-// Non-template wrappers: the 16-byte form exists on gfx950 only, and a
-// template kernel that names it directly is dropped by the host pass.
-__device__ __forceinline__ void lds_load_b128(__amdgpu_buffer_rsrc_t r, lds_ptr_t dst, uint32_t voff,
-                                              uint32_t soff) {
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 16, voff, soff, 0, 0);
-}
-__device__ __forceinline__ void lds_load_b32(__amdgpu_buffer_rsrc_t r, lds_ptr_t dst, uint32_t voff,
-                                             uint32_t soff) {
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 4, voff, soff, 0, 0);
-}
-
-// LDS reads of the producer wave.  The compiler makes any LDS access that
-// follows a direct buffer-to-LDS load wait until all of them have landed
-// (vmcnt 0), which would drain the plane ring at every step; these reads
-// wait only for themselves (lgkmcnt 0), inside the asm statement that issues
-// them, so no output register is left pending.  Addresses are LDS byte
-// addresses.
-
-__device__ __forceinline__ uint32_t lds_addr(const void* p) { return (uint32_t)(size_t)(lds_ptr_t)p; }
-
-__device__ __forceinline__ uint32_t lds_read_u32(uint32_t a) {
-    uint32_t r;
-    asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(r) : "v"(a) : "memory");
-    return r;
-}
 // Fused-gather list entries.  Staged key of entry i of a tile's list: the
 // site's plane within the tile's slab (bits 16..31) and its byte offset in
 // a ring slot (bits 0..15); entries are sorted by plane, and entry i always
@@ -125,77 +98,6 @@ __device__ __forceinline__ uint32_t lds_read_u32(uint32_t a) {
 // kGatherRegs keys per lane are held in registers (lists of up to 256).
 constexpr int kGatherRegs = 4;
 constexpr uint32_t kNoEntry = 0xFFFFFFFFu;  // plane field never matches
-
-// One entry's value (at a ring address) and its Q and S (LDS), one wait.
-template <class St>
-__device__ __forceinline__ void lds_read_entry(uint32_t av, uint32_t aq, uint32_t as, float& v, double& Qi,
-                                               double& Si) {
-    u32x2 q, sv;
-    uint32_t r;
-    if constexpr (St::kBytes == 4)
-        asm volatile("ds_read_b32 %0, %3\n\tds_read_b64 %1, %4\n\tds_read_b64 %2, %5\n\ts_waitcnt lgkmcnt(0)"
-                     : "=&v"(r), "=&v"(q), "=&v"(sv)
-                     : "v"(av), "v"(aq), "v"(as)
-                     : "memory");
-    else
-        asm volatile("ds_read_u16 %0, %3\n\tds_read_b64 %1, %4\n\tds_read_b64 %2, %5\n\ts_waitcnt lgkmcnt(0)"
-                     : "=&v"(r), "=&v"(q), "=&v"(sv)
-                     : "v"(av), "v"(aq), "v"(as)
-                     : "memory");
-    if constexpr (St::kBytes == 4)
-        v = __uint_as_float(r);
-    else if constexpr (std::is_same<St, StoreBF16>::value)
-        v = __uint_as_float(r << 16);
-    else
-        v = (float)__builtin_bit_cast(_Float16, (uint16_t)r);
-    Qi = __builtin_bit_cast(double, q);
-    Si = __builtin_bit_cast(double, sv);
-}
-
-// s_waitcnt immediates (gfx9 encoding): vmcnt in bits 3:0 and 15:14, expcnt
-// 6:4, lgkmcnt 11:8; a field at its maximum does not wait.
-template <int kVm>
-__device__ __forceinline__ void wait_vm_lgkm0() {
-    static_assert(kVm >= 0 && kVm < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((kVm & 15) | (7 << 4) | (0 << 8) | ((kVm >> 4) << 14));
-}
-
-// Workgroup barrier for the producer: its LDS writes were waited for above,
-// and the asm statements keep the compiler from moving memory operations
-// across the barrier.
-__device__ __forceinline__ void producer_barrier() {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
-
-// Finalize of the previous sample by workgroup 0 of a launch: threads below
-// kLoaders (the compute waves, which issue no direct-to-LDS loads) sum the
-// partial pairs with several loads in flight each, every thread takes part in
-// the workgroup sum, thread 0 records the sample.  It runs while the
-// producer's first planes are in flight.
-template <int kThreads, int kLoaders>
-__device__ __forceinline__ void finalize_in_workgroup(const SampleFinalize& f) {
-    constexpr int kUnroll = 4;  // few registers: this code shares the kernel's register budget
-    const uint32_t t = threadIdx.x;
-    double X = 0.0, Y = 0.0;
-    if (t < (uint32_t)kLoaders) {
-        const double2* p = reinterpret_cast<const double2*>(f.part);
-        for (uint32_t b0 = 0; b0 < f.n; b0 += kLoaders * kUnroll) {
-            double2 v[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) v[u] = p[min(b0 + (uint32_t)u * kLoaders + t, f.n - 1u)];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                if (b0 + (uint32_t)u * kLoaders + t < f.n) {
-                    X += v[u].x;
-                    Y += v[u].y;
-                }
-        }
-    }
-    block_sum2<kThreads>(X, Y);
-    if (t == 0) record_sample(X, Y, f.bins, (f.m + (f.mdev ? f.mdev[0] : 0u)) / f.bin_size, f.last_xy);
-}
 
 // kNT: non-temporal stores of the updated colour.
 template <class St, int kM, int kTY, int kRing, bool kNT>

@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "liblatcoul.so")
 
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
-VARIANT = {"auto": 0, "quad": 1, "generic": 2, "zslab": 3, "fused": 4, "resident": 5, "stream": 6}
+VARIANT = {"auto": 0, "quad": 1, "generic": 2, "zslab": 3, "fused": 4, "resident": 5, "stream": 6,
+           "blocked": 7}
 ERR_NAMES = {1: "LAT_ERR_ARG", 2: "LAT_ERR_STATE", 3: "LAT_ERR_ALLOC", 4: "LAT_ERR_DEVICE"}
 
 _i64 = ctypes.c_int64
@@ -82,6 +83,7 @@ def load_library() -> ctypes.CDLL:
         "lattice_use_graphs": (_int, [_p, _int]),
         "lattice_get_tuning": (_int, [_p, ctypes.POINTER(_int), _pi64, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
         "lattice_get_sample_path": (_int, [_p, ctypes.POINTER(_int)]),
+        "lattice_get_gather_parts": (_int, [_p, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
         "lattice_autotune": (_int, [_p, _i64, ctypes.POINTER(_int), _pi64, ctypes.POINTER(_int),
                                     ctypes.POINTER(_int), _pd]),
         "lattice_get_field": (_int, [_p, _p]),
@@ -326,6 +328,13 @@ class Lattice:
         f = ctypes.c_int()
         self._call(self.lib.lattice_get_sample_path, ctypes.byref(f))
         return "fused" if f.value else "separate"
+
+    def gather_parts(self) -> tuple:
+        """(parts, entries per part) of the blocked sweep's staged charge
+        lists; (0, 0) when samples are not gathered inside that kernel."""
+        p, e = ctypes.c_int(), ctypes.c_int()
+        self._call(self.lib.lattice_get_gather_parts, ctypes.byref(p), ctypes.byref(e))
+        return p.value, e.value
 
     def autotune(self, reps: int = 5) -> dict:
         """Time the sweep kernels on scratch memory and keep the fastest."""

@@ -195,15 +195,16 @@ def test_fused_gather_new_charges_and_fallbacks(lat_mod):
 
 
 def test_fused_gather_full_size(lat_mod):
-    """768^3 in the configuration the benchmark times (library default
-    kernel and tiling) with its charge workload: fused samples against the
-    separate gather on the same chain."""
+    """768^3 on the streaming kernel in its default tiling with the
+    benchmark's charge workload: fused samples against the separate gather
+    on the same chain."""
     print("[gpu] fused gather 768^3", flush=True)
     from paper_1403_0711_amd import workloads
 
     c = workloads.largest_subdomain()
     shape, xyz, q = c.shape, c.xyz, c.q
     a = lat_mod.Lattice(shape, seed=77)
+    a.set_variant("stream")
     a.set_charges(xyz, q)
     assert a.tuning()["variant"] == "stream"
     a.thermalise(2)
@@ -263,3 +264,174 @@ def test_workgroup_orders_agree(lat_mod):
             np.testing.assert_array_equal(f, out[0][0])
             np.testing.assert_array_equal(bins, out[0][1])
             assert path == out[0][2] == "fused"
+
+
+# Blocked sweep (both half-sweeps per pass): its producer wave gathers a
+# sample's colour-0 sites from the colour-0 ring in the sample's own launch
+# and its colour-1 sites from the old-plane ring of the next launch; the
+# launch after records it.  (shape, storage, planes, rows per tile, order)
+BLOCKED_CASES = [
+    ((64, 24, 20), "fp32", 0, -1, 2),
+    ((64, 24, 20), "fp32", 5, 3, 1),
+    ((200, 37, 33), "fp32", 7, 5, 2),   # 25 quads per row, ragged rows and slabs
+    ((64, 24, 20), "fp16", 4, 6, 0),
+    ((64, 24, 20), "bf16", 3, 2, 2),
+    ((8, 1, 3), "fp32", 1, 1, 0),       # one plane per workgroup, one quad per row
+    ((96, 37, 23), "fp32", 2, 7, 1),
+]
+
+
+def _blocked_pair(lat_mod, shape, storage, planes, rows, xcd, xyz, q, seed=3, chain=5):
+    a = lat_mod.Lattice(shape, storage, seed=seed, chain_id=chain)
+    a.set_variant("blocked")
+    a.set_tuning(planes, rows, xcd)
+    b = lat_mod.Lattice(shape, storage, seed=seed, chain_id=chain)
+    b.set_variant("zslab")
+    for lat in (a, b):
+        lat.set_charges(xyz, q)
+    return a, b
+
+
+@pytest.mark.parametrize("shape,storage,planes,rows,xcd", BLOCKED_CASES)
+def test_blocked_fused_gather_matches_separate_and_oracle(lat_mod, shape, storage, planes, rows, xcd):
+    print(f"[gpu] blocked fused gather {shape} {storage} planes={planes} rows={rows} xcd={xcd}", flush=True)
+    xyz, q = _charges(shape, 300, 12)
+    a, b = _blocked_pair(lat_mod, shape, storage, planes, rows, xcd, xyz, q)
+    for lat in (a, b):
+        lat.thermalise(5)
+        lat.sweep_and_measure(40, 1, 1)
+    assert a.sample_path() == "fused" and b.sample_path() == "separate"
+    fa, fb = a.get_field(), b.get_field()
+    np.testing.assert_array_equal(fa, fb)
+    sa, sb = a.get_state(), b.get_state()
+    assert sa[:2] == sb[:2] == (45, 40)
+    tol = 1e-12 * _scale(q, fa)
+    assert np.abs(sa[2] - sb[2]).max() <= tol
+    ref = oracle.OracleChain(shape)
+    ref.phi = fa.astype(np.float64)
+    ref.set_charges(xyz, q)
+    X, Y = ref.gather()
+    Xa, Ya = a.last_measure()
+    assert abs(Xa - X) <= 1e-12 * max(1.0, np.sum(np.abs(q)) * np.abs(fa).max())
+    assert abs(Ya - Y) <= tol
+
+
+@pytest.mark.parametrize("shape,planes,rows,n_charges,part_cap", [
+    ((64, 24, 20), 7, 5, 3000, 64),    # two or more parts per list
+    ((64, 24, 20), 16, 4, 6000, 128),  # four or more parts, ragged last slab
+    ((200, 37, 33), 11, 6, 4000, 64),   # ragged rows and slabs
+])
+def test_blocked_fused_gather_in_parts(lat_mod, monkeypatch, shape, planes, rows, n_charges, part_cap):
+    """Charge lists staged in several parts (a part restaged in the step
+    before its first one): samples equal to the separate gather's and the
+    oracle's, fields bit-identical."""
+    print(f"[gpu] blocked fused gather in parts {shape} planes={planes} rows={rows} "
+          f"charges={n_charges} cap={part_cap}", flush=True)
+    monkeypatch.setenv("LATCOUL_GATHER_PART_CAP", str(part_cap))
+    xyz, q = _charges(shape, n_charges, 31)
+    a, b = _blocked_pair(lat_mod, shape, "fp32", planes, rows, 1, xyz, q)
+    parts, entries = a.gather_parts()
+    assert parts >= 2 and 0 < entries <= max(64, part_cap)
+    for lat in (a, b):
+        lat.thermalise(3)
+        lat.sweep_and_measure(25, 1, 1)
+    assert a.sample_path() == "fused" and b.sample_path() == "separate"
+    fa = a.get_field()
+    np.testing.assert_array_equal(fa, b.get_field())
+    sa, sb = a.get_state(), b.get_state()
+    assert np.abs(sa[2] - sb[2]).max() <= 1e-12 * _scale(q, fa)
+    ref = oracle.OracleChain(shape)
+    ref.phi = fa.astype(np.float64)
+    ref.set_charges(xyz, q)
+    X, Y = ref.gather()
+    Xa, Ya = a.last_measure()
+    assert abs(Xa - X) <= 1e-12 * max(1.0, np.sum(np.abs(q)) * np.abs(fa).max())
+    assert abs(Ya - Y) <= 1e-12 * _scale(q, fa)
+
+
+def test_blocked_fused_gather_graphs_and_retiling(lat_mod):
+    """Blocked sweeps with the fused gather: graph replays bit-identical to
+    launch-by-launch runs, tiling changes between runs, samples every k-th
+    sweep (a sample whose colour-1 sites the next launch gathers, recorded by
+    the one after or by the call's tail), all equal to the separate gather."""
+    print("[gpu] blocked fused gather graphs + retiling", flush=True)
+    shape = (64, 24, 20)
+    xyz, q = _charges(shape, 150, 5)
+    lats = []
+    for mode in (0, 2):
+        lat = lat_mod.Lattice(shape, seed=21, chain_id=2)
+        lat.set_variant("blocked")
+        lat.use_graphs(mode)
+        lat.set_charges(xyz, q)
+        lats.append(lat)
+    sep = lat_mod.Lattice(shape, seed=21, chain_id=2)
+    sep.set_variant("zslab")
+    sep.set_charges(xyz, q)
+    for step, (planes, rows, xcd) in enumerate([(0, -1, 2), (7, 5, 1), (3, 2, 0), (20, 16, 2)]):
+        for lat in lats:
+            lat.set_tuning(planes, rows, xcd)
+            lat.thermalise(70)
+            lat.sweep_and_measure(96, 3, 8)
+            assert lat.sample_path() == "fused"
+        sep.thermalise(70)
+        sep.sweep_and_measure(96, 3, 8)
+        s0, s1, s2 = lats[0].get_state(), lats[1].get_state(), sep.get_state()
+        assert s0[0] == s1[0] == s2[0] == 166 * (step + 1)
+        np.testing.assert_array_equal(s0[2], s1[2])
+        np.testing.assert_array_equal(lats[0].get_field(), lats[1].get_field())
+        np.testing.assert_array_equal(lats[0].get_field(), sep.get_field())
+        assert np.abs(s0[2] - s2[2]).max() <= 1e-12 * _scale(q, sep.get_field()) * 8
+        assert lats[0].last_measure() == lats[1].last_measure()
+    for n, every in ((37, 5), (3, 1), (1, 1), (2, 2), (64, 1), (10, 4)):
+        for lat in lats + [sep]:
+            lat.sweep_and_measure(n, every, 8)
+        s0, s1, s2 = lats[0].get_state(), lats[1].get_state(), sep.get_state()
+        assert s0[1] == s1[1] == s2[1]
+        np.testing.assert_array_equal(s0[2], s1[2])
+        assert np.abs(s0[2] - s2[2]).max() <= 1e-12 * _scale(q, sep.get_field()) * 8
+        assert lats[0].last_measure() == lats[1].last_measure()
+        X2, Y2 = sep.last_measure()
+        assert abs(lats[0].last_measure()[1] - Y2) <= 1e-12 * max(1.0, abs(Y2))
+
+
+def test_blocked_fused_gather_full_size(lat_mod):
+    """768^3 with the benchmark's charges on the blocked sweep in its default
+    configuration: fused samples against the oracle's gather of the
+    read-back field, and against the separate gather of the streaming
+    kernel on the same chain."""
+    print("[gpu] blocked fused gather 768^3", flush=True)
+    from paper_1403_0711_amd import workloads
+
+    c = workloads.largest_subdomain()
+    shape, xyz, q = c.shape, c.xyz, c.q
+    a = lat_mod.Lattice(shape, seed=77)
+    a.set_variant("blocked")
+    a.set_charges(xyz, q)
+    a.thermalise(2)
+    a.sweep_and_measure(3, 1, 1)
+    assert a.sample_path() == "fused"
+    print("[gpu] staged parts, entries per part:", a.gather_parts(), flush=True)
+    assert a.gather_parts()[0] >= 1
+    sa = a.get_state()
+    Xa, Ya = a.last_measure()
+    phi = a.get_field()
+    a.close()
+    v = np.ascontiguousarray(phi[xyz[:, 2], xyz[:, 1], xyz[:, 0]], dtype=np.float64)
+    del phi
+    n = v.shape[0]
+    line = oracle.OracleChain((n, 1, 1), seed=0)
+    line.phi = v.reshape(1, 1, n)
+    line.set_charges(np.stack([np.arange(n), np.zeros(n), np.zeros(n)], axis=1), q)
+    Xo, Yo = line.gather()
+    tol = (n + 4) * 2.0 ** -53
+    assert abs(Xa - Xo) <= tol * np.sum(np.abs(q * v)), (Xa, Xo)
+    assert abs(Ya - Yo) <= tol * Yo, (Ya, Yo)
+    b = lat_mod.Lattice(shape, seed=77)
+    b.set_variant("stream")
+    b.set_charges(xyz, q)
+    b.thermalise(2)
+    b.sweep_and_measure(3, 1, 1)
+    sb = b.get_state()
+    b.close()
+    qa = float(np.sum(np.abs(q)))
+    assert np.abs(sa[2] - sb[2]).max() <= 1e-12 * (qa * 10.0) ** 2
