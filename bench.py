@@ -214,9 +214,11 @@ def kernel_key(kname: str, lat_tuning: dict, workload: str, storage: str) -> str
     return f"{kname}_p{t.get('planes', 0)}_t{t.get('tile', 0)}_{workload}_{storage}"
 
 
-def fp16_comparison(cs, seed, steps, bin_size, torch, lattice, tuned: bool):
-    """The same workload with FP16 field storage (FP32 arithmetic): per-step time."""
-    lat = lattice.Lattice(cs.shape, "fp16", seed=seed)
+def fp16_comparison(cs, seed, steps, bin_size, torch, lattice, tuned: bool, storage: str = "fp16"):
+    """The same workload with 16-bit field storage (FP16 or BF16; FP32
+    arithmetic): per-step time after the workload's thermalisation-free
+    warm-up, the library's default kernel for that storage."""
+    lat = lattice.Lattice(cs.shape, storage, seed=seed)
     if tuned:
         lat.autotune(5)
     tune = lat.tuning()
@@ -233,11 +235,17 @@ def fp16_comparison(cs, seed, steps, bin_size, torch, lattice, tuned: bool):
 
 
 def batched_comparison(sweeps, torch, lattice, workloads):
-    """512 chains (edges 24..64, 16..512 charges) in one persistent launch."""
+    """512 chains (edges 24..64, 16..512 charges) in one persistent launch,
+    the half-sweep form chosen per box by the batch autotuner.  Against the
+    vector-ALU ceiling (the same algorithmic slots per site update as the
+    single lattice), and against the bound of its largest chains: one
+    workgroup sweeps a chain, so the launch lasts at least as long as a 64^3
+    chain takes on one CU (reported as the workgroup's rate)."""
     chains = workloads.batched_chains(seed=0)
     b = lattice.Batch([c.shape for c in chains], "fp32", seed=0)
     for k, c in enumerate(chains):
         b.set_charges(k, c.xyz, c.q)
+    n_ring = b.autotune(3)
     b.run(5, 10, 10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -246,8 +254,15 @@ def batched_comparison(sweeps, torch, lattice, workloads):
     dt = time.perf_counter() - t0
     sites = sum(int(np.prod(c.shape)) for c in chains)
     b.close()
-    return {"chains": len(chains), "sites": sites, "sweeps": sweeps, "seconds": dt,
-            "site_updates_per_s": sites * sweeps / dt}
+    rate = sites * sweeps / dt
+    slots = ALU_SLOTS_PER_SITE * rate / 1e12
+    return {"chains": len(chains), "sites": sites, "sweeps": sweeps, "seconds": dt, "site_updates_per_s": rate,
+            "chains_on_the_lds_ring": n_ring,
+            "roofline": {"bound": "alu", "achieved": slots, "peak": ALU_PEAK_TSLOTS, "unit": "Tslot/s",
+                         "frac": slots / ALU_PEAK_TSLOTS},
+            "largest_chain": {"edge": 64, "sites": 64 ** 3,
+                              "sweep_time_bound_ms": 1e3 * dt / sweeps,
+                              "one_workgroup_site_updates_per_s": 64 ** 3 * sweeps / dt}}
 
 
 def dense_batch(sweeps, torch, lattice):
@@ -282,22 +297,57 @@ def calibrate_copy(spec, torch):
     print(json.dumps({"calibrate_copy_bytes_read": n * 4, "calibrate_copy_bytes_written": n * 4}), flush=True)
 
 
-def precision_coupled(sweeps, torch, lattice, workloads):
+def binning_curve(series: np.ndarray):
+    """Standard error of the mean of a correlated series from blocks of
+    1, 2, 4, ... samples (at least 16 blocks): the plateau is the error with
+    the autocorrelation included; tau_int = (plateau / naive)^2 / 2."""
+    out = []
+    b = 1
+    while len(series) // b >= 16:
+        n = len(series) // b
+        m = series[: n * b].reshape(n, b).mean(axis=1)
+        out.append((b, float(m.std(ddof=1) / math.sqrt(n))))
+        b *= 2
+    return out
+
+
+def tau_and_error(series: np.ndarray):
+    """The binning curve's largest error (its plateau, or a lower bound when
+    the series is shorter than a few autocorrelation times) and tau_int."""
+    curve = binning_curve(series)
+    if not curve:
+        return None, None, curve
+    err = max(e for _, e in curve)
+    return err, 0.5 * (err / curve[0][1]) ** 2, curve
+
+
+def precision_coupled(sweeps, torch, lattice, workloads, therm=40000):
     """Reduced-precision storage at equal accuracy, on the 384^3 Gaussian blob
-    (2e5 charges of +1): FP32, BF16 and FP16 chains on one Philox stream (same
-    seed and chain id, no thermalisation), one sample per sweep.  The chains
-    move together, so the per-sweep difference of a 16-bit chain's sample from
-    the FP32 chain's measures its bias with an error far below the chains' own
-    statistical error; with equal statistics, time to a given error scales as
-    the cost per sweep.  Each storage format runs the sweep configuration the
-    library's autotuner picks for it on this machine (kernel choice does not
-    change the chain: every kernel computes the same update)."""
+    (2e5 charges of +1).  One FP32 chain is thermalised (`therm` sweeps from
+    phi = 0, about 5 e-folds of the slowest mode's variance); its field is the
+    common start of an FP32, a BF16 and an FP16 chain on one Philox stream
+    (same seed and chain id; the 16-bit copies round it), one sample per
+    sweep.  The chains move together, so the per-sweep difference of a 16-bit
+    chain's sample from the FP32 chain's measures its bias with an error far
+    below the chains' own statistical error; each format also reports its
+    mean against the exact E_lat with the binning curve's error (a lower
+    bound: `sweeps` is about 2 autocorrelation times here).  With equal
+    statistics, time to a given error scales as the cost per sweep.  Each
+    format runs the sweep configuration the library's autotuner picks for it
+    on this machine (kernel choice does not change the chain: every kernel
+    computes the same update)."""
     name = "gaussian_blob_384"
     spec = workloads.WORKLOADS[name]
     cs = spec["make"]()
-    out, series = {"workload": name, "sweeps": sweeps, "E_exact": exact_energy(name)}, {}
+    E = exact_energy(name)
+    out, series = {"workload": name, "sweeps": sweeps, "thermalisation_fp32": therm, "E_exact": E}, {}
+    lat = lattice.Lattice(cs.shape, "fp32", seed=spec["philox_seed"], chain_id=7)
+    lat.thermalise(therm)
+    phi0 = lat.get_field()
+    lat.close()
     for st in ("fp32", "bf16", "fp16"):
         lat = lattice.Lattice(cs.shape, st, seed=spec["philox_seed"])
+        lat.set_field(phi0)
         lat.set_charges(cs.xyz, cs.q)
         lat.autotune(3)
         torch.cuda.synchronize()
@@ -307,17 +357,112 @@ def precision_coupled(sweeps, torch, lattice, workloads):
         dt = time.perf_counter() - t0
         _, n, bins = lat.get_state()
         series[st] = bins[:, 0] - bins[:, 1]  # one sample per bin
-        out[st] = {"ms_per_sweep": 1e3 * dt / sweeps, "mean_O": float(series[st].mean()), "tuning": lat.tuning()}
+        err, tau, _ = tau_and_error(series[st])
+        mean = float(series[st].mean())
+        out[st] = {"ms_per_sweep": 1e3 * dt / sweeps, "mean_O": mean, "stderr_binned": err, "tau_int": tau,
+                   "tuning": lat.tuning()}
+        if E:
+            out[st]["rel_error_vs_exact"] = (mean - E) / E
+            out[st]["rel_stderr"] = err / abs(E) if err is not None else None
         lat.close()
+    del phi0
     out["sd_O"] = float(series["fp32"].std())
-    nblk = 10
     for st in ("bf16", "fp16"):
+        # the difference of two coupled chains drifts in the slowest modes
+        # (rounding errors accumulate there over their relaxation time, about
+        # 1e4 sweeps on this machine): its error is the binning curve's largest,
+        # a lower bound when the run is not much longer than that time
         d = series[st] - series["fp32"]
-        blocks = d[: len(d) // nblk * nblk].reshape(nblk, -1).mean(axis=1)
-        out[st].update({"bias_vs_fp32": float(d.mean()),
-                        "bias_stderr": float(blocks.std(ddof=1) / math.sqrt(nblk)),
+        err, tau, _ = tau_and_error(d)
+        out[st].update({"bias_vs_fp32": float(d.mean()), "bias_stderr": err, "bias_tau_int": tau,
+                        "bias_rel_to_exact": float(d.mean()) / E if E else None,
                         "sd_of_difference": float(d.std()),
                         "cost_vs_fp32": out[st]["ms_per_sweep"] / out["fp32"]["ms_per_sweep"]})
+    return out
+
+
+def time_to_1pct_256(torch, lattice, workloads, therm=2000, sweeps=4000):
+    """Time to a 1% statistical error on E_N for the 256^3 chain with 65,536
+    charges of +-1 (E_lat = 12.0, sd(O) about 2e4: billions of samples, so
+    extrapolated): the library's default sweep, one sample per sweep after
+    `therm` sweeps; the error of the mean from the binning curve (tau_int
+    from its plateau), time = t_run (error / 1%)^2."""
+    name = "large_neutral_256"
+    spec = workloads.WORKLOADS[name]
+    cs = spec["make"]()
+    E = exact_energy(name)
+    lat = lattice.Lattice(cs.shape, "fp32", seed=spec["philox_seed"])
+    lat.set_charges(cs.xyz, cs.q)
+    lat.thermalise(therm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.sweep_and_measure(sweeps, 1, 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, _, bins = lat.get_state()
+    tuning = lat.tuning()
+    lat.close()
+    O = bins[:, 0] - bins[:, 1]
+    err, tau, curve = tau_and_error(O)
+    out = {"workload": name, "thermalisation": therm, "sweeps": sweeps, "seconds_run": dt,
+           "ms_per_sweep": 1e3 * dt / sweeps, "mean": float(O.mean()), "stderr": err, "tau_int": tau,
+           "binning_curve": curve, "E_exact": E, "tuning": tuning}
+    if E and err:
+        out["time_to_1pct_s"] = dt * (err / (0.01 * abs(E))) ** 2
+        out["kind"] = "extrapolated"
+    return out
+
+
+def batched_time_to_1pct(torch, lattice, workloads, therm=1000, sweeps=2000, bin_size=100, sample=32):
+    """Time to 1% on the 512-chain batch (edges 24..64, 16..512 charges):
+    all chains in one persistent launch against the same chains run one by
+    one with the single-lattice library (the library's default sweep per
+    box).  Both give each chain the same field and samples (same kernel
+    arithmetic, same Philox streams), so their errors are equal and time to
+    1% scales as wall time: t_run (error / 1%)^2 per chain, its median over
+    the chains with an exact energy reported.  One by one is timed on every
+    (512 / sample)-th chain and scaled to the 512."""
+    chains = workloads.batched_chains(seed=0)
+    with open(EXACT_FILE) as f:
+        E = json.load(f).get("batched_512", {}).get("E_lat", [])
+    b = lattice.Batch([c.shape for c in chains], "fp32", seed=0)
+    for k, c in enumerate(chains):
+        b.set_charges(k, c.xyz, c.q)
+    b.run(therm, 0, bin_size)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(0, sweeps, bin_size)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    ratios = []
+    for k in range(min(len(E), len(chains))):
+        m, se = b.energy_estimate(k)[:2]
+        if E[k] and math.isfinite(se):
+            ratios.append((se / (0.01 * abs(E[k]))) ** 2)
+    b.close()
+    step = max(1, len(chains) // sample)
+    picked = list(range(0, len(chains), step))
+    t0 = time.perf_counter()
+    for k in picked:
+        c = chains[k]
+        lat = lattice.Lattice(c.shape, "fp32", seed=0, chain_id=k)
+        lat.set_charges(c.xyz, c.q)
+        lat.thermalise(therm)
+        lat.sweep_and_measure(sweeps, 1, bin_size)
+        lat.energy_estimate(allow_few_bins=True)
+        lat.close()
+    torch.cuda.synchronize()
+    t_one = (time.perf_counter() - t0) * len(chains) / len(picked)
+    t_batch_all = t_batch * (therm + sweeps) / sweeps  # the batch's thermalisation too, as one by one
+    med = float(np.median(ratios)) if ratios else None
+    out = {"chains": len(chains), "thermalisation": therm, "sweeps": sweeps, "bin_size": bin_size,
+           "batched_seconds": t_batch_all, "one_by_one_seconds": t_one,
+           "one_by_one_timed_chains": len(picked), "speedup": t_one / t_batch_all,
+           "chains_with_exact_energy": len(ratios), "median_error_over_1pct_squared": med}
+    if med:
+        out["time_to_1pct_batched_s"] = t_batch_all * med
+        out["time_to_1pct_one_by_one_s"] = t_one * med
+        out["kind"] = "extrapolated"
     return out
 
 
@@ -613,13 +758,16 @@ def main():
             out["copy_same_bytes"] = copy_reference(bytes_per_launch // 2, torch)
             out["copy_same_bytes"]["kernel_vs_copy"] = out["copy_same_bytes"]["ms"] / launch_ms
             if args.storage == "fp32":
-                f16 = fp16_comparison(cs, seed, min(args.steps, 200), bin_size, torch, lattice,
-                                      args.variant == "tuned")
-                f16["speedup_vs_fp32"] = ms_per_step / f16["ms_per_step"]
-                out["fp16_storage"] = f16
+                for st in ("fp16", "bf16"):
+                    r = fp16_comparison(cs, seed, min(args.steps, 200), bin_size, torch, lattice,
+                                        args.variant == "tuned", storage=st)
+                    r["speedup_vs_fp32"] = ms_per_step / r["ms_per_step"]
+                    out[f"{st}_storage"] = r
             out["batched_512"] = batched_comparison(200, torch, lattice, workloads)
             out["batched_256x64"] = dense_batch(100, torch, lattice)
             out["time_to_1pct_16"] = time_to_1pct_measured(torch, lattice, workloads)
+            out["time_to_1pct_256"] = time_to_1pct_256(torch, lattice, workloads)
+            out["time_to_1pct_batched_512"] = batched_time_to_1pct(torch, lattice, workloads)
             out["precision_coupled"] = precision_coupled(args.coupled_sweeps, torch, lattice, workloads)
             out["figures_128"] = figures_comparison(args.figures_sweeps)
             if args.storage == "fp32":

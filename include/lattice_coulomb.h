@@ -171,8 +171,11 @@ int thermalise(lattice_t *lat, int64_t n_sweeps);
 /* Enqueue n_sweeps sweeps; after every measure_every-th one (counted within
  * this call) take one sample O = X^2 - Y into the bins (Eq. nsum2).
  * bin_size >= 1 must equal the value used by earlier calls since the last
- * set_charges.  Errors: LAT_ERR_ARG for n_sweeps < 0, measure_every < 1,
- * bin_size < 1 or a changed bin_size. */
+ * set_charges.  Samples fill consecutive bins of bin_size across calls, so
+ * bin_size need not divide the number of samples: the last bin may be
+ * partial, and energy_estimate counts it in the mean only.  Errors:
+ * LAT_ERR_ARG for n_sweeps < 0, measure_every < 1, bin_size < 1 or a changed
+ * bin_size. */
 int sweep_and_measure(lattice_t *lat, int64_t n_sweeps, int64_t measure_every,
                       int64_t bin_size);
 
@@ -181,7 +184,9 @@ int sweep_and_measure(lattice_t *lat, int64_t n_sweeps, int64_t measure_every,
  * n_b full bins (m_b bin means, m their mean); a partial last bin enters the
  * mean only.  Any output pointer may be NULL.  Errors: LAT_ERR_STATE with
  * fewer than 2 full bins (outputs still written, stderr = NaN) or when a
- * non-finite sample is found. */
+ * bin holds a non-finite sum.  Only the samples are checked, not the field:
+ * a non-finite field value reaches the estimate through the samples taken
+ * after it appeared (lattice_get_field reads the field itself). */
 int energy_estimate(lattice_t *lat, double *mean, double *stderr_binned, int64_t *n_samples,
                     int64_t *n_bins);
 
@@ -354,10 +359,20 @@ int batch_set_charges(lattice_batch_t *b, int64_t chain, int64_t n, const int32_
  * bins of bin_size) for every chain, in one persistent launch.  Batches whose
  * fields fill the 256 MiB last-level cache sweep chains of at most 3072 quads
  * (4 compact sites) per plane through an LDS ring, each value loaded from
- * memory once per half-sweep; chains of at most 8192 sites (lx / 8 * ly * lz
- * quads <= 1024) keep their whole field in LDS in any batch.  The chains'
- * fields are the same either way. */
+ * memory once per half-sweep (after batch_autotune: the form it chose for
+ * each box); chains of at most 8192 sites (lx / 8 * ly * lz quads <= 1024)
+ * keep their whole field in LDS in any batch.  The chains' fields are the
+ * same either way. */
 int batch_run(lattice_batch_t *b, int64_t n_therm, int64_t n_meas, int64_t bin_size);
+
+/* Choose the half-sweep form (LDS ring or memory) per box of the batch: for
+ * each box the ring applies to, a scratch batch of as many chains of that box
+ * as this batch holds is timed over reps sweeps (1 <= reps <= 1000) each way,
+ * and the ring kept only where it is more than 3% faster.  Choices are cached
+ * per (device architecture, box, storage, number of chains) for the process.
+ * The chains' fields and samples do not change.  *n_ring (may be NULL): the
+ * chains that will use the ring.  Synchronises; allocates scratch fields. */
+int batch_autotune(lattice_batch_t *b, int64_t reps, int64_t *n_ring);
 
 /* Estimate of one chain (as energy_estimate). */
 int batch_energy_estimate(lattice_batch_t *b, int64_t chain, double *mean,

@@ -77,6 +77,8 @@ def load() -> ctypes.CDLL:
     lib.orc_site_values_f32.restype = None
     lib.orc_noise_grid.argtypes = [_i64, _i64, _p]
     lib.orc_noise_grid.restype = None
+    lib.orc_cg_laplacian.argtypes = [_i64, _i64, _i64, _p, _p, _d, _i64]
+    lib.orc_cg_laplacian.restype = _i64
     lib.orc_max_threads.argtypes = []
     lib.orc_max_threads.restype = ctypes.c_int
     lib.orc_set_threads.argtypes = [ctypes.c_int]
@@ -216,6 +218,21 @@ def noise_grid(k_first: int, n: int) -> np.ndarray:
     out = np.zeros(int(n), dtype=np.float64)
     load().orc_noise_grid(int(k_first), int(n), _ptr(out))
     return out
+
+
+def green_column_cg(shape, site, rtol: float = 1e-13, maxit: int = 100000) -> np.ndarray:
+    """Column G(., n) of the lattice propagator G = (-Delta_L)^{-1} (Dirichlet
+    box, the Hessian of the paper's discretised action) for the site n =
+    (x, y, z): the solution of -Delta_L u = e_n by plain FP64 conjugate
+    gradients; array order (z, y, x)."""
+    lx, ly, lz = (int(v) for v in shape)
+    b = np.zeros((lz, ly, lx))
+    b[site[2], site[1], site[0]] = 1.0
+    u = np.empty_like(b)
+    it = load().orc_cg_laplacian(lx, ly, lz, _ptr(b), _ptr(u), float(rtol), int(maxit))
+    if it < 0:
+        raise RuntimeError(f"CG failed ({it})")
+    return u
 
 
 def estimate(O: np.ndarray, bin_size: int):

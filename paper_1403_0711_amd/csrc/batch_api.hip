@@ -5,7 +5,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.hpp"
@@ -37,6 +41,11 @@ struct lattice_batch {
     int64_t bin_size = 0;
     int64_t t = 0;
     bool charges_dirty = true;
+    // the half-sweep form per chain: the library's rule (false) or the
+    // autotuner's per-box choice (ring[k])
+    bool tuned = false;
+    std::vector<uint8_t> ring;
+    int force_ring = -1;  // the autotuner's timing runs: every chain the ring (1) or memory (0)
 };
 
 static int check_batch(const lattice_batch* b) {
@@ -212,11 +221,22 @@ int batch_run(lattice_batch_t* B, int64_t n_therm, int64_t n_meas, int64_t bin_s
         if (int r = upload_charges(B)) return r;
     int64_t need = 1;
     for (int64_t m : B->n_meas) need = std::max(need, (m + n_meas + bin_size - 1) / bin_size);
+    // bin slots are indexed in 64 bits; the bin table (2 doubles per slot)
+    // must stay addressable
+    if ((double)B->n * (double)std::max<int64_t>({need, 2 * B->bins_per_chain, 16}) * 16.0 >= 9.0e18)
+        return set_error(LAT_ERR_ARG, "the sample bins of this batch would exceed the addressable range");
     if (int r = ensure_batch_bins(B, need)) return r;
     B->bin_size = bin_size;
+    // the half-sweep form: without tuning, the LDS ring for every chain it
+    // applies to when the fields fill the 256 MiB last-level cache (the
+    // chains then wait on memory, where the ring is faster)
+    const bool big = B->field_bytes >= ((size_t)256 << 20);
     for (int64_t k = 0; k < B->n; ++k) {
-        B->desc[k].bin_off = (uint32_t)(k * B->bins_per_chain);
-        B->desc[k].meas0 = (uint32_t)B->n_meas[k];
+        BatchChainDesc& d = B->desc[k];
+        d.bin_off = (uint64_t)k * (uint64_t)B->bins_per_chain;
+        d.meas0 = (uint32_t)B->n_meas[k];
+        const bool ring = B->force_ring >= 0 ? B->force_ring != 0 : B->tuned ? B->ring[k] != 0 : big;
+        d.ring = ring && batch_ring_applies(d.lh, d.ly, d.vh) ? 1u : 0u;
     }
     hipError_t e = hipStreamSynchronize(B->stream);
     if (e == hipSuccess)
@@ -240,14 +260,96 @@ int batch_run(lattice_batch_t* B, int64_t n_therm, int64_t n_meas, int64_t bin_s
     a.k0 = (uint32_t)B->seed;
     a.k1 = (uint32_t)(B->seed >> 32);
     a.storage = B->storage;
-    // fields that fill the 256 MiB last-level cache: the chains wait on memory,
-    // where the half-sweep through an LDS ring is faster
-    a.ring = B->field_bytes >= ((size_t)256 << 20);
     a.single = false;
     e = launch_batch(a, B->stream);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     B->t += n_therm + n_meas;
     for (auto& m : B->n_meas) m += n_meas;
+    return LAT_OK;
+}
+
+// Per-box choice of the batch's half-sweep form, cached for the process:
+// (device architecture, box, storage, chains of that box in the batch) ->
+// LDS ring or memory.
+using BatchTuneKey = std::tuple<std::string, int64_t, int64_t, int64_t, int, int64_t>;
+static std::mutex g_batch_tune_mu;
+static std::map<BatchTuneKey, bool> g_batch_tune_cache;
+
+// Time `reps` sweeps of a scratch batch of `count` chains of one box with
+// every chain the ring (ring = true) or memory.
+static int time_scratch_batch(lattice_batch* B, const int64_t* edge, int64_t count, bool ring, int64_t reps,
+                              float* ms) {
+    std::vector<int64_t> edges;
+    for (int64_t k = 0; k < count; ++k) edges.insert(edges.end(), edge, edge + 3);
+    lattice_batch_t* T = nullptr;
+    if (int r = batch_create(count, edges.data(), nullptr, B->storage, B->seed, B->mem.source(), B->stream, &T))
+        return r;
+    T->force_ring = ring ? 1 : 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = batch_run(T, 1, 0, 1);  // the launch's first use of the kernel and the fields
+    hipError_t e = hipSuccess;
+    if (rc == LAT_OK) e = hipEventCreate(&e0);
+    if (rc == LAT_OK && e == hipSuccess) e = hipEventCreate(&e1);
+    if (rc == LAT_OK && e == hipSuccess) e = hipEventRecord(e0, B->stream);
+    if (rc == LAT_OK && e == hipSuccess) rc = batch_run(T, reps, 0, 1);
+    if (rc == LAT_OK && e == hipSuccess) e = hipEventRecord(e1, B->stream);
+    if (rc == LAT_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    if (rc == LAT_OK && e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    batch_destroy(T);
+    if (rc != LAT_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "batch autotuning");
+    return LAT_OK;
+}
+
+int batch_autotune(lattice_batch_t* B, int64_t reps, int64_t* n_ring) {
+    TraceRange tr("batch_autotune");
+    if (int r = check_batch(B)) return r;
+    if (reps < 1 || reps > 1000) return set_error(LAT_ERR_ARG, "reps must be in [1, 1000]");
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t pe = hipGetDevice(&dev);
+    if (pe == hipSuccess) pe = hipGetDeviceProperties(&prop, dev);
+    if (pe != hipSuccess) return hip_fail(pe, "device properties");
+    std::string arch(prop.gcnArchName);
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    // the boxes the ring applies to, with their number of chains
+    std::map<std::tuple<int64_t, int64_t, int64_t>, int64_t> count;
+    for (int64_t k = 0; k < B->n; ++k) {
+        const BatchChainDesc& d = B->desc[k];
+        if (batch_ring_applies(d.lh, d.ly, d.vh)) ++count[{B->edges[3 * k], B->edges[3 * k + 1], B->edges[3 * k + 2]}];
+    }
+    std::map<std::tuple<int64_t, int64_t, int64_t>, bool> choice;
+    for (const auto& [shape, cnt] : count) {
+        const BatchTuneKey key(arch, std::get<0>(shape), std::get<1>(shape), std::get<2>(shape), B->storage, cnt);
+        {
+            std::lock_guard<std::mutex> g(g_batch_tune_mu);
+            auto it = g_batch_tune_cache.find(key);
+            if (it != g_batch_tune_cache.end()) {
+                choice[shape] = it->second;
+                continue;
+            }
+        }
+        const int64_t edge[3] = {std::get<0>(shape), std::get<1>(shape), std::get<2>(shape)};
+        float ms_ring = 0.f, ms_mem = 0.f;
+        if (int r = time_scratch_batch(B, edge, cnt, true, reps, &ms_ring)) return r;
+        if (int r = time_scratch_batch(B, edge, cnt, false, reps, &ms_mem)) return r;
+        const bool ring = ms_ring < 0.97f * ms_mem;  // the ring only where it is clearly faster
+        choice[shape] = ring;
+        std::lock_guard<std::mutex> g(g_batch_tune_mu);
+        g_batch_tune_cache[key] = ring;
+    }
+    B->ring.assign((size_t)B->n, 0);
+    int64_t nr = 0;
+    for (int64_t k = 0; k < B->n; ++k) {
+        auto it = choice.find({B->edges[3 * k], B->edges[3 * k + 1], B->edges[3 * k + 2]});
+        B->ring[k] = it != choice.end() && it->second ? 1 : 0;
+        nr += B->ring[k];
+    }
+    B->tuned = true;
+    if (n_ring) *n_ring = nr;
     return LAT_OK;
 }
 

@@ -23,6 +23,8 @@ constexpr int kBatchThreads = 1024;
 // allow one 1024-thread workgroup per CU in any case.
 constexpr uint32_t kRingQuads = 8192;
 constexpr uint32_t kRingMaxPlaneQuads = (kRingQuads - 2u * kBatchThreads) / 2u;
+static_assert(kRingMaxPlaneQuads == kBatchRingMaxPlaneQuads && 4u * kBatchThreads == 4096u,
+              "the host's test of which chains the ring takes");
 
 // One raw quad (4 elements) of a storage format
 template <class St>
@@ -248,7 +250,7 @@ __device__ __forceinline__ void run_chain(typename St::T* fields, const BatchCha
             block_sum2<kBatchThreads>(x, y);  // ends with a barrier
             if (threadIdx.x == 0) {
                 const uint32_t m = (s - n_therm + 1) / every - 1;  // sample index within this run
-                const uint32_t b = d.bin_off + (d.meas0 + m) / bin_size;
+                const uint64_t b = d.bin_off + (d.meas0 + m) / bin_size;
                 const double O = x * x - y;
                 double sum = bins[2 * b], comp = bins[2 * b + 1];
                 const double yk = O - comp;
@@ -274,10 +276,10 @@ __global__ __launch_bounds__(kBatchThreads) void batch_chains(typename St::T* __
                                                               const double* __restrict__ S, double* bins,
                                                               uint32_t t0, uint32_t n_therm, uint32_t n_meas,
                                                               uint32_t every, uint32_t bin_size, uint32_t k0,
-                                                              uint32_t k1, uint32_t use_ring) {
+                                                              uint32_t k1) {
     const BatchChainDesc d = desc[order[blockIdx.x]];
     run_chain<St>(fields, d, site, Q, S, bins, t0, n_therm, n_meas, every, bin_size, k0, k1, nullptr,
-                  use_ring != 0);
+                  d.ring != 0);
 }
 
 // One lattice small enough for one workgroup: the whole run in one launch.
@@ -302,7 +304,7 @@ static hipError_t launch_batch_t(const BatchArgs& a, hipStream_t stream) {
     } else {
         hipLaunchKernelGGL(batch_chains<St>, dim3(a.n_chains), dim3(kBatchThreads), 0, stream,
                            static_cast<typename St::T*>(a.field), a.desc, a.order, a.site, a.Q, a.S, a.bins, a.t0,
-                           a.n_therm, a.n_meas, a.every, a.bin_size, a.k0, a.k1, a.ring ? 1u : 0u);
+                           a.n_therm, a.n_meas, a.every, a.bin_size, a.k0, a.k1);
     }
     return hipGetLastError();
 }

@@ -212,12 +212,20 @@ hipError_t launch_measure_offlattice(const OffLatticeArgs& a, hipStream_t stream
 // Batched chains: one workgroup owns one chain and runs all its sweeps.
 struct BatchChainDesc {
     uint64_t field_off;   // element offset of the chain's field (2 * vh elements)
+    uint64_t bin_off;     // first bin slot of this chain (2 doubles each)
     uint32_t lh, ly, lz, vh;
     uint32_t chain_id;
     uint32_t site_off, n_sites;  // range in the concatenated charge arrays
-    uint32_t bin_off;            // first bin slot of this chain (2 doubles each)
     uint32_t meas0;              // samples this chain already holds
+    uint32_t ring;               // 1: the LDS-ring half-sweep where the chain's planes allow it
 };
+// A chain the LDS-ring half-sweep can take (lh % 4 == 0, at most
+// kBatchRingMaxPlaneQuads quads per plane) and that does not already keep its
+// whole other colour in LDS (more than 1024 quads).
+constexpr uint32_t kBatchRingMaxPlaneQuads = 3072;
+inline bool batch_ring_applies(uint32_t lh, uint32_t ly, uint32_t vh) {
+    return lh % 4u == 0 && (lh / 4u) * ly <= kBatchRingMaxPlaneQuads && vh > 4096u;
+}
 struct BatchArgs {
     void* field;
     const BatchChainDesc* desc;  // device table (batch) ...
@@ -231,7 +239,6 @@ struct BatchArgs {
     uint32_t n_therm, n_meas, every, bin_size;
     uint32_t k0, k1;
     int storage;
-    bool ring;                   // batch: the LDS-ring half-sweep where a chain's planes allow it
     bool single;                 // one lattice: descriptor passed by value
     BatchChainDesc single_desc;
     double* last_xy;             // single: X, Y of the last sample (or null)

@@ -41,6 +41,7 @@ class DeviceAllocator {
     }
     void* alloc(size_t bytes);
     void release(void* p);
+    const lat_allocator* source() const { return custom_ ? &a_ : nullptr; }  // the caller's provider, if any
 
   private:
     lat_allocator a_{};

@@ -95,6 +95,7 @@ def load_library() -> ctypes.CDLL:
         "batch_create": (_int, [_i64, _p, _p, _int, _u64, _p, _p, _p]),
         "batch_set_charges": (_int, [_p, _i64, _i64, _p, _p]),
         "batch_run": (_int, [_p, _i64, _i64, _i64]),
+        "batch_autotune": (_int, [_p, _i64, _pi64]),
         "batch_energy_estimate": (_int, [_p, _i64, _pd, _pd, _pi64, _pi64]),
         "batch_get_field": (_int, [_p, _i64, _p]),
         "batch_destroy": (None, [_p]),
@@ -432,6 +433,13 @@ class Batch:
 
     def run(self, n_therm: int, n_meas: int, bin_size: int = 100):
         self._call(self.lib.batch_run, int(n_therm), int(n_meas), int(bin_size))
+
+    def autotune(self, reps: int = 5) -> int:
+        """Choose the LDS-ring or memory half-sweep per box by timing scratch
+        batches; returns the number of chains that will use the ring."""
+        n = ctypes.c_int64()
+        self._call(self.lib.batch_autotune, int(reps), ctypes.byref(n))
+        return n.value
 
     def energy_estimate(self, chain: int):
         m, s = ctypes.c_double(), ctypes.c_double()

@@ -114,6 +114,46 @@ def test_batch_ring_matches_quad_kernel(lat_mod, storage, filled):
         assert abs(mb - ms) <= 1e-9 * max(1.0, abs(ms)), (storage, RING_EDGES[k])
 
 
+def test_batch_autotuned_matches_quad_kernel(lat_mod):
+    """A batch whose half-sweep form the autotuner chose per box (the boxes
+    on both sides of the ring's plane limit, several chains of some) gives
+    the single lattices' fields and samples bit for bit, as the untuned batch
+    does; a second autotune of the same batch reuses the cached choices."""
+    print("[gpu] autotuned batch vs quad kernel", flush=True)
+    seed = 4242
+    edges = RING_EDGES + [(64, 64, 64)] * 4 + [(48, 40, 30)] * 3
+    ids = list(range(20, 20 + len(edges)))
+    tuned = lat_mod.Batch(edges, "fp32", seed=seed, chain_ids=ids)
+    plain = lat_mod.Batch(edges, "fp32", seed=seed, chain_ids=ids)
+    n_ring = tuned.autotune(2)
+    assert 0 <= n_ring <= len(edges)
+    assert tuned.autotune(2) == n_ring
+    singles = []
+    for k, e in enumerate(edges):
+        xyz, q = _charges(e, 8, 300 + k)
+        tuned.set_charges(k, xyz, q)
+        plain.set_charges(k, xyz, q)
+        if k < len(RING_EDGES):
+            s = lat_mod.Lattice(e, "fp32", seed=seed, chain_id=ids[k])
+            s.set_variant("quad")
+            s.set_charges(xyz, q)
+            singles.append(s)
+    for b in (tuned, plain):
+        b.run(2, 6, 3)
+    for s in singles:
+        s.thermalise(2)
+        s.sweep_and_measure(6, 1, 3)
+    for k in range(len(edges)):
+        assert np.array_equal(tuned.get_field(k), plain.get_field(k)), edges[k]
+        assert tuned.energy_estimate(k)[0] == plain.energy_estimate(k)[0]
+    for k, s in enumerate(singles):
+        assert np.array_equal(tuned.get_field(k), s.get_field()), edges[k]
+        assert abs(tuned.energy_estimate(k)[0] - s.energy_estimate()[0]) <= 1e-9 * max(
+            1.0, abs(s.energy_estimate()[0]))
+    with pytest.raises(lat_mod.LatticeError):
+        tuned.autotune(0)
+
+
 def test_batch_chain_matches_oracle(lat_mod):
     print("[gpu] batch chain vs oracle", flush=True)
     seed = 99

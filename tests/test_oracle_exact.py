@@ -8,6 +8,7 @@ import os
 import numpy as np
 import pytest
 
+import oracle
 from oracle import exact as ex
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -172,3 +173,39 @@ def test_energy_pair_sum_definition():
     ref = 2 * (0.5 * -2.0 * G[i0, i0] + 0.5 * 1.5 * G[i0, i2] + -2.0 * 1.5 * G[i0, i2])
     assert abs(ex.energy_dense(shape, xyz, q, G) - ref) < 1e-15
     assert abs(ex.energy_dst(shape, xyz, q) - ref) < 1e-12
+
+
+def test_c2_subset_energy_by_cg_per_charge():
+    """The 256^3 exact reference (DST-I for q^T G q, heat-kernel quadrature
+    for the diagonal) against FP64 conjugate gradients per charge, with no
+    transform: a 3-charge subset of the first 1,024 charges of the 65,536-
+    charge workload, chosen as the closest pair and the charge nearest its
+    midpoint so that the pair terms are not lost next to the diagonal.  Two
+    CG columns give every pair of the three (about 50 s on 8 cores)."""
+    from paper_1403_0711_amd import workloads
+
+    c = workloads.large_neutral()
+    x = c.xyz[:1024].astype(np.int64)
+    q = c.q[:1024]
+    d2 = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, np.iinfo(np.int64).max)
+    a, b = np.unravel_index(np.argmin(d2), d2.shape)
+    dm = ((x - (x[a] + x[b]) / 2.0) ** 2).sum(-1)
+    dm[[a, b]] = np.inf
+    k = int(np.argmin(dm))
+    ua = oracle.green_column_cg(c.shape, x[a])
+    ub = oracle.green_column_cg(c.shape, x[b])
+
+    def g(u, s):
+        return u[s[2], s[1], s[0]]
+
+    Gab, Gac, Gbc = g(ua, x[b]), g(ua, x[k]), g(ub, x[k])
+    assert abs(g(ub, x[a]) - Gab) <= 1e-12 * Gab  # G is symmetric
+    E_cg = 2.0 * (q[a] * q[b] * Gab + q[a] * q[k] * Gac + q[b] * q[k] * Gbc)
+    sel = [a, b, k]
+    E_dst = ex.energy_dst(c.shape, x[sel], q[sel])
+    assert abs(E_cg - E_dst) <= 1e-9 * abs(E_dst), (E_cg, E_dst)
+    # the columns' diagonal entries against the heat-kernel quadrature
+    h = ex.green_diag_heat(c.shape, x[[a, b]])
+    assert abs(g(ua, x[a]) - h[0]) <= 1e-12 * h[0]
+    assert abs(g(ub, x[b]) - h[1]) <= 1e-12 * h[1]
