@@ -89,7 +89,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--figures-sweeps", type=int, default=200000,
                    help="measured sweeps of the figures comparison (128^3, 132 charge sets)")
-    p.add_argument("--coupled-sweeps", type=int, default=10000,
+    p.add_argument("--coupled-sweeps", type=int, default=100000,
                    help="sweeps per storage format of the coupled precision comparison")
     return p.parse_args()
 

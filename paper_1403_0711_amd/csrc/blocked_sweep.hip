@@ -242,8 +242,9 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
             const uint32_t r = ch / rbc, k = ch - r * rbc;
             const int yr = (int)y0 - 2 + (int)r;
             const bool in = k >= 1u && k + 1u < rbc && yr >= 0 && yr < (int)ly;
-            off[i] = ch >= chunks ? 0xFFFFFFFFu : in ? ((uint32_t)yr * lh) * kEsz + (k - 1u) * 16u : kNoLoad;
+            off[i] = ch >= chunks ? kNoLoad : in ? ((uint32_t)yr * lh) * kEsz + (k - 1u) * 16u : kNoLoad;
         }
+        const bool last_in = 64u * (ni - 1u) + lane < chunks;  // this lane's chunk of the last instruction
         auto loads = [&](uint32_t l) -> bool {
             const int o = (int)z0 - 2 + (int)l;
             return l <= n + 3u && o >= 0 && o < (int)lz;
@@ -259,11 +260,19 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
                 return;
             }
             const uint32_t soff = (uint32_t)o * plane_b;
+            // every lane of instructions 0 .. ni-2 has a chunk of the slot;
+            // only the last instruction's lanes past the slot are masked off
+            // (one lane mask for the whole plane).  The tests of i against
+            // ni are made afresh in each call (an opaque copy of ni): held
+            // across the step loop they took 48 scalar registers, spilled
+            uint32_t nl = ni;
+            asm volatile("" : "+s"(nl));
 #pragma unroll
             for (int i = 0; i < kBlkNI; ++i) {
-                if ((uint32_t)i < ni) {
-                    if (off[i] != 0xFFFFFFFFu)
-                        lds_load_b128(src, (lds_ptr_t)(dst + 1024u * (uint32_t)i), off[i], soff);
+                if ((uint32_t)i + 1u < nl) {
+                    lds_load_b128(src, (lds_ptr_t)(dst + 1024u * (uint32_t)i), off[i], soff);
+                } else if ((uint32_t)i + 1u == nl) {
+                    if (last_in) lds_load_b128(src, (lds_ptr_t)(dst + 1024u * (uint32_t)i), off[i], soff);
                 } else {
                     lds_load_b128(src, (lds_ptr_t)sink, kNoLoad, 0u);  // padding: zeros into the sink
                 }

@@ -32,14 +32,11 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
-    // the round keys are formed here by scalar adds: without this the
-    // compiler keeps all twenty of them in scalar registers for the whole
-    // kernel, which pushes other wave-uniform values out to vector lanes
-    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        // one 32x32->64 product per word: lowers to a single v_mad_u64_u32
-        // (full rate on gfx950) instead of separate low and high multiplies
+        // one 32x32->64 product per word: a single v_mad_u64_u32 (issued at
+        // the integer rate, half the FP32 FMA rate on gfx950) instead of
+        // separate low and high multiplies
         const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
         const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);

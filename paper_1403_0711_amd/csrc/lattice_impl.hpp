@@ -203,9 +203,10 @@ struct lattice {
     // The library's (rows per tile, planes per workgroup) for the blocked
     // sweep: the pair with the highest estimated rate, counting per step the
     // tasks of the busiest SIMD (task t runs on SIMD t % 4), per slab three
-    // steps beyond its planes, and per launch whole rounds of resident
-    // workgroups over the device's CUs (one or two per CU, by LDS).  (0, 0):
-    // the kernel cannot run this box.
+    // steps beyond its planes, and per launch whole rounds of workgroups over
+    // the device's CUs.  One workgroup per CU: its 13 waves at 84-116 VGPRs
+    // leave no SIMD room for the waves of a second.  (0, 0): the kernel
+    // cannot run this box.
     std::pair<uint32_t, uint32_t> blocked_choice() const {
         static const uint32_t kSlabs[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
         double best = 0.0;
@@ -214,7 +215,7 @@ struct lattice {
         for (uint32_t k = 1; k <= 16; ++k) {
             BlockedShape sh;
             if (!blocked_geometry(lh, (uint32_t)esz, k, 4u, &sh)) continue;
-            const double per_cu = sh.lds <= 80u * 1024u ? 2.0 : 1.0;
+            const double per_cu = 1.0;
             for (uint32_t i = 0; i < ns; ++i) {
                 const uint32_t zc = slab ? slab : (i < ns - 1u ? kSlabs[i] : (uint32_t)lz);
                 if (zc > (uint32_t)lz) continue;
