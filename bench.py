@@ -331,8 +331,12 @@ def precision_coupled(sweeps, torch, lattice, workloads, therm=40000):
     chain's sample from the FP32 chain's measures its bias with an error far
     below the chains' own statistical error; each format also reports its
     mean against the exact E_lat with the binning curve's error (a lower
-    bound: `sweeps` is about 2 autocorrelation times here).  With equal
-    statistics, time to a given error scales as the cost per sweep.  Each
+    bound when `sweeps` is only a few autocorrelation times, about 1300
+    sweeps here).  Storage rounding shrinks stored values slightly toward
+    zero (round-to-nearest-even cells are asymmetric at each power of two),
+    a weak mass term whose effect on E_N grows as u^2 L^2: the BF16 chain's
+    difference is several percent at 384^3, FP16's 64 times smaller.  With
+    equal statistics, time to a given error scales as the cost per sweep.  Each
     format runs the sweep configuration the library's autotuner picks for it
     on this machine (kernel choice does not change the chain: every kernel
     computes the same update)."""
