@@ -6,8 +6,13 @@ Chains with FP32, BF16 and FP16 storage driven by the same random numbers
 to the storage format and the heat-bath map contracts, so the fields differ
 by a few storage ulps at every sweep.  The per-sweep samples O = X^2 - Y of a
 16-bit chain then differ from the FP32 chain's by far less than the samples'
-own spread, and the mean difference (the bias of the 16-bit estimate) is
-zero within its error.  This is the coupled-chain check of the reduced
+own spread.  Storage rounding does bias E_N low: round-to-nearest-even
+shrinks values slightly toward zero (its cells are asymmetric at each power
+of two), a weak mass term whose relative effect grows as u^2 L^2 (u the
+format's unit roundoff).  On this 64^3 box over 3000 sweeps that bias is
+below the run's resolution, so the mean difference is zero within its
+error; long runs on larger boxes resolve it (BF16 about -0.7% of E_N at
+128^3, FP16 64 times less).  This is the coupled-chain check of the reduced
 precision forms on a same-sign (Gaussian-blob) charge set, whose slow modes
 make independent-run comparisons impractical."""
 
