@@ -27,9 +27,12 @@ import os
 import numpy as np
 
 __all__ = ["OracleChain", "load", "philox4x32_10", "inv_norm_cdf", "round_storage",
-           "site_uniform", "noise_grid", "estimate", "gather_offlattice", "force_sample", "STORAGE"]
+           "site_uniform", "site_word", "noise_grid", "estimate", "gather_offlattice", "force_sample", "STORAGE"]
 
-STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
+# storage formats: 16-bit values rounded to nearest even (bf16, fp16) or
+# stochastically with the 8 low bits of each site's Philox word (bf16sr, fp16sr)
+STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16sr": 3, "fp16sr": 4}
+_GRID_OF = {0: 0, 1: 1, 2: 2, 3: 1, 4: 2}  # the round-to-nearest format of the same grid
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
@@ -62,6 +65,10 @@ def load() -> ctypes.CDLL:
     lib.orc_round_storage.restype = _d
     lib.orc_site_uniform.argtypes = [_i64, _i64, _i64, _i64, _i64, _u64, _u32, _u32]
     lib.orc_site_uniform.restype = _d
+    lib.orc_site_word.argtypes = [_i64, _i64, _i64, _i64, _i64, _u64, _u32, _u32]
+    lib.orc_site_word.restype = _u32
+    lib.orc_round_storage_sr.argtypes = [_d, ctypes.c_int, _u32]
+    lib.orc_round_storage_sr.restype = _d
     lib.orc_site_value.argtypes = [_p, _i64, _i64, _i64, _i64, _i64, _i64, _u64, _u32, _u32]
     lib.orc_site_value.restype = _d
     lib.orc_halfsweep.argtypes = [_p, _i64, _i64, _i64, ctypes.c_int, _u64, _u32, _u32]
@@ -105,14 +112,26 @@ def inv_norm_cdf(r: float) -> float:
     return load().orc_inv_norm_cdf(float(r))
 
 
-def round_storage(v: float, storage: str) -> float:
-    """Round-to-nearest-even of an FP64 value to the storage format."""
-    return load().orc_round_storage(float(v), STORAGE[storage])
+def round_storage(v: float, storage: str, u8=None) -> float:
+    """An FP64 value rounded to the storage format: to nearest even, or for
+    the stochastic formats with random bits ``u8`` (0..255; without them the
+    nearest-even rounding of the same grid, which field uploads use)."""
+    code = STORAGE[storage]
+    if code >= 3 and u8 is not None:
+        return load().orc_round_storage_sr(float(v), code, int(u8) & 0xFF)
+    return load().orc_round_storage(float(v), _GRID_OF[code])
 
 
 def site_uniform(shape, x, y, z, seed, chain, h) -> float:
     lx, ly, _ = shape
     return load().orc_site_uniform(lx, ly, x, y, z, seed, chain, h)
+
+
+def site_word(shape, x, y, z, seed, chain, h) -> int:
+    """The 32-bit Philox word of a site in half-sweep h (its uniform is
+    word >> 8, its stochastic-rounding bits word & 0xFF)."""
+    lx, ly, _ = shape
+    return int(load().orc_site_word(lx, ly, x, y, z, seed, chain, h))
 
 
 class OracleChain:

@@ -31,8 +31,10 @@
  * word (j & 3) of Philox(counter = (j >> 2, h, chain, 0), key = (lo32(seed),
  * hi32(seed))).  Uniform: k = word >> 8, r = (k + 1/2) * 2^-24.
  *
- * Arithmetic is FP64; each stored value is rounded (round-to-nearest-even)
- * to the storage format: 0 = FP32, 1 = BF16, 2 = FP16.
+ * Arithmetic is FP64; each stored value is rounded to the storage format:
+ * 0 = FP32, 1 = BF16, 2 = FP16 (round-to-nearest-even), 3 = BF16, 4 = FP16
+ * (stochastic rounding with the 8 low bits of the site's Philox word, which
+ * the uniform does not use).
  */
 #include <math.h>
 #include <stdint.h>
@@ -135,6 +137,35 @@ double orc_round_storage(double v, int storage) {
     }
 }
 
+/* Stochastic rounding to p significant bits (smallest normal exponent emin,
+ * the subnormal grid below it).  lo is |v| rounded toward zero to the grid,
+ * ulp the grid spacing there and f = (|v| - lo) / ulp in [0, 1).  The
+ * magnitude becomes lo + ulp when f >= (255.5 - u8) / 256, else lo, with u8
+ * the 8 random bits (0 .. 255): over the 256 values of u8 it rounds up
+ * floor(256 f + 1/2) times, so the mean result is |v| up to ulp / 512 (an
+ * unbiased rounding quantised to 1/256 of the spacing).  The sign is kept. */
+static double orc_round_sig_sr(double v, int p, int emin, uint32_t u8) {
+    if (v == 0.0 || !isfinite(v)) return v;
+    const double a = fabs(v);
+    int e;
+    (void)frexp(a, &e);
+    int lead = e - 1;
+    if (lead < emin) lead = emin;
+    const double ulp = ldexp(1.0, lead - p + 1);
+    const double lo = floor(a / ulp) * ulp;  /* exact: division by a power of two */
+    const double f = (a - lo) / ulp;          /* exact */
+    const double m = f >= (255.5 - (double)(u8 & 0xFFu)) / 256.0 ? lo + ulp : lo;
+    return v < 0.0 ? -m : m;
+}
+
+double orc_round_storage_sr(double v, int storage, uint32_t u8) {
+    switch (storage) {
+        case 3: return orc_round_sig_sr(v, 8, -126, u8);  /* BF16 */
+        case 4: return orc_round_sig_sr(v, 11, -14, u8);  /* FP16 */
+        default: return NAN;
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Heat bath                                                            */
 /* ------------------------------------------------------------------ */
@@ -144,16 +175,22 @@ static inline double orc_at(const double *phi, int64_t lx, int64_t ly, int64_t l
     return phi[x + lx * (y + ly * z)];
 }
 
-/* Uniform r in (0,1) used by site (x,y,z) in half-sweep h. */
-double orc_site_uniform(int64_t lx, int64_t ly, int64_t x, int64_t y, int64_t z,
-                        uint64_t seed, uint32_t chain, uint32_t h) {
+/* The Philox word of site (x,y,z) in half-sweep h. */
+uint32_t orc_site_word(int64_t lx, int64_t ly, int64_t x, int64_t y, int64_t z,
+                       uint64_t seed, uint32_t chain, uint32_t h) {
     int64_t i = x + lx * (y + ly * z);
     int64_t j = i >> 1;
     uint32_t ctr[4] = {(uint32_t)(j >> 2), h, chain, 0u};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t w[4];
     orc_philox4x32_10(ctr, key, w);
-    uint32_t k = w[j & 3] >> 8;
+    return w[j & 3];
+}
+
+/* Uniform r in (0,1) used by site (x,y,z) in half-sweep h. */
+double orc_site_uniform(int64_t lx, int64_t ly, int64_t x, int64_t y, int64_t z,
+                        uint64_t seed, uint32_t chain, uint32_t h) {
+    uint32_t k = orc_site_word(lx, ly, x, y, z, seed, chain, h) >> 8;
     return ((double)k + 0.5) * 0x1p-24;
 }
 
@@ -177,7 +214,9 @@ void orc_halfsweep(double *phi, int64_t lx, int64_t ly, int64_t lz, int storage,
             for (int64_t x = 0; x < lx; ++x) {
                 if ((int)((x + y + z) & 1) != c) continue;
                 double v = orc_site_value(phi, lx, ly, lz, x, y, z, seed, chain, h);
-                phi[x + lx * (y + ly * z)] = orc_round_storage(v, storage);
+                phi[x + lx * (y + ly * z)] =
+                    storage >= 3 ? orc_round_storage_sr(v, storage, orc_site_word(lx, ly, x, y, z, seed, chain, h) & 0xFFu)
+                                 : orc_round_storage(v, storage);
             }
 }
 
