@@ -66,7 +66,7 @@ def parse():
     p.add_argument("--workload", default="largest_subdomain_768",
                    choices=["largest_subdomain_768", "large_neutral_256", "gaussian_blob_384",
                             "small_neutral_16"])
-    p.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
+    p.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16", "bf16sr", "fp16sr"])
     p.add_argument("--variant", default="auto",
                    choices=["auto", "tuned", "quad", "generic", "zslab", "stream", "fused", "resident", "blocked"],
                    help="auto: the library's default kernel and tuning for the box; "
@@ -325,9 +325,9 @@ def precision_coupled(sweeps, torch, lattice, workloads, therm=40000):
     """Reduced-precision storage at equal accuracy, on the 384^3 Gaussian blob
     (2e5 charges of +1).  One FP32 chain is thermalised (`therm` sweeps from
     phi = 0, about 5 e-folds of the slowest mode's variance); its field is the
-    common start of an FP32, a BF16 and an FP16 chain on one Philox stream
-    (same seed and chain id; the 16-bit copies round it), one sample per
-    sweep.  The chains move together, so the per-sweep difference of a 16-bit
+    common start of an FP32 chain and of BF16 and FP16 chains, each rounded
+    to nearest even and stochastically, on one Philox stream (same seed and
+    chain id; the 16-bit copies round it), one sample per sweep.  The chains move together, so the per-sweep difference of a 16-bit
     chain's sample from the FP32 chain's measures its bias with an error far
     below the chains' own statistical error; each format also reports its
     mean against the exact E_lat with the binning curve's error (a lower
@@ -335,7 +335,9 @@ def precision_coupled(sweeps, torch, lattice, workloads, therm=40000):
     sweeps here).  Storage rounding shrinks stored values slightly toward
     zero (round-to-nearest-even cells are asymmetric at each power of two),
     a weak mass term whose effect on E_N grows as u^2 L^2: the BF16 chain's
-    difference is several percent at 384^3, FP16's 64 times smaller.  With
+    difference is several percent at 384^3, FP16's 64 times smaller.
+    Stochastic rounding (the low byte of each site's Philox word) has no
+    such shrinkage, so its chains' differences are zero within error.  With
     equal statistics, time to a given error scales as the cost per sweep.  Each
     format runs the sweep configuration the library's autotuner picks for it
     on this machine (kernel choice does not change the chain: every kernel
@@ -349,7 +351,8 @@ def precision_coupled(sweeps, torch, lattice, workloads, therm=40000):
     lat.thermalise(therm)
     phi0 = lat.get_field()
     lat.close()
-    for st in ("fp32", "bf16", "fp16"):
+    formats = ("fp32", "bf16", "fp16", "bf16sr", "fp16sr")
+    for st in formats:
         lat = lattice.Lattice(cs.shape, st, seed=spec["philox_seed"])
         lat.set_field(phi0)
         lat.set_charges(cs.xyz, cs.q)
@@ -371,7 +374,7 @@ def precision_coupled(sweeps, torch, lattice, workloads, therm=40000):
         lat.close()
     del phi0
     out["sd_O"] = float(series["fp32"].std())
-    for st in ("bf16", "fp16"):
+    for st in formats[1:]:
         # the difference of two coupled chains drifts in the slowest modes
         # (rounding errors accumulate there over their relaxation time, about
         # 1e4 sweeps on this machine): its error is the binning curve's largest,
@@ -762,7 +765,7 @@ def main():
             out["copy_same_bytes"] = copy_reference(bytes_per_launch // 2, torch)
             out["copy_same_bytes"]["kernel_vs_copy"] = out["copy_same_bytes"]["ms"] / launch_ms
             if args.storage == "fp32":
-                for st in ("fp16", "bf16"):
+                for st in ("fp16", "bf16", "fp16sr", "bf16sr"):
                     r = fp16_comparison(cs, seed, min(args.steps, 200), bin_size, torch, lattice,
                                         args.variant == "tuned", storage=st)
                     r["speedup_vs_fp32"] = ms_per_step / r["ms_per_step"]

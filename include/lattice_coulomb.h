@@ -29,7 +29,8 @@
  *     key = (lo32(seed), hi32(seed))); k = word >> 8; r = (k + 1/2) 2^-24.
  *   - Update: phi = (1/6) sum of the 6 neighbours + erfinv(2r - 1)/sqrt(3)
  *     (= Eq. phi's -erfc^{-1}(2r)/sqrt(3)), in FP32 arithmetic, stored
- *     rounded to nearest even in the storage format.
+ *     rounded in the storage format (to nearest even, or stochastically
+ *     with the word's low 8 bits: LAT_BF16_SR, LAT_FP16_SR).
  *   - A measured sweep adds O = X^2 - Y, X = sum_i q_i phi(n_i),
  *     Y = sum_i q_i^2 phi(n_i)^2 (FP64), into bins of bin_size consecutive
  *     samples with compensated (Kahan) FP64 sums.
@@ -74,7 +75,20 @@ enum {
     LAT_ERR_DEVICE = 4  /* a HIP call failed                                   */
 };
 
-enum { LAT_FP32 = 0, LAT_BF16 = 1, LAT_FP16 = 2 }; /* field storage format */
+/* Field storage format.  Arithmetic is FP32 in every format; an updated
+ * value is stored rounded to nearest even (FP32, BF16, FP16) or, in the SR
+ * formats, stochastically rounded to BF16 or FP16 with the 8 low bits u8 of
+ * the site's Philox word (which the uniform does not use): with f the
+ * value's distance past the grid point below its magnitude in grid
+ * spacings, the magnitude goes up to the next grid point when
+ * 256 f + u8 >= 255.5.  Over the 256 values of u8 the mean stored value is
+ * the FP32 value to 1/512 of a spacing.  Rounding to nearest even instead
+ * shrinks values toward zero on average (at each power of two its cell
+ * reaches half the smaller spacing below and half the larger one above),
+ * a weak mass term that lowers E_N on large boxes.  An SR format's arrays
+ * are those of the round-to-nearest format of the same width (field
+ * uploads round to nearest even). */
+enum { LAT_FP32 = 0, LAT_BF16 = 1, LAT_FP16 = 2, LAT_BF16_SR = 3, LAT_FP16_SR = 4 };
 
 /* Sweep kernel selection for lattice_set_variant. */
 enum {
@@ -99,7 +113,7 @@ enum {
 
 /* Create a chain on an lx*ly*lz box with field phi = 0 and sweep counter 0.
  * lx must be even and >= 2, ly, lz >= 1, lx*ly*lz < 2^31.  storage is a
- * LAT_FP32/BF16/FP16 value.  seed keys Philox; chain_id is counter word 2
+ * LAT_FP32/BF16/FP16/BF16_SR/FP16_SR value.  seed keys Philox; chain_id is counter word 2
  * (independent chains of one seed use distinct chain_ids).  hip_stream is a
  * hipStream_t (NULL = null stream), borrowed, never destroyed.
  * Paper: the lattice L^3 and spacing a = 1 of the discretisation (Eq.

@@ -131,7 +131,7 @@ int batch_create(int64_t n_chains, const int64_t* edges, const uint32_t* chain_i
     *out = nullptr;
     if (n_chains < 1 || n_chains > (1 << 20)) return set_error(LAT_ERR_ARG, "n_chains must be in [1, 2^20]");
     if (!edges) return set_error(LAT_ERR_ARG, "edges is NULL");
-    if (storage < LAT_FP32 || storage > LAT_FP16) return set_error(LAT_ERR_ARG, "unknown storage format");
+    if (storage < LAT_FP32 || storage > LAT_FP16_SR) return set_error(LAT_ERR_ARG, "unknown storage format");
     if (alloc && (!alloc->alloc || !alloc->release))
         return set_error(LAT_ERR_ARG, "allocator needs both alloc and release");
     const size_t esz = storage == LAT_FP32 ? 4 : 2;

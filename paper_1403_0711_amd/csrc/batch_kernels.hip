@@ -28,7 +28,7 @@ static_assert(kRingMaxPlaneQuads == kBatchRingMaxPlaneQuads && 4u * kBatchThread
 
 // One raw quad (4 elements) of a storage format
 template <class St>
-using RawQuad = typename std::conditional<St::kBytes == 4, uint4, u32x2>::type;
+using RawQuad = typename St::Raw;
 
 // The neighbours of quad qi (element 4 qi) read from the ring; the same
 // values and face flags as quad_load_global reads from the colour array.
@@ -39,7 +39,7 @@ __device__ __forceinline__ QuadNeighbours<St> quad_load_ring(const typename St::
     auto el = [](uint32_t k) { return (k & (kRingQuads - 1u)) << 2; };
     const uint32_t ie = p == 0 ? el(qi - 1u) + 3u : el(qi + 1u);  // the x-neighbour beyond the quad
     QuadNeighbours<St> nb;
-    if constexpr (std::is_same<St, StoreF16>::value) {
+    if constexpr (kF16Grid<St>) {
         const u32x2 zero = {0u, 0u};
         nb.cen = at<u32x2>(ring, el(qi));
         nb.ym = ym_in ? at<u32x2>(ring, el(qi - nq)) : zero;
@@ -84,8 +84,8 @@ __device__ __forceinline__ QuadNeighbours<St> quad_load_ring(const typename St::
 template <class St>
 __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const BatchChainDesc& d, uint32_t c,
                                                 uint32_t h, uint32_t k0, uint32_t k1, bool use_ring,
-                                                typename St::T* ring, bool seeded, float4& keep0,
-                                                float4& keep1) {
+                                                typename St::T* ring, bool seeded, typename St::Raw& keep0,
+                                                typename St::Raw& keep1) {
     using T = typename St::T;
     const T* other = field + (size_t)(c ^ 1u) * d.vh;
     T* own = field + (size_t)c * d.vh;
@@ -106,11 +106,12 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
             const uint32_t p = (c + y + z) & 1u;
             const QuadNeighbours<St> nb = quad_load_ring<St>(ring, t, nq, qpp, y > 0, y + 1 < ly, z > 0, z + 1 < lz,
                                                              p == 0 ? q > 0 : q + 1 < nq, p);
-            keep0 = quad_update_from<St>(nb, p, t << 2, h, d.chain_id, k0, k1);
-            St::st4(own, t << 2, keep0);
+            const QuadOut o = quad_update_from<St>(nb, p, t << 2, h, d.chain_id, k0, k1);
+            keep0 = St::pack4(o.v, o.w);
+            at<RawQuad<St>>(own, t << 2) = keep0;
         }
         __syncthreads();  // every ring read done before the ring takes this colour
-        if (t < nquads) St::st4(ring, el(t), keep0);
+        if (t < nquads) at<RawQuad<St>>(ring, el(t)) = keep0;
     } else if (use_ring && (lh & 3u) == 0 && (lh >> 2) * ly <= kRingMaxPlaneQuads) {
         using Raw = RawQuad<St>;
         const uint32_t nq = lh >> 2, qpp = nq * ly, nquads = d.vh >> 2;
@@ -143,9 +144,10 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
             const uint32_t p = (c + y + z) & 1u;
             const QuadNeighbours<St> nb = quad_load_ring<St>(ring, qi, nq, qpp, y > 0, y + 1 < ly, z > 0, z + 1 < lz,
                                                              p == 0 ? q > 0 : q + 1 < nq, p);
-            const float4 v = quad_update_from<St>(nb, p, qi << 2, h, d.chain_id, k0, k1);
+            const QuadOut o = quad_update_from<St>(nb, p, qi << 2, h, d.chain_id, k0, k1);
+            const Raw v = St::pack4(o.v, o.w);
             at<Raw>(ring, el(g)) = nxt;
-            if (qi < nquads) St::st4(own, qi << 2, v);
+            if (qi < nquads) at<Raw>(own, qi << 2) = v;
             if (base == 0) keep0 = v;
             if (base == (uint32_t)kBatchThreads) keep1 = v;
             qi += kBatchThreads;
@@ -162,8 +164,8 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
         // below 2048, stored in the ring in the storage format, as in memory
         // (the caller's barrier orders these writes before the next
         // half-sweep's reads)
-        if (t < pro) St::st4(ring, el(t), keep0);
-        if (t + (uint32_t)kBatchThreads < pro) St::st4(ring, el(t + (uint32_t)kBatchThreads), keep1);
+        if (t < pro) at<Raw>(ring, el(t)) = keep0;
+        if (t + (uint32_t)kBatchThreads < pro) at<Raw>(ring, el(t + (uint32_t)kBatchThreads)) = keep1;
     } else if ((lh & 3u) == 0) {
         const uint32_t nq = lh >> 2, nquads = d.vh >> 2;
         // the thread's quad (q, y, z), advanced kBatchThreads quads at a time
@@ -200,7 +202,10 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u)
-                if (in[u]) St::st4(own, j0[u], quad_update_from<St>(nb[u], p[u], j0[u], h, d.chain_id, k0, k1));
+                if (in[u]) {
+                    const QuadOut o = quad_update_from<St>(nb[u], p[u], j0[u], h, d.chain_id, k0, k1);
+                    St::st4(own, j0[u], o.v, o.w);
+                }
         }
     } else {
         for (uint32_t j = threadIdx.x; j < d.vh; j += kBatchThreads) {
@@ -216,7 +221,7 @@ __device__ __forceinline__ void chain_halfsweep(typename St::T* field, const Bat
             if (z + 1 < lz) s += St::ld(other, j + plane);
             const uint4 r = philox4x32_10(j >> 2, h, d.chain_id, 0u, k0, k1);
             const uint32_t w = (j & 3u) == 0 ? r.x : (j & 3u) == 1 ? r.y : (j & 3u) == 2 ? r.z : r.w;
-            St::st(own, j, fmaf(s, sixth, heatbath_noise(w)));
+            St::st(own, j, fmaf(s, sixth, heatbath_noise(w)), w);
         }
     }
 }
@@ -233,7 +238,7 @@ __device__ __forceinline__ void run_chain(typename St::T* fields, const BatchCha
     const typename St::T* cfield = field;
     __shared__ __align__(16) typename St::T ring[kRingQuads * 4];
     const uint32_t n_sweeps = n_therm + n_meas;
-    float4 keep0 = make_float4(0.f, 0.f, 0.f, 0.f), keep1 = keep0;
+    typename St::Raw keep0{}, keep1{};
     for (uint32_t s = 0; s < n_sweeps; ++s) {
         const uint32_t t = t0 + s;
         chain_halfsweep<St>(field, d, 0u, 2u * t, k0, k1, use_ring, ring, s > 0, keep0, keep1);
@@ -314,6 +319,8 @@ hipError_t launch_batch(const BatchArgs& a, hipStream_t stream) {
         case 0: return launch_batch_t<StoreF32>(a, stream);
         case 1: return launch_batch_t<StoreBF16>(a, stream);
         case 2: return launch_batch_t<StoreF16>(a, stream);
+        case 3: return launch_batch_t<StoreBF16SR>(a, stream);
+        case 4: return launch_batch_t<StoreF16SR>(a, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -81,18 +81,8 @@ __host__ __device__ constexpr uint32_t blk_stage_bytes(uint32_t cap) { return kG
 // halves of the 16-bit formats.
 template <class St>
 struct BlkTraits {
-    using Q = float4;
-    static constexpr uint32_t kEsz = 4;
-};
-template <>
-struct BlkTraits<StoreBF16> {
-    using Q = u32x2;
-    static constexpr uint32_t kEsz = 2;
-};
-template <>
-struct BlkTraits<StoreF16> {
-    using Q = u32x2;
-    static constexpr uint32_t kEsz = 2;
+    using Q = typename St::Raw;
+    static constexpr uint32_t kEsz = St::kBytes;
 };
 
 template <class St>
@@ -105,14 +95,14 @@ __device__ __forceinline__ typename BlkTraits<St>::Q blk_quad(const unsigned cha
 // heatbath_quad_f16) and the single value beyond a quad.
 template <class St>
 __device__ __forceinline__ auto blk_ld4(const unsigned char* p) {
-    if constexpr (std::is_same<St, StoreF16>::value)
+    if constexpr (kF16Grid<St>)
         return *reinterpret_cast<const u32x2*>(p);
     else
         return St::ld4(reinterpret_cast<const typename St::T*>(p), 0);
 }
 template <class St>
 __device__ __forceinline__ auto blk_ld1(const unsigned char* p) {
-    if constexpr (std::is_same<St, StoreF16>::value)
+    if constexpr (kF16Grid<St>)
         return (uint32_t) * reinterpret_cast<const uint16_t*>(p);
     else
         return St::ld(reinterpret_cast<const typename St::T*>(p), 0);
@@ -136,19 +126,11 @@ __device__ __forceinline__ QuadNeighbours<St> blk_neighbours(const unsigned char
     return nb;
 }
 
-// The stored form of an updated quad (rounded to the storage format) and
-// its stores to LDS and memory.
+// The stored form of an updated quad (rounded to the storage format with
+// its Philox words) and its stores to LDS and memory.
 template <class St>
-__device__ __forceinline__ typename BlkTraits<St>::Q blk_round(float4 v) {
-    if constexpr (std::is_same<St, StoreF32>::value) {
-        return v;
-    } else if constexpr (std::is_same<St, StoreBF16>::value) {
-        return u32x2{bf16x2_rne(v.x, v.y), bf16x2_rne(v.z, v.w)};
-    } else {
-        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-        const h2 a = {to_f16(v.x), to_f16(v.y)}, b = {to_f16(v.z), to_f16(v.w)};
-        return u32x2{__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b)};
-    }
+__device__ __forceinline__ typename BlkTraits<St>::Q blk_round(const QuadOut& o) {
+    return St::pack4(o.v, o.w);
 }
 template <class St, bool kNT>
 __device__ __forceinline__ void blk_store(typename St::T* base, uint32_t j0, typename BlkTraits<St>::Q v) {
@@ -476,7 +458,7 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
                     unsigned char* wr = valid[i] ? cring + (s % 3u) * cslot + woff[i] : sinkp;
                     const int az = (int)z0 - 1 + (int)s;
                     if (!kSteady && (az < 0 || az >= (int)lz)) {
-                        *reinterpret_cast<Q*>(wr) = blk_round<St>(make_float4(0.f, 0.f, 0.f, 0.f));
+                        *reinterpret_cast<Q*>(wr) = blk_round<St>(QuadOut{make_float4(0.f, 0.f, 0.f, 0.f), uint4{}});
                         continue;
                     }
                     const uint32_t az_u = (uint32_t)az;
@@ -598,6 +580,8 @@ hipError_t prepare_blocked_sweep() {
         result = set_lds_attrs_t<StoreF32>();
         if (result == hipSuccess) result = set_lds_attrs_t<StoreBF16>();
         if (result == hipSuccess) result = set_lds_attrs_t<StoreF16>();
+        if (result == hipSuccess) result = set_lds_attrs_t<StoreBF16SR>();
+        if (result == hipSuccess) result = set_lds_attrs_t<StoreF16SR>();
     });
     return result;
 }
@@ -652,6 +636,8 @@ hipError_t launch_blocked_sweep(const BlockedArgs& a, hipStream_t stream) {
         case 0: launch_blocked_t<StoreF32>(a, sh, (uint32_t)blocks, stream); break;
         case 1: launch_blocked_t<StoreBF16>(a, sh, (uint32_t)blocks, stream); break;
         case 2: launch_blocked_t<StoreF16>(a, sh, (uint32_t)blocks, stream); break;
+        case 3: launch_blocked_t<StoreBF16SR>(a, sh, (uint32_t)blocks, stream); break;
+        case 4: launch_blocked_t<StoreF16SR>(a, sh, (uint32_t)blocks, stream); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

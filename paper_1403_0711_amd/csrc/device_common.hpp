@@ -95,8 +95,15 @@ __device__ __forceinline__ float heatbath_noise(uint32_t u) {
 // y-1/y+1, bc the other-colour quad at the same columns, e the other-colour
 // value beyond the quad on the side p selects (p = (c + y + z) & 1: the
 // x-neighbours of site k are other-colour columns k-1+p and k+p).  One
-// Philox4x32-10 call with counter (j0/4, h, chain, 0) gives the 4 words.
-__device__ __forceinline__ float4 heatbath_quad(const float4& bm, const float4& bc, const float4& bn,
+// Philox4x32-10 call with counter (j0/4, h, chain, 0) gives the 4 words;
+// they are returned with the update, since the stochastically rounding
+// storage formats draw their random bits from the words' low bytes (the
+// uniform uses only the top 24 bits of a word).
+struct QuadOut {
+    float4 v;
+    uint4 w;
+};
+__device__ __forceinline__ QuadOut heatbath_quad(const float4& bm, const float4& bc, const float4& bn,
                                                 const float4& up, const float4& dn, float e, uint32_t p,
                                                 uint32_t j0, uint32_t h, uint32_t chain, uint32_t k0,
                                                 uint32_t k1) {
@@ -119,7 +126,7 @@ __device__ __forceinline__ float4 heatbath_quad(const float4& bm, const float4& 
     out.y = fmaf(a1 + up.y + dn.y + bm.y + bn.y, sixth, heatbath_noise(r.y));
     out.z = fmaf(a2 + up.z + dn.z + bm.z + bn.z, sixth, heatbath_noise(r.z));
     out.w = fmaf(a3 + up.w + dn.w + bm.w + bn.w, sixth, heatbath_noise(r.w));
-    return out;
+    return QuadOut{out, r};
 }
 
 // ---------------------------------------------------------------------------
@@ -146,9 +153,20 @@ __device__ __forceinline__ float bload_f32(__amdgpu_buffer_rsrc_t r, uint32_t of
 }
 
 // ---------------------------------------------------------------------------
-// Field storage formats: FP32, BF16, FP16.  Arithmetic is always FP32; a
-// stored value is rounded to nearest even.
+// Field storage formats.  Arithmetic is always FP32.  A stored value is the
+// FP32 update rounded to FP32 (no change), to BF16 or FP16 to nearest even,
+// or to BF16 or FP16 stochastically (the SR formats: the same arrays as the
+// round-to-nearest ones, only the rounding of an update differs).
+//
+// Stochastic rounding takes the 8 low bits u8 of the site's Philox word.
+// With f the value's distance beyond the grid point below its magnitude, in
+// grid spacings, the magnitude goes up to the next grid point when
+// 256 f + u8 >= 255.5: over the 256 values of u8 it goes up in the nearest
+// whole number of cases to 256 f, so the mean stored value is the FP32 value
+// up to 1/512 of a spacing, with no bias toward zero.
 // ---------------------------------------------------------------------------
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 // Element i of an array as a 32-bit byte offset from its base (every array
 // here is below 4 GiB), so loads use an SGPR base plus a VGPR offset instead
 // of a 64-bit address per lane.
@@ -161,32 +179,59 @@ __device__ __forceinline__ V& at(T* p, uint32_t i) {
     return *reinterpret_cast<V*>(reinterpret_cast<char*>(p) + i * (uint32_t)sizeof(T));
 }
 
-struct StoreF32 {
-    using T = float;
-    static constexpr int kBytes = 4;
-    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return at<float>(p, i); }
-    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) { return at<float4>(p, i); }
-    __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) { at<float4>(p, i) = v; }
-    __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v) {
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        __builtin_nontemporal_store(f4{v.x, v.y, v.z, v.w}, &at<f4>(p, i));
-    }
-    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<float>(p, i) = v; }
-    __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32x4(r, off); }
-    __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32(r, off); }
-    // the value a store followed by a load returns
-    __device__ static __forceinline__ float4 round4(float4 v) { return v; }
-};
-
-__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
-// The FP32 value v as a register: the rounding to FP16 that follows cannot
-// be folded into the FMA that produced v (a mixed-precision FMA rounds once,
-// from the exact result), so every kernel stores the FP32 update rounded to
-// the storage format, and a value recomputed elsewhere rounds the same way.
+// The FP32 value v as a register: the rounding to the storage format that
+// follows cannot be folded into the FMA that produced v (a mixed-precision
+// FMA rounds once, from the exact result), so every kernel stores the FP32
+// update rounded to the storage format, and a value recomputed elsewhere
+// rounds the same way.
 __device__ __forceinline__ float fp32_reg(float v) {
     asm("" : "+v"(v));
     return v;
 }
+
+// Every format provides: T (array element), Grid (the round-to-nearest
+// format of the same array, which readers use), Raw (a stored quad),
+// ld/ld4/bld/bld4 (loads as FP32), unpack4, pack4 and pack1 (an updated
+// quad or value with its Philox words, as stored), and through StoreOps the
+// stores of updates st4/st4_nt/st and round4 (the value a store followed by
+// a load returns).
+template <class D>
+struct StoreOps {
+    template <class T>
+    __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v, uint4 w) {
+        at<typename D::Raw>(p, i) = D::pack4(v, w);
+    }
+    template <class T>
+    __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v, uint4 w) {
+        __builtin_nontemporal_store(D::pack4(v, w), &at<typename D::Raw>(p, i));
+    }
+    template <class T>
+    __device__ static __forceinline__ void st(T* p, uint32_t i, float v, uint32_t w) {
+        at<T>(p, i) = D::pack1(v, w);
+    }
+    __device__ static __forceinline__ float4 round4(float4 v, uint4 w) { return D::unpack4(D::pack4(v, w)); }
+};
+
+struct StoreF32 : StoreOps<StoreF32> {
+    using T = float;
+    using Grid = StoreF32;
+    using Raw = float4;
+    static constexpr int kBytes = 4;
+    static constexpr bool kSR = false;
+    __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return at<float>(p, i); }
+    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) { return at<float4>(p, i); }
+    __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32x4(r, off); }
+    __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) { return bload_f32(r, off); }
+    __device__ static __forceinline__ float4 unpack4(Raw r) { return r; }
+    __device__ static __forceinline__ Raw pack4(float4 v, uint4) { return v; }
+    __device__ static __forceinline__ float pack1(float v, uint32_t) { return v; }
+    __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v, uint4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(f4{v.x, v.y, v.z, v.w}, &at<f4>(p, i));
+    }
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 // Two values rounded to nearest even to BF16 and packed (a in the low half):
 // gfx950's v_cvt_pk_bf16_f32, one instruction per pair instead of an integer
 // rounding sequence per value; finite inputs only.
@@ -196,86 +241,121 @@ __device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
     const f32x2 v = {fp32_reg(a), fp32_reg(b)};
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
+// Stochastic rounding to BF16 (a BF16 value is the upper half of an FP32
+// word): with d the word's low 16 bits, f = d / 2^16, and the rule above is
+// d + 256 u8 + 128 >= 2^16, so adding 256 u8 + 128 to the word and keeping
+// its upper half rounds as required (the carry runs into the exponent at a
+// power of two, as the next grid point requires; finite inputs only: the
+// sign bit is never reached).  Two values packed, a in the low half.
+__device__ __forceinline__ uint32_t bf16x2_sr(float a, float b, uint32_t wa, uint32_t wb) {
+    const uint32_t ua = __float_as_uint(fp32_reg(a)) + (((wa & 0xFFu) << 8) | 0x80u);
+    const uint32_t ub = __float_as_uint(fp32_reg(b)) + (((wb & 0xFFu) << 8) | 0x80u);
+    return __builtin_amdgcn_perm(ub, ua, 0x07060302u);  // upper halves: b's over a's
+}
 
-struct StoreBF16 {
+struct Bf16Array {
     using T = uint16_t;
+    using Raw = u32x2;
     static constexpr int kBytes = 2;
     __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return bf16_to_f32(at<uint16_t>(p, i)); }
-    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) {
-        const uint2 w = at<uint2>(p, i);
-        return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
-                           __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
-    }
-    __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) {
-        uint2 w;
-        w.x = bf16x2_rne(v.x, v.y);
-        w.y = bf16x2_rne(v.z, v.w);
-        at<uint2>(p, i) = w;
-    }
-    __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v) {
-        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
-        const u2 w = {bf16x2_rne(v.x, v.y), bf16x2_rne(v.z, v.w)};
-        __builtin_nontemporal_store(w, &at<u2>(p, i));
-    }
-    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) {
-        at<uint16_t>(p, i) = (T)(bf16x2_rne(v, 0.0f) & 0xFFFFu);
-    }
-    __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    __device__ static __forceinline__ float4 unpack4(Raw w) {
         return make_float4(__uint_as_float(w[0] << 16), __uint_as_float(w[0] & 0xFFFF0000u),
                            __uint_as_float(w[1] << 16), __uint_as_float(w[1] & 0xFFFF0000u));
+    }
+    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) { return unpack4(at<Raw>(p, i)); }
+    __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return unpack4(Raw{w[0], w[1]});
     }
     __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
     }
-    __device__ static __forceinline__ float4 round4(float4 v) {
-        const uint32_t a = bf16x2_rne(v.x, v.y), b = bf16x2_rne(v.z, v.w);
-        return make_float4(__uint_as_float(a << 16), __uint_as_float(a & 0xFFFF0000u), __uint_as_float(b << 16),
-                           __uint_as_float(b & 0xFFFF0000u));
+};
+struct StoreBF16 : Bf16Array, StoreOps<StoreBF16> {
+    using Grid = StoreBF16;
+    static constexpr bool kSR = false;
+    __device__ static __forceinline__ Raw pack4(float4 v, uint4) {
+        return Raw{bf16x2_rne(v.x, v.y), bf16x2_rne(v.z, v.w)};
     }
+    __device__ static __forceinline__ T pack1(float v, uint32_t) { return (T)(bf16x2_rne(v, 0.0f) & 0xFFFFu); }
+};
+struct StoreBF16SR : Bf16Array, StoreOps<StoreBF16SR> {
+    using Grid = StoreBF16;
+    static constexpr bool kSR = true;
+    __device__ static __forceinline__ Raw pack4(float4 v, uint4 w) {
+        return Raw{bf16x2_sr(v.x, v.y, w.x, w.y), bf16x2_sr(v.z, v.w, w.z, w.w)};
+    }
+    __device__ static __forceinline__ T pack1(float v, uint32_t w) { return (T)(bf16x2_sr(v, 0.0f, w, 0u) & 0xFFFFu); }
 };
 
 __device__ __forceinline__ _Float16 to_f16(float v) { return (_Float16)fp32_reg(v); }
+// Stochastic rounding to FP16.  From the smallest normal 2^-14 up, 13 bits
+// of the FP32 significand are dropped: with d those bits, f = d / 2^13 and
+// the rule is d + 32 u8 + 16 >= 2^13, so adding 32 u8 + 16 to the word and
+// clearing the 13 bits gives the result as an FP32 value on the FP16 grid
+// (finite inputs below the FP16 maximum).  Below 2^-14 the grid is the
+// subnormal one, spacing 2^-24: there |v| 2^24 = k + f exactly, and the
+// magnitude becomes (k + 1) 2^-24 when f >= (511 - 2 u8) / 512 (the same
+// rule, compared exactly), else k 2^-24; taken in a wave branch only where
+// some lane needs it.  The final conversion is exact.
+__device__ __forceinline__ _Float16 f16_sr(float v, uint32_t w) {
+    const uint32_t u = __float_as_uint(fp32_reg(v));
+    float r = __uint_as_float((u + (((w & 0xFFu) << 5) | 0x10u)) & 0xFFFFE000u);
+    const bool sub = (u & 0x7FFFFFFFu) < 0x38800000u;
+    if (__builtin_amdgcn_ballot_w64(sub) != 0) {
+        const float t = __uint_as_float(u & 0x7FFFFFFFu) * 0x1p24f;  // exact
+        const float k = __builtin_floorf(t);
+        const float up = (t - k) >= (float)(511u - 2u * (w & 0xFFu)) * 0x1p-9f ? 1.0f : 0.0f;
+        const float m = __uint_as_float(__float_as_uint((k + up) * 0x1p-24f) | (u & 0x80000000u));
+        r = sub ? m : r;
+    }
+    return (_Float16)r;
+}
 
-struct StoreF16 {
+struct F16Array {
     using T = _Float16;
+    using Raw = u32x2;
     static constexpr int kBytes = 2;
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
     __device__ static __forceinline__ float ld(const T* p, uint32_t i) { return (float)at<_Float16>(p, i); }
-    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) {
-        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        const h4 w = at<h4>(p, i);
-        return make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
-    }
-    __device__ static __forceinline__ void st4(T* p, uint32_t i, float4 v) {
-        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        h4 w;
-        w[0] = to_f16(v.x);
-        w[1] = to_f16(v.y);
-        w[2] = to_f16(v.z);
-        w[3] = to_f16(v.w);
-        at<h4>(p, i) = w;
-    }
-    __device__ static __forceinline__ void st4_nt(T* p, uint32_t i, float4 v) {
-        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        const h4 w = {to_f16(v.x), to_f16(v.y), to_f16(v.z), to_f16(v.w)};
-        __builtin_nontemporal_store(w, &at<h4>(p, i));
-    }
-    __device__ static __forceinline__ void st(T* p, uint32_t i, float v) { at<_Float16>(p, i) = to_f16(v); }
-    __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    __device__ static __forceinline__ float4 unpack4(Raw w) {
         const h4 hv = __builtin_bit_cast(h4, w);
         return make_float4((float)hv[0], (float)hv[1], (float)hv[2], (float)hv[3]);
+    }
+    __device__ static __forceinline__ float4 ld4(const T* p, uint32_t i) { return unpack4(at<Raw>(p, i)); }
+    __device__ static __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return unpack4(Raw{w[0], w[1]});
     }
     __device__ static __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
     }
-    __device__ static __forceinline__ float4 round4(float4 v) {
-        return make_float4((float)to_f16(v.x), (float)to_f16(v.y), (float)to_f16(v.z), (float)to_f16(v.w));
+    __device__ static __forceinline__ uint32_t pair(_Float16 a, _Float16 b) {
+        return __builtin_bit_cast(uint32_t, h2{a, b});
     }
 };
+struct StoreF16 : F16Array, StoreOps<StoreF16> {
+    using Grid = StoreF16;
+    static constexpr bool kSR = false;
+    __device__ static __forceinline__ Raw pack4(float4 v, uint4) {
+        return Raw{pair(to_f16(v.x), to_f16(v.y)), pair(to_f16(v.z), to_f16(v.w))};
+    }
+    __device__ static __forceinline__ T pack1(float v, uint32_t) { return to_f16(v); }
+};
+struct StoreF16SR : F16Array, StoreOps<StoreF16SR> {
+    using Grid = StoreF16;
+    static constexpr bool kSR = true;
+    __device__ static __forceinline__ Raw pack4(float4 v, uint4 w) {
+        return Raw{pair(f16_sr(v.x, w.x), f16_sr(v.y, w.y)), pair(f16_sr(v.z, w.z), f16_sr(v.w, w.w))};
+    }
+    __device__ static __forceinline__ T pack1(float v, uint32_t w) { return f16_sr(v, w); }
+};
 
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// FP16 arrays (either rounding) hold raw halves that the FP16 update adds
+// in mixed-precision FMAs.
+template <class St>
+constexpr bool kF16Grid = std::is_same<typename St::Grid, StoreF16>::value;
 
 // FP16 storage: the update of heatbath_quad on raw halves (element k of a
 // quad in half k & 1 of word k >> 1).  Each f16 term joins its FP32 sum in
@@ -304,7 +384,7 @@ __device__ __forceinline__ float add_f16_pair(uint32_t a, uint32_t b) {  // half
         asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
-__device__ __forceinline__ float4 heatbath_quad_f16(u32x2 bm, u32x2 bc, u32x2 bn, u32x2 up, u32x2 dn, uint32_t e,
+__device__ __forceinline__ QuadOut heatbath_quad_f16(u32x2 bm, u32x2 bc, u32x2 bn, u32x2 up, u32x2 dn, uint32_t e,
                                                     uint32_t p, uint32_t j0, uint32_t h, uint32_t chain, uint32_t k0,
                                                     uint32_t k1) {
     float a0, a1, a2, a3;  // e + x, x + y, y + z, z + w (p = 0); x + y, y + z, z + w, w + e (p = 1)
@@ -330,7 +410,7 @@ __device__ __forceinline__ float4 heatbath_quad_f16(u32x2 bm, u32x2 bc, u32x2 bn
                  sixth, heatbath_noise(r.z));
     out.w = fmaf(add_f16<true>(bn[1], add_f16<true>(bm[1], add_f16<true>(dn[1], add_f16<true>(up[1], a3)))), sixth,
                  heatbath_noise(r.w));
-    return out;
+    return QuadOut{out, r};
 }
 
 // The neighbours of the quad at compact index j0 of a row, read straight
@@ -338,13 +418,13 @@ __device__ __forceinline__ float4 heatbath_quad_f16(u32x2 bm, u32x2 bc, u32x2 bn
 // position decide which x-neighbour beyond the quad is read), and the
 // update computed from them.  FP16 storage keeps the raw halves.  Split so
 // that a thread can have the loads of several quads in flight.
-template <class St>
+template <class St, bool kF16 = kF16Grid<St>>
 struct QuadNeighbours {
     float4 cen, ym, yp, zm, zp;
     float e;
 };
-template <>
-struct QuadNeighbours<StoreF16> {
+template <class St>
+struct QuadNeighbours<St, true> {
     u32x2 cen, ym, yp, zm, zp;
     uint32_t e;
 };
@@ -355,7 +435,7 @@ __device__ __forceinline__ QuadNeighbours<St> quad_load_global(const typename St
                                                               bool zp_in, bool e_in, uint32_t p) {
     const uint32_t je = p == 0 ? j0 - 1u : j0 + 4u;  // the x-neighbour beyond the quad
     QuadNeighbours<St> nb;
-    if constexpr (std::is_same<St, StoreF16>::value) {
+    if constexpr (kF16Grid<St>) {
         const u32x2 zero = {0u, 0u};
         nb.cen = at<u32x2>(other, j0);
         nb.ym = ym_in ? at<u32x2>(other, j0 - lh) : zero;
@@ -376,16 +456,16 @@ __device__ __forceinline__ QuadNeighbours<St> quad_load_global(const typename St
 }
 
 template <class St>
-__device__ __forceinline__ float4 quad_update_from(const QuadNeighbours<St>& nb, uint32_t p, uint32_t j0, uint32_t h,
+__device__ __forceinline__ QuadOut quad_update_from(const QuadNeighbours<St>& nb, uint32_t p, uint32_t j0, uint32_t h,
                                                    uint32_t chain, uint32_t k0, uint32_t k1) {
-    if constexpr (std::is_same<St, StoreF16>::value)
+    if constexpr (kF16Grid<St>)
         return heatbath_quad_f16(nb.zm, nb.cen, nb.zp, nb.ym, nb.yp, nb.e, p, j0, h, chain, k0, k1);
     else
         return heatbath_quad(nb.zm, nb.cen, nb.zp, nb.ym, nb.yp, nb.e, p, j0, h, chain, k0, k1);
 }
 
 template <class St>
-__device__ __forceinline__ float4 quad_update_global(const typename St::T* other, uint32_t j0, uint32_t lh,
+__device__ __forceinline__ QuadOut quad_update_global(const typename St::T* other, uint32_t j0, uint32_t lh,
                                                      uint32_t plane, bool ym_in, bool yp_in, bool zm_in, bool zp_in,
                                                      bool e_in, uint32_t p, uint32_t h, uint32_t chain, uint32_t k0,
                                                      uint32_t k1) {

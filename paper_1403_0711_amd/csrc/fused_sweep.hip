@@ -130,8 +130,9 @@ __global__ __launch_bounds__(1024) void fused_sweep(typename St::T* __restrict__
                     out.y = fmaf(a1 + ym.y + yp.y + zm.y + zp.y, sixth, heatbath_noise(rr.y));
                     out.z = fmaf(a2 + ym.z + yp.z + zm.z + zp.z, sixth, heatbath_noise(rr.z));
                     out.w = fmaf(a3 + ym.w + yp.w + zm.w + zp.w, sixth, heatbath_noise(rr.w));
-                    out = St::round4(out);
-                    if (za >= z0 && za < z1 && y >= y0 && y < y0 + (int)TY) St::st4(c0, j0, out);
+                    const float4 v = out;
+                    out = St::round4(v, rr);
+                    if (za >= z0 && za < z1 && y >= y0 && y < y0 + (int)TY) St::st4(c0, j0, v, rr);
                 }
                 A4(s, r) = out;
             }
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(1024) void fused_sweep(typename St::T* __restrict__
                 out.y = fmaf(a1 + ym.y + yp.y + zm.y + zp.y, sixth, heatbath_noise(rr.y));
                 out.z = fmaf(a2 + ym.z + yp.z + zm.z + zp.z, sixth, heatbath_noise(rr.z));
                 out.w = fmaf(a3 + ym.w + yp.w + zm.w + zp.w, sixth, heatbath_noise(rr.w));
-                St::st4(b_out, j0, out);
+                St::st4(b_out, j0, out, rr);
             }
         }
     }
@@ -200,6 +201,12 @@ hipError_t prepare_fused_sweep() {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_sweep<StoreF16>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_sweep<StoreBF16SR>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_sweep<StoreF16SR>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
     return e;
 }
 
@@ -209,6 +216,8 @@ hipError_t launch_fused_sweep(const FusedArgs& a, hipStream_t stream) {
         case 0: return launch_fused_t<StoreF32>(a, stream);
         case 1: return launch_fused_t<StoreBF16>(a, stream);
         case 2: return launch_fused_t<StoreF16>(a, stream);
+        case 3: return launch_fused_t<StoreBF16SR>(a, stream);
+        case 4: return launch_fused_t<StoreF16SR>(a, stream);
         default: return hipErrorInvalidValue;
     }
 }

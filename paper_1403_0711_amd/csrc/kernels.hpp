@@ -8,6 +8,11 @@ namespace latcoul {
 
 enum : int { kVariantQuad = 1, kVariantGeneric = 2, kVariantZslab = 3, kVariantFused = 4, kVariantStream = 6 };
 
+// Storage codes: 0 FP32, 1 BF16, 2 FP16 (round to nearest even), 3 BF16 and
+// 4 FP16 rounded stochastically.  The array format of a code (what readers
+// of the field use): 3 is a BF16 array, 4 an FP16 one.
+inline int storage_grid(int storage) { return storage == 3 ? 1 : storage == 4 ? 2 : storage; }
+
 // One half-sweep of colour c = h & 1 on one lattice.
 // Finalize of one sample inside a sweep launch (workgroup 0, overlapped with
 // its first plane loads): the sum of n (X, Y) partial pairs at part is
@@ -27,7 +32,7 @@ struct SweepArgs {
     uint32_t c, h;    // colour, half-sweep index (Philox counter word 1)
     uint32_t k0, k1;  // Philox key
     uint32_t chain;   // Philox counter word 2
-    int storage;      // 0 FP32, 1 BF16, 2 FP16
+    int storage;      // storage code (storage_grid)
     int variant;      // kVariantQuad / kVariantGeneric / kVariantZslab / kVariantStream
     uint32_t zc;      // slab kernels: planes per workgroup (0 = 16)
     uint32_t xcd_order;  // slab kernels: XCD-aware block order

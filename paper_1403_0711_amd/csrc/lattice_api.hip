@@ -429,7 +429,7 @@ int lattice_create(int64_t lx, int64_t ly, int64_t lz, int storage, uint64_t see
     if (ly < 1 || lz < 1) return set_error(LAT_ERR_ARG, "ly and lz must be >= 1");
     if ((double)lx * (double)ly * (double)lz >= 2147483648.0)
         return set_error(LAT_ERR_ARG, "lattice must have fewer than 2^31 sites");
-    if (storage < LAT_FP32 || storage > LAT_FP16) return set_error(LAT_ERR_ARG, "unknown storage format");
+    if (storage < LAT_FP32 || storage > LAT_FP16_SR) return set_error(LAT_ERR_ARG, "unknown storage format");
     if (alloc && (!alloc->alloc || !alloc->release))
         return set_error(LAT_ERR_ARG, "allocator needs both alloc and release");
     lattice* L = new lattice();

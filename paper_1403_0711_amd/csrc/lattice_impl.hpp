@@ -266,7 +266,7 @@ struct lattice {
         // -18% from 240^3 to 448^3).  FP16 storage, whose quad kernel adds
         // neighbours in mixed-precision FMAs, and smaller boxes (quad -20% at
         // 192^3, -55% at 128^3) stay with the quad kernel
-        if (esz == 4 || storage == LAT_BF16)
+        if (esz == 4 || storage == LAT_BF16 || storage == LAT_BF16_SR)
             if ((uint64_t)vh * 2 >= kZslabAutoMinSites) return LAT_SWEEP_ZSLAB;
         return LAT_SWEEP_QUAD;
     }

@@ -53,7 +53,7 @@ __device__ __forceinline__ void lds_read_entry(uint32_t av, uint32_t aq, uint32_
                      : "memory");
     if constexpr (St::kBytes == 4)
         v = __uint_as_float(r);
-    else if constexpr (std::is_same<St, StoreBF16>::value)
+    else if constexpr (std::is_same<typename St::Grid, StoreBF16>::value)
         v = __uint_as_float(r << 16);
     else
         v = (float)__builtin_bit_cast(_Float16, (uint16_t)r);

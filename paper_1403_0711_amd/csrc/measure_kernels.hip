@@ -139,7 +139,7 @@ static hipError_t launch_measure_t(const MeasureArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream) {
-    switch (a.storage) {
+    switch (storage_grid(a.storage)) {
         case 0: return launch_measure_t<StoreF32>(a, stream);
         case 1: return launch_measure_t<StoreBF16>(a, stream);
         case 2: return launch_measure_t<StoreF16>(a, stream);

@@ -117,7 +117,7 @@ static hipError_t launch_offlattice_t(const OffLatticeArgs& a, hipStream_t strea
 
 hipError_t launch_measure_offlattice(const OffLatticeArgs& a, hipStream_t stream) {
     if (a.lx < 2 || a.ly < 2 || a.lz < 2 || (a.lx & 1u)) return hipErrorInvalidValue;
-    switch (a.storage) {
+    switch (storage_grid(a.storage)) {
         case 0: return launch_offlattice_t<StoreF32>(a, stream);
         case 1: return launch_offlattice_t<StoreBF16>(a, stream);
         case 2: return launch_offlattice_t<StoreF16>(a, stream);

@@ -129,7 +129,7 @@ void compact_to_natural(const void* compact, int storage, int64_t lx, int64_t ly
                 float v;
                 if (storage == LAT_FP32)
                     v = static_cast<const float*>(compact)[k];
-                else if (storage == LAT_BF16)
+                else if (storage == LAT_BF16 || storage == LAT_BF16_SR)
                     v = bf16_bits_to_float(static_cast<const uint16_t*>(compact)[k]);
                 else
                     v = (float)static_cast<const _Float16*>(compact)[k];
@@ -146,7 +146,7 @@ void natural_to_compact(const float* in, int storage, int64_t lx, int64_t ly, in
                 const size_t k = (size_t)((x + y + z) & 1) * vh + (size_t)(i >> 1);
                 if (storage == LAT_FP32)
                     static_cast<float*>(compact)[k] = in[i];
-                else if (storage == LAT_BF16)
+                else if (storage == LAT_BF16 || storage == LAT_BF16_SR)
                     static_cast<uint16_t*>(compact)[k] = float_to_bf16_rne(in[i]);
                 else
                     static_cast<_Float16*>(compact)[k] = (_Float16)in[i];

@@ -320,8 +320,8 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
             const unsigned char* pn = down ? pw0 : pw2;  // plane z + 1
             const uint32_t p = __builtin_amdgcn_readfirstlane((c + y + z) & 1u);  // uniform per wave
             const uint32_t j0 = z * plane + rowj;
-            float4 out;
-            if constexpr (std::is_same<St, StoreF16>::value) {  // halves added in mixed-precision FMAs
+            QuadOut out;
+            if constexpr (kF16Grid<St>) {  // halves added in mixed-precision FMAs
                 const unsigned char* pe = p == 0 ? pc - S::kEsz : pc + S::kQB;
                 out = heatbath_quad_f16(*reinterpret_cast<const u32x2*>(pm), *reinterpret_cast<const u32x2*>(pc),
                                         *reinterpret_cast<const u32x2*>(pn),
@@ -339,9 +339,9 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
                 out = heatbath_quad(bm, bc, bn, up, dn, e, p, j0, h, chain, k0, k1);
             }
             if constexpr (kNT)
-                St::st4_nt(own, j0, out);
+                St::st4_nt(own, j0, out.v, out.w);
             else
-                St::st4(own, j0, out);
+                St::st4(own, j0, out.v, out.w);
         }
     }
 }
@@ -428,6 +428,14 @@ hipError_t launch_halfsweep_stream(const SweepArgs& a, hipStream_t stream) {
             _Float16* f = static_cast<_Float16*>(a.field);
             return launch_stream_t<StoreF16>(a, f + (size_t)(a.c ^ 1u) * a.vh, f + (size_t)a.c * a.vh, stream);
         }
+        case 3: {
+            uint16_t* f = static_cast<uint16_t*>(a.field);
+            return launch_stream_t<StoreBF16SR>(a, f + (size_t)(a.c ^ 1u) * a.vh, f + (size_t)a.c * a.vh, stream);
+        }
+        case 4: {
+            _Float16* f = static_cast<_Float16*>(a.field);
+            return launch_stream_t<StoreF16SR>(a, f + (size_t)(a.c ^ 1u) * a.vh, f + (size_t)a.c * a.vh, stream);
+        }
         default: return hipErrorInvalidValue;
     }
 }
@@ -459,7 +467,7 @@ __global__ __launch_bounds__(64) void gather_tail(const typename St::T* __restri
 
 hipError_t launch_gather_tail(const GatherTailArgs& a, hipStream_t stream) {
     if (!a.field1 || !a.g_off || !a.g_j || !a.g_Q || !a.g_S || !a.g_part || a.tiles == 0) return hipErrorInvalidValue;
-    switch (a.storage) {
+    switch (storage_grid(a.storage)) {
         case 0:
             hipLaunchKernelGGL(gather_tail<StoreF32>, dim3(a.tiles), dim3(64), 0, stream,
                                static_cast<const float*>(a.field1), a.g_off, a.g_j, a.g_Q, a.g_S, a.g_part);

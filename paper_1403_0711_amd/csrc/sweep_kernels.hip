@@ -38,9 +38,9 @@ __global__ __launch_bounds__(256) void halfsweep_quad(const typename St::T* __re
     const uint32_t plane = ly * lh;
     const uint32_t j0 = (z * ly + y) * lh + 4u * q;
 
-    const float4 out = quad_update_global<St>(other, j0, lh, plane, y > 0, y + 1 < ly, z > 0, z + 1 < lz,
-                                              p == 0 ? q > 0 : q + 1 < nq, p, h, chain, k0, k1);
-    St::st4(own, j0, out);
+    const QuadOut out = quad_update_global<St>(other, j0, lh, plane, y > 0, y + 1 < ly, z > 0, z + 1 < lz,
+                                               p == 0 ? q > 0 : q + 1 < nq, p, h, chain, k0, k1);
+    St::st4(own, j0, out.v, out.w);
 }
 
 // One compact site per thread, any even lx.  Site j of colour c.
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void halfsweep_generic(const typename St::T* _
     if (z + 1 < lz) s += St::ld(other, j + plane);
     const uint4 r = philox4x32_10(j >> 2, h, chain, 0u, k0, k1);
     const uint32_t w = (j & 3u) == 0 ? r.x : (j & 3u) == 1 ? r.y : (j & 3u) == 2 ? r.z : r.w;
-    St::st(own, j, fmaf(s, 1.0f / 6.0f, heatbath_noise(w)));
+    St::st(own, j, fmaf(s, 1.0f / 6.0f, heatbath_noise(w)), w);
 }
 
 // z-marching slab (2.5-D blocking): a workgroup owns a tile of kTX quads x
@@ -140,7 +140,8 @@ struct Zslab {
         const uint32_t p = __builtin_amdgcn_readfirstlane((c + y + z) & 1u);
         const float e = p == 0 ? tile[buf][row + 1][3 + 4 * tx] : tile[buf][row + 1][8 + 4 * tx];
         const uint32_t j0 = z * plane + rowj;
-        St::st4(own, j0, heatbath_quad(bm, bc, bn, up, dn, e, p, j0, h, chain, k0, k1));
+        const QuadOut out = heatbath_quad(bm, bc, bn, up, dn, e, p, j0, h, chain, k0, k1);
+        St::st4(own, j0, out.v, out.w);
     }
 
     // one plane: stage bc (+ halo, edges) in LDS buffer kBuf, prefetch plane
@@ -319,6 +320,8 @@ hipError_t launch_halfsweep(const SweepArgs& a, hipStream_t stream) {
         case 0: return launch_halfsweep_t<StoreF32>(a, stream);
         case 1: return launch_halfsweep_t<StoreBF16>(a, stream);
         case 2: return launch_halfsweep_t<StoreF16>(a, stream);
+        case 3: return launch_halfsweep_t<StoreBF16SR>(a, stream);
+        case 4: return launch_halfsweep_t<StoreF16SR>(a, stream);
         default: return hipErrorInvalidValue;
     }
 }

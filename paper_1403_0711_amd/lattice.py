@@ -19,7 +19,9 @@ __all__ = ["Lattice", "Batch", "LatticeError", "load_library", "STORAGE", "VARIA
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "liblatcoul.so")
 
-STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
+# field storage formats (bf16sr and fp16sr round stochastically with the low
+# byte of each site's Philox word)
+STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16sr": 3, "fp16sr": 4}
 VARIANT = {"auto": 0, "quad": 1, "generic": 2, "zslab": 3, "fused": 4, "resident": 5, "stream": 6,
            "blocked": 7}
 ERR_NAMES = {1: "LAT_ERR_ARG", 2: "LAT_ERR_STATE", 3: "LAT_ERR_ALLOC", 4: "LAT_ERR_DEVICE"}

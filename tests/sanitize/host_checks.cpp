@@ -71,7 +71,7 @@ int main() {
     {
         const int64_t shapes[][3] = {{2, 1, 1}, {6, 3, 2}, {10, 7, 5}, {16, 16, 16}};
         for (const auto& sh : shapes)
-            for (int storage : {LAT_FP32, LAT_BF16, LAT_FP16}) {
+            for (int storage : {LAT_FP32, LAT_BF16, LAT_FP16, LAT_BF16_SR, LAT_FP16_SR}) {
                 const int64_t lx = sh[0], ly = sh[1], lz = sh[2], V = lx * ly * lz;
                 const uint32_t vh = (uint32_t)(V / 2);
                 std::vector<float> in((size_t)V), back((size_t)V, -1.0f);
@@ -89,7 +89,7 @@ int main() {
         const int32_t xyz[] = {1, 1, 1, 6, 4, 3, 3, 2, 2};
         const double q[] = {1.0, -1.0, 0.5};
         std::vector<double> samples(3 * 10);
-        for (int storage : {LAT_FP32, LAT_BF16, LAT_FP16}) {
+        for (int storage : {LAT_FP32, LAT_BF16, LAT_FP16, LAT_BF16_SR, LAT_FP16_SR}) {
             const int64_t m = orc_run(phi.data(), lx, ly, lz, storage, 7, 3, 0, 10, 1, 3, xyz, q, samples.data());
             CHECK(m == 10);
             for (double v : samples) CHECK(std::isfinite(v));

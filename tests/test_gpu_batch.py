@@ -82,7 +82,8 @@ def _fillers(storage):
     return [(64, 64, 64)] * (256 if storage == "fp32" else 512)
 
 
-@pytest.mark.parametrize("storage,filled", [("fp32", False), ("fp32", True), ("bf16", True), ("fp16", True)])
+@pytest.mark.parametrize("storage,filled", [("fp32", False), ("fp32", True), ("bf16", True), ("fp16", True),
+                                            ("bf16sr", True), ("fp16sr", False)])
 def test_batch_ring_matches_quad_kernel(lat_mod, storage, filled):
     """Batched chains equal single lattices swept by the quad kernel, bit for
     bit: in a small batch (the half-sweep from memory) and in batches filled

@@ -136,6 +136,30 @@ def test_variants_agree(lat_mod):
         np.testing.assert_array_equal(f, slab_fields[0])
 
 
+@pytest.mark.parametrize("storage", ["bf16sr", "fp16sr"])
+def test_variants_agree_stochastic_rounding(lat_mod, storage):
+    """Stochastically rounded storage: every sweep kernel, tiling and slab
+    depth stores the same bits (each site's rounding draws on its own Philox
+    word, also where the blocked and fused sweeps recompute halo rows)."""
+    print(f"[gpu] variants agree {storage}", flush=True)
+    shape = (64, 24, 20)
+    ref = lat_mod.Lattice(shape, storage, seed=7)
+    ref.set_variant("generic")
+    ref.thermalise(12)
+    fr = ref.get_field()
+    assert np.abs(fr).max() > 0
+    for variant, slab, tile, xcd in (("quad", 0, 0, True), ("resident", 0, 0, True), ("fused", 0, 0, True),
+                                     ("fused", 5, 0, False), ("zslab", 0, 0, True), ("zslab", 7, 2, True),
+                                     ("zslab", 5, 4, True), ("stream", 0, 0, True), ("stream", 7, 2, True),
+                                     ("stream", 3, 4, True), ("stream", 9, 6, True), ("blocked", 0, -1, 2),
+                                     ("blocked", 5, 3, 1), ("blocked", 20, 16, 2)):
+        a = lat_mod.Lattice(shape, storage, seed=7)
+        a.set_variant(variant)
+        a.set_tuning(slab, tile, xcd)
+        a.thermalise(12)
+        np.testing.assert_array_equal(a.get_field(), fr, err_msg=f"{variant} {slab} {tile} {xcd}")
+
+
 def test_measure_parity_and_pair_sum(lat_mod):
     """Samples taken on the GPU equal the oracle's gather of the read-back
     field; duplicate sites are aggregated without changing X and Y."""
@@ -215,28 +239,43 @@ def test_small_neutral_energy_vs_exact(lat_mod):
 def _ulp(v, storage):
     """Spacing of the storage format at |v|: 2^(e - p) for |v| in
     [2^(e-1), 2^e), p significant bits; fixed below the smallest normal."""
-    p, emin = (8, -126) if storage == "bf16" else (11, -14)
+    p, emin = (8, -126) if storage.startswith("bf16") else (11, -14)
     _, e = np.frexp(np.abs(v))
     e = np.maximum(e - 1, emin)
     return np.ldexp(1.0, e - p + 1)
 
 
-@pytest.mark.parametrize("variant", ["auto", "zslab", "stream", "blocked"])
-@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def _rounded_like_storage(vals, pts, storage, shape, seed, chain, h):
+    """The oracle's values rounded as the storage format stores them: to
+    nearest even, or (bf16sr, fp16sr) stochastically with the low byte of
+    each site's Philox word in half-sweep h."""
+    if not storage.endswith("sr"):
+        return np.array([oracle.round_storage(v, storage) for v in vals])
+    return np.array([oracle.round_storage(v, storage, oracle.site_word(shape, int(x), int(y), int(z), seed, chain, h))
+                     for v, (x, y, z) in zip(vals, pts)])
+
+
+@pytest.mark.parametrize("variant", ["auto", "zslab", "stream", "blocked", "quad", "generic", "fused", "resident"])
+@pytest.mark.parametrize("storage", ["bf16", "fp16", "bf16sr", "fp16sr"])
 def test_reduced_precision_parity(lat_mod, storage, variant):
     """16-bit storage, one sweep from a common field, checked half-sweep by
     half-sweep: each colour's new values equal the oracle's heat-bath values
-    (FP64, rounded to the storage format) computed from the field the GPU
+    (FP64, rounded to the storage format: to nearest even, or stochastically
+    with the site's Philox low byte) computed from the field the GPU
     actually read, except at under 1% of sites where FP32 vs FP64 arithmetic
     lands on the other side of a rounding boundary: there by one storage ulp.
     After 30 more sweeps the field stays within a few ulps of the oracle's
     chain (the map contracts)."""
+    if storage in ("bf16", "fp16") and variant in ("quad", "generic", "fused", "resident"):
+        pytest.skip("round-to-nearest storage on these kernels: covered by the kernel-agreement tests")
     print(f"[gpu] reduced precision {storage} {variant}", flush=True)
-    shape = (24, 16, 12) if variant != "blocked" else (32, 16, 12)  # blocked 16-bit: rows of whole 16-byte chunks
+    # blocked 16-bit: rows of whole 16-byte chunks; fused: rows of 8 quads;
+    # generic: quads that straddle rows
+    shape = {"blocked": (32, 16, 12), "fused": (64, 16, 12), "generic": (10, 6, 5)}.get(variant, (24, 16, 12))
     lx, ly, lz = shape
     lat = lat_mod.Lattice(shape, storage, seed=5)
     lat.set_variant(variant)
-    if variant != "auto":  # (the blocked sweep's tile is its rows per tile)
+    if variant in ("zslab", "stream", "blocked"):  # (the blocked sweep's tile is its rows per tile)
         lat.set_tuning(5, 0 if variant != "blocked" else 4, xcd_order=True)
     ref = oracle.OracleChain(shape, storage, seed=5)
     rng = np.random.default_rng(0)
@@ -252,7 +291,7 @@ def test_reduced_precision_parity(lat_mod, storage, variant):
         zz, yy, xx = np.nonzero(colour == c)
         pts = np.stack([xx, yy, zz], axis=1)
         vals = oracle.site_values_f32(src, pts, 5, 0, c)
-        want = np.array([oracle.round_storage(v, storage) for v in vals])
+        want = _rounded_like_storage(vals, pts, storage, shape, 5, 0, c)
         got = g[zz, yy, xx].astype(np.float64)
         diff = np.abs(got - want)
         assert (diff > 0).mean() < 0.01, c
@@ -416,7 +455,7 @@ def _sampled_sweep_parity(lat_mod, shape, variant, n_samples=4096, storage="fp32
         if storage == "fp32":
             assert np.abs(got - ref).max() <= 2e-6 * max(1.0, np.abs(ref).max()), c
         else:  # the oracle's value rounded to the storage format; one ulp at under 1% of sites
-            want = np.array([oracle.round_storage(v, storage) for v in ref])
+            want = _rounded_like_storage(ref, pts, storage, shape, seed, 1, 2 * 3 + c)
             diff = np.abs(got - want)
             assert (diff > 0).mean() < 0.01, c
             assert np.all(diff <= np.maximum(_ulp(got, storage), _ulp(want, storage))), c
@@ -435,6 +474,14 @@ def test_sampled_parity_largest_box(lat_mod):
     BF16 runs)."""
     print("[gpu] sampled parity 768^3", flush=True)
     _sampled_sweep_parity(lat_mod, (768, 768, 768), "stream", n_samples=2048)
+
+
+@pytest.mark.parametrize("storage", ["fp16sr", "bf16sr"])
+def test_sampled_parity_largest_box_sr(lat_mod, storage):
+    """768^3 with stochastically rounded 16-bit storage on the library's
+    default kernel for the box (the streaming sweep)."""
+    print(f"[gpu] sampled parity 768^3 {storage}", flush=True)
+    _sampled_sweep_parity(lat_mod, (768, 768, 768), "auto", n_samples=2048, storage=storage)
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
