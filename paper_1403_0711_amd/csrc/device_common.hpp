@@ -241,16 +241,22 @@ __device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
     const f32x2 v = {fp32_reg(a), fp32_reg(b)};
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
-// Stochastic rounding to BF16 (a BF16 value is the upper half of an FP32
-// word): with d the word's low 16 bits, f = d / 2^16, and the rule above is
-// d + 256 u8 + 128 >= 2^16, so adding 256 u8 + 128 to the word and keeping
-// its upper half rounds as required (the carry runs into the exponent at a
-// power of two, as the next grid point requires; finite inputs only: the
-// sign bit is never reached).  Two values packed, a in the low half.
+// Stochastic rounding in hardware: gfx950's v_cvt_sr_bf16_f32 and
+// v_cvt_sr_f16_f32 round with a 32-bit random operand.  With the operand
+// (w << 24) | 2^23 they apply the rule above with u8 = w & 0xFF: for BF16,
+// with d the FP32 word's low 16 bits (f = d / 2^16), the magnitude goes up
+// when d + 256 u8 + 128 >= 2^16; for FP16 the same with the 13 dropped bits
+// (d + 32 u8 + 16 >= 2^13) and on the subnormal grid below 2^-14.  Checked
+// bit for bit against that integer rule on 2^20 values (normal values,
+// values next to powers of two, FP16 subnormals and zeros).  One
+// instruction per value writes one half of the packed result.
+__device__ __forceinline__ uint32_t sr_operand(uint32_t w) { return (w << 24) | 0x800000u; }
 __device__ __forceinline__ uint32_t bf16x2_sr(float a, float b, uint32_t wa, uint32_t wb) {
-    const uint32_t ua = __float_as_uint(fp32_reg(a)) + (((wa & 0xFFu) << 8) | 0x80u);
-    const uint32_t ub = __float_as_uint(fp32_reg(b)) + (((wb & 0xFFu) << 8) | 0x80u);
-    return __builtin_amdgcn_perm(ub, ua, 0x07060302u);  // upper halves: b's over a's
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    bf16x2 o = {};
+    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(a), sr_operand(wa), false);
+    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(b), sr_operand(wb), true);
+    return __builtin_bit_cast(uint32_t, o);
 }
 
 struct Bf16Array {
@@ -289,27 +295,13 @@ struct StoreBF16SR : Bf16Array, StoreOps<StoreBF16SR> {
 };
 
 __device__ __forceinline__ _Float16 to_f16(float v) { return (_Float16)fp32_reg(v); }
-// Stochastic rounding to FP16.  From the smallest normal 2^-14 up, 13 bits
-// of the FP32 significand are dropped: with d those bits, f = d / 2^13 and
-// the rule is d + 32 u8 + 16 >= 2^13, so adding 32 u8 + 16 to the word and
-// clearing the 13 bits gives the result as an FP32 value on the FP16 grid
-// (finite inputs below the FP16 maximum).  Below 2^-14 the grid is the
-// subnormal one, spacing 2^-24: there |v| 2^24 = k + f exactly, and the
-// magnitude becomes (k + 1) 2^-24 when f >= (511 - 2 u8) / 512 (the same
-// rule, compared exactly), else k 2^-24; taken in a wave branch only where
-// some lane needs it.  The final conversion is exact.
-__device__ __forceinline__ _Float16 f16_sr(float v, uint32_t w) {
-    const uint32_t u = __float_as_uint(fp32_reg(v));
-    float r = __uint_as_float((u + (((w & 0xFFu) << 5) | 0x10u)) & 0xFFFFE000u);
-    const bool sub = (u & 0x7FFFFFFFu) < 0x38800000u;
-    if (__builtin_amdgcn_ballot_w64(sub) != 0) {
-        const float t = __uint_as_float(u & 0x7FFFFFFFu) * 0x1p24f;  // exact
-        const float k = __builtin_floorf(t);
-        const float up = (t - k) >= (float)(511u - 2u * (w & 0xFFu)) * 0x1p-9f ? 1.0f : 0.0f;
-        const float m = __uint_as_float(__float_as_uint((k + up) * 0x1p-24f) | (u & 0x80000000u));
-        r = sub ? m : r;
-    }
-    return (_Float16)r;
+// Two values stochastically rounded to FP16 and packed (a in the low half).
+__device__ __forceinline__ uint32_t f16x2_sr(float a, float b, uint32_t wa, uint32_t wb) {
+    typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+    f16x2 o = {};
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(a), sr_operand(wa), false);
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(b), sr_operand(wb), true);
+    return __builtin_bit_cast(uint32_t, o);
 }
 
 struct F16Array {
@@ -347,9 +339,11 @@ struct StoreF16SR : F16Array, StoreOps<StoreF16SR> {
     using Grid = StoreF16;
     static constexpr bool kSR = true;
     __device__ static __forceinline__ Raw pack4(float4 v, uint4 w) {
-        return Raw{pair(f16_sr(v.x, w.x), f16_sr(v.y, w.y)), pair(f16_sr(v.z, w.z), f16_sr(v.w, w.w))};
+        return Raw{f16x2_sr(v.x, v.y, w.x, w.y), f16x2_sr(v.z, v.w, w.z, w.w)};
     }
-    __device__ static __forceinline__ T pack1(float v, uint32_t w) { return f16_sr(v, w); }
+    __device__ static __forceinline__ T pack1(float v, uint32_t w) {
+        return __builtin_bit_cast(T, (uint16_t)(f16x2_sr(v, 0.0f, w, 0u) & 0xFFFFu));
+    }
 };
 
 // FP16 arrays (either rounding) hold raw halves that the FP16 update adds
