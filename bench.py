@@ -89,6 +89,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--figures-sweeps", type=int, default=200000,
                    help="measured sweeps of the figures comparison (128^3, 132 charge sets)")
+    p.add_argument("--precision-128", type=int, default=0, metavar="SWEEPS",
+                   help="only the coupled precision comparison on a 128^3 Gaussian blob (7400 charges of +1, "
+                        "sigma 16; 1e5 FP32 thermalisation sweeps) with SWEEPS sweeps per format")
     p.add_argument("--coupled-sweeps", type=int, default=100000,
                    help="sweeps per storage format of the coupled precision comparison")
     return p.parse_args()
@@ -321,7 +324,7 @@ def tau_and_error(series: np.ndarray):
     return err, 0.5 * (err / curve[0][1]) ** 2, curve
 
 
-def precision_coupled(sweeps, torch, lattice, workloads, therm=40000):
+def precision_coupled(sweeps, torch, lattice, workloads, therm=40000, small=None):
     """Reduced-precision storage at equal accuracy, on the 384^3 Gaussian blob
     (2e5 charges of +1).  One FP32 chain is thermalised (`therm` sweeps from
     phi = 0, about 5 e-folds of the slowest mode's variance); its field is the
@@ -341,25 +344,32 @@ def precision_coupled(sweeps, torch, lattice, workloads, therm=40000):
     equal statistics, time to a given error scales as the cost per sweep.  Each
     format runs the sweep configuration the library's autotuner picks for it
     on this machine (kernel choice does not change the chain: every kernel
-    computes the same update)."""
-    name = "gaussian_blob_384"
-    spec = workloads.WORKLOADS[name]
-    cs = spec["make"]()
-    E = exact_energy(name)
+    computes the same update).  With `small` (a charge set), the same on
+    that set instead (the 128^3 blob of --precision-128: long runs resolve
+    biases of 1e-4 of E_N)."""
+    name = "gaussian_blob_384" if small is None else "gaussian_blob_128"
+    if small is None:
+        spec = workloads.WORKLOADS[name]
+        cs, seed, E = spec["make"](), spec["philox_seed"], exact_energy(name)
+    else:
+        cs, seed, E = small, 0, None
     out, series = {"workload": name, "sweeps": sweeps, "thermalisation_fp32": therm, "E_exact": E}, {}
-    lat = lattice.Lattice(cs.shape, "fp32", seed=spec["philox_seed"], chain_id=7)
+    lat = lattice.Lattice(cs.shape, "fp32", seed=seed, chain_id=7)
     lat.thermalise(therm)
     phi0 = lat.get_field()
     lat.close()
     formats = ("fp32", "bf16", "fp16", "bf16sr", "fp16sr")
     for st in formats:
-        lat = lattice.Lattice(cs.shape, st, seed=spec["philox_seed"])
+        lat = lattice.Lattice(cs.shape, st, seed=seed)
         lat.set_field(phi0)
         lat.set_charges(cs.xyz, cs.q)
         lat.autotune(3)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        lat.sweep_and_measure(sweeps, 1, 1)
+        for done in range(0, sweeps, 200000):  # calls of at most 2e5 sweeps (progress lines)
+            lat.sweep_and_measure(min(200000, sweeps - done), 1, 1)
+            if sweeps > 200000:
+                print(f"precision {name} {st}: {min(done + 200000, sweeps)} sweeps", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         _, n, bins = lat.get_state()
@@ -383,6 +393,7 @@ def precision_coupled(sweeps, torch, lattice, workloads, therm=40000):
         err, tau, _ = tau_and_error(d)
         out[st].update({"bias_vs_fp32": float(d.mean()), "bias_stderr": err, "bias_tau_int": tau,
                         "bias_rel_to_exact": float(d.mean()) / E if E else None,
+                        "bias_rel_to_fp32_mean": float(d.mean()) / out["fp32"]["mean_O"],
                         "sd_of_difference": float(d.std()),
                         "cost_vs_fp32": out[st]["ms_per_sweep"] / out["fp32"]["ms_per_sweep"]})
     return out
@@ -680,6 +691,11 @@ def main():
     spec = workloads.WORKLOADS[args.workload]
     if args.calibrate_copy:
         calibrate_copy(spec, torch)
+        return
+    if args.precision_128:
+        blob = workloads.gaussian_blob(seed=0, L=128, n=7400, sigma=16.0)
+        print(json.dumps({"precision_coupled_128": precision_coupled(args.precision_128, torch, lattice, workloads,
+                                                                     therm=100000, small=blob)}), flush=True)
         return
     cs = spec["make"]()
     seed = spec["philox_seed"]

@@ -27,7 +27,7 @@ import os
 import numpy as np
 
 __all__ = ["OracleChain", "load", "philox4x32_10", "inv_norm_cdf", "round_storage",
-           "site_uniform", "site_word", "noise_grid", "estimate", "gather_offlattice", "force_sample", "STORAGE"]
+           "round_storage_sr_mean", "site_uniform", "site_word", "noise_grid", "estimate", "gather_offlattice", "force_sample", "STORAGE"]
 
 # storage formats: 16-bit values rounded to nearest even (bf16, fp16) or
 # stochastically with the 8 low bits of each site's Philox word (bf16sr, fp16sr)
@@ -69,6 +69,8 @@ def load() -> ctypes.CDLL:
     lib.orc_site_word.restype = _u32
     lib.orc_round_storage_sr.argtypes = [_d, ctypes.c_int, _u32]
     lib.orc_round_storage_sr.restype = _d
+    lib.orc_round_storage_sr_mean.argtypes = [_p, _i64, ctypes.c_int, _p]
+    lib.orc_round_storage_sr_mean.restype = None
     lib.orc_site_value.argtypes = [_p, _i64, _i64, _i64, _i64, _i64, _i64, _u64, _u32, _u32]
     lib.orc_site_value.restype = _d
     lib.orc_halfsweep.argtypes = [_p, _i64, _i64, _i64, ctypes.c_int, _u64, _u32, _u32]
@@ -120,6 +122,15 @@ def round_storage(v: float, storage: str, u8=None) -> float:
     if code >= 3 and u8 is not None:
         return load().orc_round_storage_sr(float(v), code, int(u8) & 0xFF)
     return load().orc_round_storage(float(v), _GRID_OF[code])
+
+
+def round_storage_sr_mean(v: np.ndarray, storage: str) -> np.ndarray:
+    """For each FP64 value, the mean of its stochastic roundings (format
+    ``bf16sr`` or ``fp16sr``) over the 256 values of the random byte."""
+    x = np.ascontiguousarray(v, dtype=np.float64).ravel()
+    out = np.empty_like(x)
+    load().orc_round_storage_sr_mean(_ptr(x), x.size, STORAGE[storage], _ptr(out))
+    return out
 
 
 def site_uniform(shape, x, y, z, seed, chain, h) -> float:

@@ -34,7 +34,7 @@
  * Arithmetic is FP64; each stored value is rounded to the storage format:
  * 0 = FP32, 1 = BF16, 2 = FP16 (round-to-nearest-even), 3 = BF16, 4 = FP16
  * (stochastic rounding with the 8 low bits of the site's Philox word, which
- * the uniform does not use).
+ * the uniform does not use; ties broken by the parity of those bits).
  */
 #include <math.h>
 #include <stdint.h>
@@ -139,11 +139,16 @@ double orc_round_storage(double v, int storage) {
 
 /* Stochastic rounding to p significant bits (smallest normal exponent emin,
  * the subnormal grid below it).  lo is |v| rounded toward zero to the grid,
- * ulp the grid spacing there and f = (|v| - lo) / ulp in [0, 1).  The
- * magnitude becomes lo + ulp when f >= (255.5 - u8) / 256, else lo, with u8
- * the 8 random bits (0 .. 255): over the 256 values of u8 it rounds up
- * floor(256 f + 1/2) times, so the mean result is |v| up to ulp / 512 (an
- * unbiased rounding quantised to 1/256 of the spacing).  The sign is kept. */
+ * ulp the grid spacing there and f = (|v| - lo) / ulp in [0, 1).  With u8
+ * the 8 random bits (0 .. 255) and t = 256 f + u8, the magnitude becomes
+ * lo + ulp when t > 255.5, or when t = 255.5 and u8 is even, else lo.  Over
+ * the 256 values of u8 it rounds up in the nearest whole number of cases to
+ * 256 f, so the mean result is |v| up to ulp / 512.  The tie t = 255.5 needs
+ * 256 f to end in exactly one half, which values with few bits below the
+ * grid (FP32 values: 13 bits below FP16's, 16 below BF16's) reach for 1/32
+ * and 1/256 of values: sending every tie up would move magnitudes away from
+ * zero on average, so ties go up for even u8 (u8 = 255.5 - 256 f: the parity
+ * of the value's own digit) and down for odd.  The sign is kept. */
 static double orc_round_sig_sr(double v, int p, int emin, uint32_t u8) {
     if (v == 0.0 || !isfinite(v)) return v;
     const double a = fabs(v);
@@ -154,7 +159,9 @@ static double orc_round_sig_sr(double v, int p, int emin, uint32_t u8) {
     const double ulp = ldexp(1.0, lead - p + 1);
     const double lo = floor(a / ulp) * ulp;  /* exact: division by a power of two */
     const double f = (a - lo) / ulp;          /* exact */
-    const double m = f >= (255.5 - (double)(u8 & 0xFFu)) / 256.0 ? lo + ulp : lo;
+    const double t = 256.0 * f + (double)(u8 & 0xFFu);  /* exact: below 512, 53 bits */
+    const int up = t > 255.5 || (t == 255.5 && (u8 & 1u) == 0u);
+    const double m = up ? lo + ulp : lo;
     return v < 0.0 ? -m : m;
 }
 
@@ -163,6 +170,17 @@ double orc_round_storage_sr(double v, int storage, uint32_t u8) {
         case 3: return orc_round_sig_sr(v, 8, -126, u8);  /* BF16 */
         case 4: return orc_round_sig_sr(v, 11, -14, u8);  /* FP16 */
         default: return NAN;
+    }
+}
+
+/* The mean over the 256 values of u8 of the stochastic rounding of each of
+ * v[0 .. n-1] (tests of the rounding's bias). */
+void orc_round_storage_sr_mean(const double *v, int64_t n, int storage, double *out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (uint32_t u = 0; u < 256u; ++u) s += orc_round_storage_sr(v[i], storage, u);
+        out[i] = s / 256.0;
     }
 }
 

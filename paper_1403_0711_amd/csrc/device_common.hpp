@@ -160,10 +160,11 @@ __device__ __forceinline__ float bload_f32(__amdgpu_buffer_rsrc_t r, uint32_t of
 //
 // Stochastic rounding takes the 8 low bits u8 of the site's Philox word.
 // With f the value's distance beyond the grid point below its magnitude, in
-// grid spacings, the magnitude goes up to the next grid point when
-// 256 f + u8 >= 255.5: over the 256 values of u8 it goes up in the nearest
-// whole number of cases to 256 f, so the mean stored value is the FP32 value
-// up to 1/512 of a spacing, with no bias toward zero.
+// grid spacings, and t = 256 f + u8, the magnitude goes up to the next grid
+// point when t > 255.5, or t = 255.5 and u8 is even: over the 256 values of
+// u8 it goes up in the nearest whole number of cases to 256 f (ties by the
+// parity of u8), so the mean stored value is the FP32 value up to 1/512 of
+// a spacing, with no drift toward or away from zero.
 // ---------------------------------------------------------------------------
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
@@ -242,20 +243,28 @@ __device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 // Stochastic rounding in hardware: gfx950's v_cvt_sr_bf16_f32 and
-// v_cvt_sr_f16_f32 round with a 32-bit random operand.  With the operand
-// (w << 24) | 2^23 they apply the rule above with u8 = w & 0xFF: for BF16,
-// with d the FP32 word's low 16 bits (f = d / 2^16), the magnitude goes up
-// when d + 256 u8 + 128 >= 2^16; for FP16 the same with the 13 dropped bits
-// (d + 32 u8 + 16 >= 2^13) and on the subnormal grid below 2^-14.  Checked
-// bit for bit against that integer rule on 2^20 values (normal values,
-// values next to powers of two, FP16 subnormals and zeros).  One
-// instruction per value writes one half of the packed result.
-__device__ __forceinline__ uint32_t sr_operand(uint32_t w) { return (w << 24) | 0x800000u; }
+// v_cvt_sr_f16_f32 round with a 32-bit random operand R.  For BF16, with d
+// the FP32 word's low 16 bits, the magnitude goes up when d plus R's top 16
+// bits reaches 2^16; for FP16, with d the 13 dropped bits, when d plus R's
+// top 13 bits reaches 2^13 (and likewise on the subnormal grid below
+// 2^-14).  The rule above, with t = 256 f + u8 and f = d / 2^16 (BF16) or
+// d / 2^13, is up when t > 255.5, and at a tie t = 255.5 when u8 is even:
+// top bits 256 u8 + 128 - (u8 & 1) (BF16) or 32 u8 + 16 - (u8 & 1) (FP16).
+// A tie needs d to end in exactly half of a 1/256 step, which 1/256 (BF16)
+// and 1/32 (FP16) of FP32 values do: sending every tie up would move
+// magnitudes away from zero on average (by 2^-25 of the value, a negative
+// mass term), so ties go by the parity of u8.  Checked bit for bit against
+// the rule on 2^20 values (normal values, values next to powers of two,
+// exact ties, FP16 subnormals and zeros).
+template <int kTieShift>  // 16: BF16, 19: FP16
+__device__ __forceinline__ uint32_t sr_operand(uint32_t w) {
+    return ((w << 24) | 0x800000u) - ((w & 1u) << kTieShift);
+}
 __device__ __forceinline__ uint32_t bf16x2_sr(float a, float b, uint32_t wa, uint32_t wb) {
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     bf16x2 o = {};
-    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(a), sr_operand(wa), false);
-    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(b), sr_operand(wb), true);
+    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(a), sr_operand<16>(wa), false);
+    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(b), sr_operand<16>(wb), true);
     return __builtin_bit_cast(uint32_t, o);
 }
 
@@ -299,8 +308,8 @@ __device__ __forceinline__ _Float16 to_f16(float v) { return (_Float16)fp32_reg(
 __device__ __forceinline__ uint32_t f16x2_sr(float a, float b, uint32_t wa, uint32_t wb) {
     typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
     f16x2 o = {};
-    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(a), sr_operand(wa), false);
-    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(b), sr_operand(wb), true);
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(a), sr_operand<19>(wa), false);
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(b), sr_operand<19>(wb), true);
     return __builtin_bit_cast(uint32_t, o);
 }
 
