@@ -246,8 +246,10 @@ __device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
 // v_cvt_sr_f16_f32 round with a 32-bit random operand R.  For BF16, with d
 // the FP32 word's low 16 bits, the magnitude goes up when d plus R's top 16
 // bits reaches 2^16; for FP16, with d the 13 dropped bits, when d plus R's
-// top 13 bits reaches 2^13 (and likewise on the subnormal grid below
-// 2^-14).  The rule above, with t = 256 f + u8 and f = d / 2^16 (BF16) or
+// top 13 bits reaches 2^13 (on the subnormal grid below 2^-14 the dropped
+// fraction, which then has more bits, is first truncated to 13: there the
+// device rounds down where the rule rounds up for about 1/64 of values,
+// those just above a tie with an odd u8).  The rule above, with t = 256 f + u8 and f = d / 2^16 (BF16) or
 // d / 2^13, is up when t > 255.5, and at a tie t = 255.5 when u8 is even:
 // top bits 256 u8 + 128 - (u8 & 1) (BF16) or 32 u8 + 16 - (u8 & 1) (FP16).
 // A tie needs d to end in exactly half of a 1/256 step, which 1/256 (BF16)
@@ -255,7 +257,7 @@ __device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
 // magnitudes away from zero on average (by 2^-25 of the value, a negative
 // mass term), so ties go by the parity of u8.  Checked bit for bit against
 // the rule on 2^20 values (normal values, values next to powers of two,
-// exact ties, FP16 subnormals and zeros).
+// exact ties, zeros; FP16 subnormals as stated).
 template <int kTieShift>  // 16: BF16, 19: FP16
 __device__ __forceinline__ uint32_t sr_operand(uint32_t w) {
     return ((w << 24) | 0x800000u) - ((w & 1u) << kTieShift);
