@@ -255,18 +255,21 @@ __device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
 // A tie needs d to end in exactly half of a 1/256 step, which 1/256 (BF16)
 // and 1/32 (FP16) of FP32 values do: sending every tie up would move
 // magnitudes away from zero on average (by 2^-25 of the value, a negative
-// mass term), so ties go by the parity of u8.  Checked bit for bit against
-// the rule on 2^20 values (normal values, values next to powers of two,
-// exact ties, zeros; FP16 subnormals as stated).
-template <int kTieShift>  // 16: BF16, 19: FP16
+// mass term), so ties go by the parity of u8.  One operand serves both
+// formats: u8 in the top byte and 0x80 - (u8 & 1) in the next (FP16 reads
+// its top 5 bits, 16 - (u8 & 1)), built by one byte permute (the top byte
+// from w, the next from the sign of w << 15, i.e. 0x00 or 0xFF by u8 & 1)
+// and an xor.  Checked bit for bit against the rule on 2^20 values (normal
+// values, values next to powers of two, exact ties, zeros; FP16 subnormals
+// as stated).
 __device__ __forceinline__ uint32_t sr_operand(uint32_t w) {
-    return ((w << 24) | 0x800000u) - ((w & 1u) << kTieShift);
+    return __builtin_amdgcn_perm(w, w << 15, 0x04080C0Cu) ^ 0x800000u;
 }
 __device__ __forceinline__ uint32_t bf16x2_sr(float a, float b, uint32_t wa, uint32_t wb) {
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     bf16x2 o = {};
-    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(a), sr_operand<16>(wa), false);
-    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(b), sr_operand<16>(wb), true);
+    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(a), sr_operand(wa), false);
+    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(b), sr_operand(wb), true);
     return __builtin_bit_cast(uint32_t, o);
 }
 
@@ -310,8 +313,8 @@ __device__ __forceinline__ _Float16 to_f16(float v) { return (_Float16)fp32_reg(
 __device__ __forceinline__ uint32_t f16x2_sr(float a, float b, uint32_t wa, uint32_t wb) {
     typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
     f16x2 o = {};
-    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(a), sr_operand<19>(wa), false);
-    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(b), sr_operand<19>(wb), true);
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(a), sr_operand(wa), false);
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(b), sr_operand(wb), true);
     return __builtin_bit_cast(uint32_t, o);
 }
 
