@@ -250,13 +250,16 @@ struct lattice {
         // fed through LDS by a producer wave (colour arrays below 2 GiB)
         const size_t bytes = (size_t)vh * esz;
         if (2 * bytes >= ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) {
-            // FP32 with one on-lattice charge set (samples gathered in the
-            // kernel) and no tile or planes set (those name the streaming
+            // FP32 with no tile or planes set (those name the streaming
             // kernel's): the blocked sweep, measured 5-22% faster per sweep
-            // from 448^3 to 768^3; 16-bit storage keeps the streaming sweep
+            // from 448^3 to 768^3.  One on-lattice charge set is gathered in
+            // the kernel; several sets or off-lattice charges read colour 0,
+            // which a measured sweep then stores, from memory (768^3, four
+            // sets of 1.1e6 charges: 0.780 against 0.803 ms per step on the
+            // streaming sweep; off-lattice charges with forces: 0.862
+            // against 0.906).  16-bit storage keeps the streaming sweep
             // (24-32% faster than the blocked one at 512^3 and 768^3)
-            if (auto_blocked && n_sets == 1 && !offl && tile == kTileDefault && slab == 0 && blocked_rows() != 0)
-                return LAT_SWEEP_BLOCKED;
+            if (auto_blocked && tile == kTileDefault && slab == 0 && blocked_rows() != 0) return LAT_SWEEP_BLOCKED;
             return LAT_SWEEP_STREAM;
         }
         // cache-resident boxes from about 200^3 sites: the z-slab kernel keeps

@@ -42,7 +42,7 @@ def _series(bins):
     return bins[..., 0] - bins[..., 1]
 
 
-@pytest.mark.parametrize("variant", ["auto", "stream", "generic"])
+@pytest.mark.parametrize("variant", ["auto", "stream", "generic", "blocked"])
 def test_sets_equal_single_set_lattices(lat_mod, variant):
     print(f"[gpu] charge sets vs single sets {variant}", flush=True)
     shape = (32, 24, 20) if variant != "generic" else (30, 14, 9)

@@ -304,21 +304,26 @@ def test_reduced_precision_parity(lat_mod, storage, variant):
     assert np.abs(g - ref.phi).max() <= 8 * _ulp(np.array([scale]), storage)[0]
 
 
-def test_checkpoint_resume_bit_identical(lat_mod):
-    print("[gpu] checkpoint/resume", flush=True)
+@pytest.mark.parametrize("storage", ["fp32", "bf16sr", "fp16sr"])
+def test_checkpoint_resume_bit_identical(lat_mod, storage):
+    """A chain stopped, read back (field and state) and resumed in a new
+    handle continues bit for bit; a 16-bit field read back is exactly
+    representable, so its upload (rounded to nearest even in every 16-bit
+    format) restores it unchanged."""
+    print(f"[gpu] checkpoint/resume {storage}", flush=True)
     c = workloads.small_neutral(seed=1, L=16, n=12)
-    a = lat_mod.Lattice(c.shape, seed=77)
+    a = lat_mod.Lattice(c.shape, storage, seed=77)
     a.set_charges(c.xyz, c.q)
     a.thermalise(50)
     a.sweep_and_measure(300, 1, 10)
-    b = lat_mod.Lattice(c.shape, seed=77)
+    b = lat_mod.Lattice(c.shape, storage, seed=77)
     b.set_charges(c.xyz, c.q)
     b.thermalise(50)
     b.sweep_and_measure(150, 1, 10)
     t, n, bins = b.get_state()
     phi = b.get_field()
     b.close()
-    r = lat_mod.Lattice(c.shape, seed=77)
+    r = lat_mod.Lattice(c.shape, storage, seed=77)
     r.set_charges(c.xyz, c.q)
     r.set_field(phi)
     r.set_state(t, n, 10, bins)
@@ -507,6 +512,10 @@ def test_default_tuning_resolution(lat_mod):
     lat = lat_mod.Lattice((768, 768, 128), "fp32")  # 2 x 151 MB
     t = lat.tuning()
     assert t["variant"] == "blocked" and t["xcd_order"] == 2 and 1 <= t["tile"] <= 16 and t["planes"] >= 8
+    # several charge sets (samples read colour 0 from memory): the blocked sweep as well
+    lat.set_charge_sets([(np.array([[1, 2, 3]], np.int32), np.array([1.0])),
+                         (np.array([[4, 5, 6]], np.int32), np.array([-1.0]))])
+    assert lat.tuning() == t
     lat.set_tuning(32, 3, False)
     assert lat.tuning() == {"variant": "stream", "planes": 32, "tile": 3, "xcd_order": False}
     lat.set_tuning(0, -1, True)
@@ -659,6 +668,29 @@ def test_graph_replays_match_eager(lat_mod, variant):
     ref = oracle.OracleChain(shape, seed=21, chain=2)
     ref.sweeps(4 * 166)
     assert np.abs(lats[1].get_field() - ref.phi).max() <= 1e-5 * np.abs(ref.phi).max()
+
+
+@pytest.mark.parametrize("variant,storage", [("quad", "bf16sr"), ("stream", "fp16sr"), ("zslab", "bf16sr")])
+def test_graph_replays_match_eager_sr(lat_mod, variant, storage):
+    """Stochastically rounded storage under graph replays: the rounding bits
+    come from the Philox words of the sweep counter read on the device, so
+    replayed chunks store the bits launch-by-launch sweeps store."""
+    print(f"[gpu] graphs {variant} {storage}", flush=True)
+    shape = (64, 24, 20)
+    c = workloads.small_neutral(seed=5, L=min(shape), n=12)
+    lats = []
+    for mode in (0, 2):
+        lat = lat_mod.Lattice(shape, storage, seed=21, chain_id=2)
+        lat.set_variant(variant)
+        lat.use_graphs(mode)
+        lat.set_charges(c.xyz, c.q)
+        lats.append(lat)
+    for step in range(3):
+        for lat in lats:
+            lat.thermalise(70)
+            lat.sweep_and_measure(96, 3, 8)
+        np.testing.assert_array_equal(lats[0].get_field(), lats[1].get_field())
+        np.testing.assert_array_equal(lats[0].get_state()[2], lats[1].get_state()[2])
 
 
 def test_device_noise_full_grid(lat_mod):

@@ -38,7 +38,7 @@ def _charges(shape, n, seed):
     return r, q - q.mean()
 
 
-@pytest.mark.parametrize("variant", ["auto", "generic", "stream"])
+@pytest.mark.parametrize("variant", ["auto", "generic", "stream", "blocked"])
 def test_offlattice_samples_and_forces_match_oracle(lat_mod, variant):
     print(f"[gpu] off-lattice vs oracle {variant}", flush=True)
     shape = (16, 10, 8) if variant != "generic" else (14, 9, 7)
