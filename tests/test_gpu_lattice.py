@@ -272,11 +272,37 @@ def test_reduced_precision_parity(lat_mod, storage, variant):
     # blocked 16-bit: rows of whole 16-byte chunks; fused: rows of 8 quads;
     # generic: quads that straddle rows
     shape = {"blocked": (32, 16, 12), "fused": (64, 16, 12), "generic": (10, 6, 5)}.get(variant, (24, 16, 12))
+    tuning = {"zslab": (5, 0), "stream": (5, 0), "blocked": (5, 4)}.get(variant)  # (the blocked sweep's tile is its rows)
+    _half_sweep_parity_16bit(lat_mod, shape, storage, variant, tuning)
+
+
+@pytest.mark.parametrize("storage", ["bf16sr", "fp16sr"])
+@pytest.mark.parametrize("variant,shape,tuning", [
+    ("stream", (264, 10, 7), (5, 0)),    # 33 quads per row: a partial x tile
+    ("zslab", (264, 10, 7), (3, 2)),
+    ("quad", (40, 24, 9), None),         # several tiles, ragged y and z
+    ("blocked", (96, 37, 23), (5, 4)),   # several tiles and slabs, both ragged
+    ("fused", (80, 21, 13), (5, 0)),     # ragged y rows and z slabs
+    ("generic", (30, 14, 9), None),      # quads straddling rows
+    ("resident", (48, 40, 36), None),    # many passes of the single workgroup
+])
+def test_stochastic_rounding_parity_ragged(lat_mod, storage, variant, shape, tuning):
+    """Stochastically rounded storage on boxes with ragged tiles, slabs and
+    rows, half-sweep by half-sweep against the oracle (as above)."""
+    print(f"[gpu] stochastic rounding parity {storage} {variant} {shape}", flush=True)
+    _half_sweep_parity_16bit(lat_mod, shape, storage, variant, tuning)
+
+
+def _half_sweep_parity_16bit(lat_mod, shape, storage, variant, tuning):
+    """One sweep from a common seeded field on the given kernel and tuning,
+    each colour's new values against the oracle's values from the field
+    the GPU read (rounded as the format rounds), then 30 more sweeps against
+    the oracle's chain."""
     lx, ly, lz = shape
     lat = lat_mod.Lattice(shape, storage, seed=5)
     lat.set_variant(variant)
-    if variant in ("zslab", "stream", "blocked"):  # (the blocked sweep's tile is its rows per tile)
-        lat.set_tuning(5, 0 if variant != "blocked" else 4, xcd_order=True)
+    if tuning is not None:
+        lat.set_tuning(tuning[0], tuning[1], xcd_order=True)
     ref = oracle.OracleChain(shape, storage, seed=5)
     rng = np.random.default_rng(0)
     start = rng.standard_normal(shape[::-1]).astype(np.float32) * 0.5
