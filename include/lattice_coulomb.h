@@ -139,6 +139,9 @@ int set_charges(lattice_t *lat, int64_t n, const int32_t *xyz, const double *q);
  * set); xyz (3 int32 per charge) and q (one double per charge) hold the sets
  * one after the other.  Each set is aggregated per site as in set_charges.
  * Resets the bins of every set; the field and sweep counter are kept.
+ * Up to four sets are gathered inside the blocked sweep (one walk over
+ * lists holding every set's sites); more sets, or other kernels, gather
+ * each sample from memory.
  * set_charges is the case n_sets = 1.  Errors as set_charges; LAT_ERR_ARG
  * also for n_sets out of range, a negative count, or n_sets > 1 with the
  * variant LAT_SWEEP_RESIDENT (which measures one set). */

@@ -287,7 +287,12 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
         // it).  Bounds and cursors are kept in vector registers.
         uint32_t first[2] = {0u, 0u}, kbase[2] = {0u, 0u}, qbase[2] = {0u, 0u}, pend[2] = {0u, 0u}, cur[2];
         asm volatile("v_mov_b32 %0, 0\n\tv_mov_b32 %1, 0" : "=v"(cur[0]), "=v"(cur[1]));
-        double gx[2] = {0.0, 0.0}, gy[2] = {0.0, 0.0};
+        // per colour and charge set (the entry's set in bits 26-27 of its key)
+        double gx[2][kBlockedMaxSets], gy[2][kBlockedMaxSets];
+#pragma unroll
+        for (uint32_t c = 0; c < 2u; ++c)
+#pragma unroll
+            for (uint32_t k = 0; k < kBlockedMaxSets; ++k) gx[c][k] = gy[c][k] = 0.0;
         const uint32_t a_stage = lds_addr(stage), sbytes = blk_stage_bytes(a.g_cap);
         const uint32_t kbytes = 4u * a.g_cap + 64u, qbytes = 8u * a.g_cap + 64u;  // per array
         auto stage_part = [&](uint32_t p) {
@@ -329,7 +334,7 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
                 const uint32_t rc = cur[c] - first[c];
                 const uint32_t e = first[c] + rc + ((lane - rc) & 63u);  // this lane's entry of the window
                 const uint32_t key = e < pend[c] ? lds_read_u32(ak + 4u * (e - kbase[c])) : 0xFFFFFFFFu;
-                const bool hit = (key >> 16) == s;
+                const bool hit = ((key >> 16) & kBlockedStepMask) == s;
                 const uint32_t nhit = (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(hit));
                 if (hit) {
                     float v;
@@ -337,8 +342,13 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
                     const uint32_t k = 8u * (e - qbase[c]);
                     lds_read_entry<St>(aslot + (key & 0xFFFFu), aq + k, as + k, v, Qi, Si);
                     const double d = (double)v;
-                    gx[c] = fma(Qi, d, gx[c]);
-                    gy[c] = fma(Si, d * d, gy[c]);
+                    const uint32_t set = key >> 26;
+#pragma unroll
+                    for (uint32_t k = 0; k < kBlockedMaxSets; ++k)
+                        if (set == k) {
+                            gx[c][k] = fma(Qi, d, gx[c][k]);
+                            gy[c][k] = fma(Si, d * d, gy[c][k]);
+                        }
                 }
                 cur[c] += nhit;
                 if (nhit < 64u) break;
@@ -377,13 +387,18 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
             }
         }
         if (gather) {
+#pragma unroll
             for (uint32_t c = 0; c < 2u; ++c) {
                 double* part = c == 0u ? a.part0 : a.part1;
                 if (!part) continue;
-                const double x = wave_sum(gx[c]), y = wave_sum(gy[c]);
-                if (lane == 0) {
-                    part[2 * tile] = x;
-                    part[2 * tile + 1] = y;
+#pragma unroll
+                for (uint32_t k = 0; k < kBlockedMaxSets; ++k) {
+                    if (k >= a.g_sets) break;
+                    const double x = wave_sum(gx[c][k]), y = wave_sum(gy[c][k]);
+                    if (lane == 0) {
+                        part[(size_t)k * a.g_set_stride + 2u * tile] = x;
+                        part[(size_t)k * a.g_set_stride + 2u * tile + 1u] = y;
+                    }
                 }
             }
         }
@@ -621,10 +636,13 @@ hipError_t launch_blocked_sweep(const BlockedArgs& a, hipStream_t stream) {
         !blocked_geometry(a.lh, esz, a.kty, a.ring, &sh, a.g_key ? a.g_cap : 0u))
         return hipErrorInvalidValue;
     if (a.g_key && (!a.g_off || !a.g_Q || !a.g_S || a.g_cap == 0 || a.g_cap % 64u != 0 ||
-                    (uint64_t)a.g_n * 8u >= (1ull << 32) || (a.zc + 2u) > 0xFFFFu || a.g_parts == 0 ||
+                    (uint64_t)a.g_n * 8u >= (1ull << 32) || (a.zc + 2u) > kBlockedStepMask || a.g_parts == 0 ||
                     a.g_parts > kBlockedMaxParts || a.g_stride == 0 || (uint64_t)a.g_parts * a.g_stride < a.zc + 1u))
         return hipErrorInvalidValue;
     if ((a.part0 || a.part1) && !a.g_key) return hipErrorInvalidValue;
+    if (a.g_key && (a.g_sets < 1 || a.g_sets > kBlockedMaxSets || (a.g_sets > 1 && a.g_set_stride == 0) ||
+                    (a.g_sets > 1 && a.fin.part)))
+        return hipErrorInvalidValue;
     if (a.fin.part && (!a.fin.bins || !a.fin.last_xy || a.fin.n == 0 || a.fin.bin_size == 0))
         return hipErrorInvalidValue;
     // 32-bit byte offsets: each colour array below 2 GiB

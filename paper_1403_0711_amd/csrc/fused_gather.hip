@@ -37,19 +37,22 @@ bool fused_gather_current(const lattice* L) {
     return L->fg.tried && L->fg.variant == ft.variant && L->fg.tile == ft.tile && L->fg.slab == ft.slab;
 }
 
-// Whether samples of this lattice are gathered inside the sweep kernel: one
-// on-lattice charge set and the lists built for the current kernel and tiling.
+// Whether samples of this lattice are gathered inside the sweep kernel:
+// on-lattice charges (one set; the blocked sweep up to kBlockedMaxSets) and
+// the lists built for the current kernel, tiling and sets.
 bool fused_gather_on(const lattice* L) {
-    return L->fg.ready && L->n_sets == 1 && !L->offl && fused_gather_current(L) && L->fg.variant != 0;
+    return L->fg.ready && L->fg.sets == L->n_sets && !L->offl && fused_gather_current(L) && L->fg.variant != 0;
 }
 
 // Lists of the blocked sweep's tiling: per tile (by + nby bz, kty rows, zc
 // planes) the charged colour-0 sites, gathered by its producer wave in step
 // z - z0 + 2 from a colour-0 slot (row y - y0 + 1), then the charged
 // colour-1 sites, gathered in step z - z0 + 1 from an old-plane slot (row
-// y - y0 + 2), each sorted by step.  Three sample buffers of partials.
+// y - y0 + 2), each sorted by step, the entries of every charge set in one
+// list (the set in the key's bits 26-27).  Three sample buffers of
+// partials, each the colour-0 then the colour-1 pairs of set 0, then set 1's.
 static int blocked_gather_prepare(lattice* L, uint32_t kty, uint32_t zc) {
-    if (kty == 0 || zc == 0 || zc + 2u > 0xFFFFu) return LAT_OK;
+    if (kty == 0 || zc == 0 || zc + 2u > kBlockedStepMask) return LAT_OK;
     const uint32_t nq = L->lh / 4, ly = (uint32_t)L->ly, lz = (uint32_t)L->lz;
     const uint32_t nby = (ly + kty - 1) / kty, nbz = (lz + zc - 1) / zc;
     const uint32_t tiles = nby * nbz;
@@ -58,10 +61,13 @@ static int blocked_gather_prepare(lattice* L, uint32_t kty, uint32_t zc) {
     if ((uint64_t)(kty + 4u) * rb > 0xFFFFu) return LAT_OK;  // slot offsets in 16 bits
     const lattice::HostCharges& hc = *L->host_charges;
     const size_t n = hc.site.size();
+    const uint32_t sets = (uint32_t)hc.set_off.size() - 1u;
     std::vector<uint64_t> key_of(n);
     std::vector<uint32_t> tile_of(n), j_of(n), packed_of(n);
     size_t n0 = 0;
+    uint32_t set = 0;
     for (size_t i = 0; i < n; ++i) {
+        while (i >= hc.set_off[set + 1]) ++set;
         const uint32_t c = hc.site[i] >= L->vh ? 1u : 0u;
         const uint32_t j = hc.site[i] - c * L->vh;
         const uint32_t z = j / plane, rem = j - z * plane, y = rem / L->lh, jx = rem - y * L->lh;
@@ -70,7 +76,7 @@ static int blocked_gather_prepare(lattice* L, uint32_t kty, uint32_t zc) {
         j_of[i] = j;
         const uint32_t row = y - by * kty + 1u + c;
         const uint32_t step = z - bz * zc + 2u - c;
-        packed_of[i] = (step << 16) | (row * rb + 16u + jx * (uint32_t)L->esz);
+        packed_of[i] = (set << 26) | (step << 16) | (row * rb + 16u + jx * (uint32_t)L->esz);
         key_of[i] = ((uint64_t)c * tiles + tile_of[i]) * (zc + 2u) + step;
         n0 += c ? 0u : 1u;
     }
@@ -101,7 +107,7 @@ static int blocked_gather_prepare(lattice* L, uint32_t kty, uint32_t zc) {
             const size_t c = ct / tiles, t = ct % tiles;
             std::fill(cnt.begin(), cnt.end(), 0u);
             for (uint32_t k = off[c * (tiles + 1) + t]; k < off[c * (tiles + 1) + t + 1]; ++k)
-                ++cnt[((key[k] >> 16) - 1u) / stride];
+                ++cnt[(((key[k] >> 16) & kBlockedStepMask) - 1u) / stride];
             for (uint32_t x : cnt) longest = std::max(longest, x);
         }
         return std::max<uint32_t>(64u, (longest + 63u) / 64u * 64u);
@@ -132,7 +138,7 @@ static int blocked_gather_prepare(lattice* L, uint32_t kty, uint32_t zc) {
         const uint32_t b = off[c * (tiles + 1) + t], e = off[c * (tiles + 1) + t + 1];
         uint32_t k = b;
         for (uint32_t p = 0; p < parts; ++p) {
-            while (k < e && ((key[k] >> 16) - 1u) / stride < p) ++k;
+            while (k < e && (((key[k] >> 16) & kBlockedStepMask) - 1u) / stride < p) ++k;
             off[pbase + ct * np1 + p] = k;
         }
         off[pbase + ct * np1 + parts] = e;
@@ -143,7 +149,7 @@ static int blocked_gather_prepare(lattice* L, uint32_t kty, uint32_t zc) {
     g.d_j = static_cast<uint32_t*>(L->mem.alloc(std::max<size_t>(n, 1) * 4));
     g.d_Q = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
     g.d_S = static_cast<double*>(L->mem.alloc(std::max<size_t>(n, 1) * 8));
-    g.d_part = static_cast<double*>(L->mem.alloc((size_t)tiles * 96));
+    g.d_part = static_cast<double*>(L->mem.alloc((size_t)tiles * 96 * sets));
     L->fg = g;
     if (!g.d_off || !g.d_key || !g.d_j || !g.d_Q || !g.d_S || !g.d_part) {
         const lattice::FusedGather keep = L->fg;
@@ -166,6 +172,7 @@ static int blocked_gather_prepare(lattice* L, uint32_t kty, uint32_t zc) {
     }
     L->fg.ready = true;
     L->fg.nbuf = 3;
+    L->fg.sets = sets;
     L->fg.blocks = tiles;
     L->fg.n = (uint32_t)n;
     L->fg.cap = cap;
@@ -182,13 +189,15 @@ static uint32_t workgroups_per_cu(uint32_t lds, uint32_t waves) {
 
 // Build the per-tile lists of the fused gather for the current tiling (host
 // sort of the aggregated list, one upload); outside any capture.  Without
-// them (other kernels, several or off-lattice sets, a tile list too long to
+// them (other kernels, off-lattice charges, several sets on another kernel
+// than the blocked sweep or more than it serves, a tile list too long to
 // stage in LDS without costing the sweep kernel a resident workgroup,
 // allocation failure) the samples go through the separate gather.
 int fused_gather_prepare(lattice* L) {
     const FusedTiling ft = fused_tiling(L);
-    if (ft.variant == 0 || L->n_sets != 1 || L->offl || !L->host_charges ||
-        L->host_charges->site.size() != L->n_sites)
+    if (ft.variant == 0 || L->offl || !L->host_charges || L->host_charges->site.size() != L->n_sites ||
+        L->host_charges->set_off.size() != (size_t)L->n_sets + 1u ||
+        (L->n_sets != 1 && ft.variant != LAT_SWEEP_BLOCKED) || L->n_sets > kBlockedMaxSets)
         return LAT_OK;
     if (fused_gather_current(L)) return LAT_OK;
     fused_gather_release(L);
@@ -296,12 +305,19 @@ int fused_gather_prepare(lattice* L) {
 int enqueue_blocked_tail(lattice* L, hipStream_t stream, bool rec_prev, uint32_t m_prev, bool open_last,
                          uint32_t m_last, const uint32_t* mdev) {
     const lattice::FusedGather& g = L->fg;
-    auto buf = [&](uint32_t k) { return g.d_part + (size_t)(k % 3u) * 4 * g.blocks; };
+    auto buf = [&](uint32_t k) { return g.d_part + (size_t)(k % 3u) * 4 * g.blocks * g.sets; };
     hipError_t e = hipSuccess;
     if (rec_prev)
-        e = launch_finalize_measure(buf(m_prev), 2 * g.blocks, 1u, L->d_bins, m_prev, (uint32_t)L->bin_size, mdev,
-                                    L->last_xy(), (uint32_t)L->bin_cap, stream);
-    if (e == hipSuccess && open_last) {
+        e = launch_finalize_measure(buf(m_prev), 2 * g.blocks, g.sets, L->d_bins, m_prev, (uint32_t)L->bin_size,
+                                    mdev, L->last_xy(), (uint32_t)L->bin_cap, stream);
+    if (e == hipSuccess && open_last && g.sets > 1) {
+        // several sets: the last sample from memory by the separate gather
+        // (the call's last sweep stored colour 0), into its own partials
+        MeasureArgs a{L->field, L->c1cur(), L->vh, L->d_site, L->d_Q, L->d_S, L->n_sites, L->d_partials,
+                      L->d_bins, m_last, (uint32_t)L->bin_size, mdev, L->last_xy(), L->storage, L->meas_blocks,
+                      L->d_set_off, L->n_sets, (uint32_t)L->bin_cap};
+        e = launch_measure(a, stream);
+    } else if (e == hipSuccess && open_last) {
         GatherTailArgs a{L->c1cur(), L->storage, g.blocks, g.d_off + g.blocks + 1, g.d_j, g.d_Q, g.d_S,
                          buf(m_last) + 2 * (size_t)g.blocks};
         e = launch_gather_tail(a, stream);

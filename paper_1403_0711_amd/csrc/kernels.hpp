@@ -104,6 +104,10 @@ hipError_t prepare_fused_sweep();  // once, before fused launches and outside ca
 
 // Parts the blocked sweep's fused-gather lists are staged in, at most.
 constexpr uint32_t kBlockedMaxParts = 8;
+// Charge sets the blocked sweep's fused gather serves in one walk, at most
+// (an entry's set in bits 26-27 of its key, the step in bits 16-25).
+constexpr uint32_t kBlockedMaxSets = 4;
+constexpr uint32_t kBlockedStepMask = 0x3FFu;
 
 // Both half-sweeps of sweep t in one pass with colour 0 kept in LDS (the
 // streaming temporally blocked sweep): colour 1 read from c1_in, written to
@@ -124,14 +128,15 @@ struct BlockedArgs {
     const uint32_t* tdev;  // if set, h0 += 2 * tdev[0]
     int storage;
     // fused gather (g_key set): per tile (by + nby bz) a list of its charged
-    // colour-0 sites and one of its charged colour-1 sites, each sorted by the
-    // step that gathers it; entry key = step << 16 | byte offset in a ring
-    // slot (colour 0: a colour-0 slot; colour 1: an old-plane slot).  g_cap
-    // entries of each list are staged in LDS (a multiple of 64).  part0: the
-    // (X, Y) pair per tile of this sweep's colour-0 sites (null: this sweep is
-    // not sampled); part1: the pair of the previous sweep's colour-1 sites
-    // (null: it was not sampled).  fin: the sample two sweeps back, recorded
-    // by workgroup 0.
+    // colour-0 sites and one of its charged colour-1 sites (of all g_sets
+    // charge sets), each sorted by the step that gathers it; entry key =
+    // set << 26 | step << 16 | byte offset in a ring slot (colour 0: a
+    // colour-0 slot; colour 1: an old-plane slot).  g_cap entries of each
+    // list are staged in LDS (a multiple of 64).  part0: the (X, Y) pair per
+    // tile of this sweep's colour-0 sites of set 0 (null: this sweep is not
+    // sampled), set k's at part0 + k g_set_stride; part1: likewise the pairs
+    // of the previous sweep's colour-1 sites (null: it was not sampled).
+    // fin: the sample two sweeps back, recorded by workgroup 0 (one set).
     const uint32_t* g_off = nullptr;
     const uint32_t* g_key = nullptr;
     const double* g_Q = nullptr;
@@ -141,6 +146,7 @@ struct BlockedArgs {
     // steps 1 + p g_stride .. (p + 1) g_stride); g_off holds, per colour c
     // and tile t, the g_parts + 1 part bounds at (c tiles + t)(g_parts + 1)
     uint32_t g_parts = 1, g_stride = 0;  // g_parts <= kBlockedMaxParts
+    uint32_t g_sets = 1, g_set_stride = 0;  // g_sets <= kBlockedMaxSets; doubles between sets' partials
     double* part0 = nullptr;
     double* part1 = nullptr;
     SampleFinalize fin;

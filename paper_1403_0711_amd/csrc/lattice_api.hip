@@ -42,9 +42,11 @@ int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint3
         a.xcd_order = L->resolved_xcd(v);
         a.tdev = tdev;
         a.storage = L->storage;
+        bool record_after = false;  // several sets: the sample recorded by its own launch
         if (fs && (fs->open || fs->finish || fs->record)) {  // the fused gather's part in this sweep
             const lattice::FusedGather& g = L->fg;
-            auto buf = [&](uint32_t k) { return g.d_part + (size_t)(k % 3u) * 4 * g.blocks; };
+            // sample k's buffer: per set, the colour-0 then the colour-1 pairs of every tile
+            auto buf = [&](uint32_t k) { return g.d_part + (size_t)(k % 3u) * 4 * g.blocks * g.sets; };
             if (fs->open || fs->finish) {
                 a.g_off = g.d_off + 2 * ((size_t)g.blocks + 1);  // the part bounds
                 a.g_key = g.d_key;
@@ -54,11 +56,14 @@ int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint3
                 a.g_cap = g.cap;
                 a.g_parts = g.parts;
                 a.g_stride = g.stride;
+                a.g_sets = g.sets;
+                a.g_set_stride = 4 * g.blocks;
                 a.ring = L->blocked_ring(g.cap);
             }
             if (fs->open) a.part0 = buf(fs->m + 1u);                               // colour-0 pairs
             if (fs->finish) a.part1 = buf(fs->m) + 2 * (size_t)g.blocks;           // colour-1 pairs
-            if (fs->record) {
+            record_after = fs->record && g.sets > 1;
+            if (fs->record && g.sets == 1) {
                 a.fin.part = buf(fs->m_rec);
                 a.fin.n = 2 * g.blocks;
                 a.fin.bins = L->d_bins;
@@ -70,6 +75,12 @@ int enqueue_sweep_ex(lattice* L, hipStream_t stream, const uint32_t* tdev, uint3
         }
         e = launch_blocked_sweep(a, stream);
         if (e == hipSuccess) L->alt_current = !L->alt_current;
+        if (e == hipSuccess && record_after) {
+            const lattice::FusedGather& g = L->fg;
+            e = launch_finalize_measure(g.d_part + (size_t)(fs->m_rec % 3u) * 4 * g.blocks * g.sets, 2 * g.blocks,
+                                        g.sets, L->d_bins, fs->m_rec, (uint32_t)L->bin_size, fs->mdev,
+                                        L->last_xy(), (uint32_t)L->bin_cap, stream);
+        }
     } else if (v == LAT_SWEEP_FUSED) {
         void* out = L->alt_current ? L->c1main() : L->c1alt;
         FusedArgs a{L->field, L->c1cur(), out, L->lh, (uint32_t)L->ly, (uint32_t)L->lz, L->vh, h0,
@@ -729,11 +740,12 @@ int lattice_set_charge_sets(lattice_t* L, int64_t n_sets, const int64_t* counts,
     L->d_lastxy = d_xy;
     release_offlattice(L);
     fused_gather_release(L);
-    if (n_sets == 1) {
+    if (n_sets <= (int64_t)kBlockedMaxSets) {  // kept for the fused gather's lists
         auto hc = std::make_shared<lattice::HostCharges>();
         hc->site.swap(all.site);
         hc->Q.swap(all.Q);
         hc->S.swap(all.S);
+        hc->set_off.swap(off);
         L->host_charges = std::move(hc);
     } else {
         L->host_charges.reset();

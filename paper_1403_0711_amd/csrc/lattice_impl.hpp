@@ -87,6 +87,7 @@ struct lattice {
     struct HostCharges {
         std::vector<uint32_t> site;
         std::vector<double> Q, S;
+        std::vector<uint32_t> set_off;  // n_sets + 1 offsets into site / Q / S
     };
     std::shared_ptr<const HostCharges> host_charges;
     // fused gather of the streaming kernel: the list split by colour and
@@ -105,6 +106,7 @@ struct lattice {
         // blocked: lists staged in `parts` parts of `stride` steps; their
         // bounds follow the cumulative offsets in d_off
         uint32_t parts = 1, stride = 0;
+        uint32_t sets = 1;  // charge sets in the lists (blocked: up to kBlockedMaxSets)
         uint32_t* d_off = nullptr;
         uint32_t* d_key = nullptr;  // staged key: walk step << 16 | ring-slot byte offset
         uint32_t* d_j = nullptr;    // the site in its colour array (for gather_tail)

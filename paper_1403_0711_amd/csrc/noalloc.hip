@@ -47,8 +47,12 @@ static int scratch_address(int dev, void** out) {
 
 // Bytes of partial sums a measured sweep of L uses on its current path.
 static size_t partial_bytes(const lattice* L) {
-    if (fused_gather_on(L)) return (size_t)L->fg.blocks * 32u * L->fg.nbuf;  // samples x two colours x (X, Y)
-    return (size_t)L->meas_blocks * 16u * (L->offl ? 1u : L->n_sets);
+    const size_t separate = (size_t)L->meas_blocks * 16u * (L->offl ? 1u : L->n_sets);
+    if (!fused_gather_on(L)) return separate;
+    // samples x sets x two colours x (X, Y); with several sets a call's last
+    // sample goes through the separate gather as well
+    const size_t fused = (size_t)L->fg.blocks * 32u * L->fg.nbuf * L->fg.sets;
+    return L->fg.sets > 1 ? std::max(fused, separate) : fused;
 }
 
 }  // namespace latcoul

@@ -435,3 +435,86 @@ def test_blocked_fused_gather_full_size(lat_mod):
     b.close()
     qa = float(np.sum(np.abs(q)))
     assert np.abs(sa[2] - sb[2]).max() <= 1e-12 * (qa * 10.0) ** 2
+
+
+def _sets_of(shape, seed):
+    """Four charge sets: random sites with co-located duplicates, a second
+    random set, an empty set, and one that shares sites with the first."""
+    xyz, q = _charges(shape, 200, seed)
+    xyz2, q2 = _charges(shape, 120, seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    xyz4 = np.concatenate([xyz[:50], xyz2[:10]])
+    q4 = rng.standard_normal(len(xyz4))
+    return [(xyz, q), (xyz2, q2), (np.zeros((0, 3), np.int32), np.zeros(0)), (xyz4, q4)]
+
+
+@pytest.mark.parametrize("shape,storage,planes,rows,xcd", [
+    ((64, 24, 20), "fp32", 0, -1, 2),
+    ((200, 37, 33), "fp32", 7, 5, 2),   # ragged rows and slabs
+    ((64, 24, 20), "fp16sr", 4, 6, 0),
+    ((96, 37, 23), "bf16", 2, 7, 1),
+])
+def test_blocked_fused_gather_charge_sets(lat_mod, shape, storage, planes, rows, xcd):
+    """Several charge sets (up to four) gathered in the blocked sweep's one
+    walk, each entry tagged with its set: fields bit-identical to the
+    separate gather's chain, every set's samples equal to its samples there
+    (FP64 sums in another order), the empty set's samples zero, across a
+    graph chunk and the eager sweeps after it."""
+    print(f"[gpu] blocked fused gather, charge sets {shape} {storage} planes={planes} rows={rows}", flush=True)
+    sets = _sets_of(shape, 21)
+    a = lat_mod.Lattice(shape, storage, seed=3, chain_id=5)
+    a.set_variant("blocked")
+    a.set_tuning(planes, rows, xcd)
+    b = lat_mod.Lattice(shape, storage, seed=3, chain_id=5)
+    b.set_variant("zslab")
+    for lat in (a, b):
+        lat.set_charge_sets(sets)
+        lat.thermalise(5)
+        lat.sweep_and_measure(40, 1, 1)
+    assert a.sample_path() == "fused" and b.sample_path() == "separate"
+    fa = a.get_field()
+    np.testing.assert_array_equal(fa, b.get_field())
+    sa, sb = a.get_state(), b.get_state()
+    assert sa[:2] == sb[:2] == (45, 40) and sa[2].shape == (4, 40, 2)
+    for k, (xyz, q) in enumerate(sets):
+        tol = 1e-12 * max(1.0, _scale(q, fa))
+        assert np.abs(sa[2][k] - sb[2][k]).max() <= tol, k
+        ma, mb = a.energy_estimate(charge_set=k)[0], b.energy_estimate(charge_set=k)[0]
+        assert abs(ma - mb) <= tol, k
+    assert np.all(sa[2][2] == 0.0)
+    # the last sample of set 0 against the oracle's gather of the read-back field
+    ref = oracle.OracleChain(shape)
+    ref.phi = fa.astype(np.float64)
+    ref.set_charges(*sets[0])
+    X, Y = ref.gather()
+    O = sa[2][0][-1]
+    assert abs((O[0] - O[1]) - (X * X - Y)) <= 1e-10 * _scale(sets[0][1], fa)
+
+
+def test_blocked_fused_gather_charge_sets_in_parts_and_limits(lat_mod, monkeypatch):
+    """Four sets whose lists are staged in several parts give the separate
+    gather's samples; five sets (more than the walk serves) keep the
+    separate gather."""
+    print("[gpu] blocked fused gather, charge sets in parts; five sets", flush=True)
+    shape = (64, 24, 20)
+    monkeypatch.setenv("LATCOUL_GATHER_PART_CAP", "64")
+    sets = [_charges(shape, 1200, s) for s in (5, 6, 7)] + [(np.zeros((0, 3), np.int32), np.zeros(0))]
+    a = lat_mod.Lattice(shape, seed=8, chain_id=1)
+    a.set_variant("blocked")
+    a.set_tuning(11, 4, 1)
+    b = lat_mod.Lattice(shape, seed=8, chain_id=1)
+    b.set_variant("zslab")
+    for lat in (a, b):
+        lat.set_charge_sets(sets)
+        lat.sweep_and_measure(30, 1, 1)
+    assert a.sample_path() == "fused" and a.gather_parts()[0] >= 2
+    fa = a.get_field()
+    np.testing.assert_array_equal(fa, b.get_field())
+    sa, sb = a.get_state()[2], b.get_state()[2]
+    for k, (xyz, q) in enumerate(sets):
+        assert np.abs(sa[k] - sb[k]).max() <= 1e-12 * max(1.0, _scale(q, fa)), k
+    five = lat_mod.Lattice(shape, seed=8, chain_id=1)
+    five.set_variant("blocked")
+    five.set_charge_sets(sets + [sets[0]])
+    five.sweep_and_measure(4, 1, 1)
+    assert five.sample_path() == "separate"
