@@ -326,7 +326,10 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
             stage_part(0u);
         }
         // the entries of list c gathered in step s, from ring slot `slot`
-        auto walk = [&](uint32_t c, uint32_t s, const unsigned char* slot) {
+        // (the colour a compile-time constant: the accumulators stay in
+        // registers, where a run-time index would put them in scratch)
+        auto walk = [&](auto colour, uint32_t s, const unsigned char* slot) __attribute__((always_inline)) {
+            constexpr uint32_t c = decltype(colour)::value;
             const uint32_t ak = a_stage + c * sbytes;
             const uint32_t aq = ak + kbytes, as = aq + qbytes;
             const uint32_t aslot = lds_addr(slot);
@@ -342,13 +345,21 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
                     const uint32_t k = 8u * (e - qbase[c]);
                     lds_read_entry<St>(aslot + (key & 0xFFFFu), aq + k, as + k, v, Qi, Si);
                     const double d = (double)v;
-                    const uint32_t set = key >> 26;
+                    if (a.g_sets == 1u) {
+                        gx[c][0] = fma(Qi, d, gx[c][0]);
+                        gy[c][0] = fma(Si, d * d, gy[c][0]);
+                    } else {
+                        // every set's pair takes the entry, with weights zero
+                        // but for its own set (adding an exact zero): no index
+                        // by the set, so the pairs stay in registers
+                        const uint32_t set = key >> 26;
 #pragma unroll
-                    for (uint32_t k = 0; k < kBlockedMaxSets; ++k)
-                        if (set == k) {
-                            gx[c][k] = fma(Qi, d, gx[c][k]);
-                            gy[c][k] = fma(Si, d * d, gy[c][k]);
+                        for (uint32_t k = 0; k < kBlockedMaxSets; ++k) {
+                            const bool mine = set == k;
+                            gx[c][k] = fma(mine ? Qi : 0.0, d, gx[c][k]);
+                            gy[c][k] = fma(mine ? Si : 0.0, d * d, gy[c][k]);
                         }
+                    }
                 }
                 cur[c] += nhit;
                 if (nhit < 64u) break;
@@ -364,8 +375,8 @@ __global__ __launch_bounds__(kBlkThreads) void sweep_blocked(BlockedArgs a) {
                 // step s-1).  In step 1, before any new plane load, part 0
                 // and every plane requested so far have landed.
                 if (s == 1u) wait_vm_lgkm0<0>();
-                if (a.part1) walk(1u, s, oring + ((s + 1u) % kRing) * oslot);
-                if (a.part0 && s >= 2u) walk(0u, s, cring + ((s - 1u) % 3u) * cslot);
+                if (a.part1) walk(std::integral_constant<uint32_t, 1u>(), s, oring + ((s + 1u) % kRing) * oslot);
+                if (a.part0 && s >= 2u) walk(std::integral_constant<uint32_t, 0u>(), s, cring + ((s - 1u) % 3u) * cslot);
                 if (s % a.g_stride == 0u && s <= n) {  // the walks' LDS reads have completed
                     stage_part(s / a.g_stride);
                     restaged = true;

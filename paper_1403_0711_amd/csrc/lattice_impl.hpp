@@ -254,12 +254,13 @@ struct lattice {
         if (2 * bytes >= ((size_t)256 << 20) && bytes < ((size_t)1 << 31)) {
             // FP32 with no tile or planes set (those name the streaming
             // kernel's): the blocked sweep, measured 5-22% faster per sweep
-            // from 448^3 to 768^3.  One on-lattice charge set is gathered in
-            // the kernel; several sets or off-lattice charges read colour 0,
-            // which a measured sweep then stores, from memory (768^3, four
-            // sets of 1.1e6 charges: 0.780 against 0.803 ms per step on the
-            // streaming sweep; off-lattice charges with forces: 0.862
-            // against 0.906).  16-bit storage keeps the streaming sweep
+            // from 448^3 to 768^3.  Up to four on-lattice charge sets are
+            // gathered in the kernel; more sets or off-lattice charges read
+            // colour 0, which a measured sweep then stores, from memory
+            // (768^3, four sets of 1.1e6 charges through the separate
+            // gather: 0.780 against 0.803 ms per step on the streaming
+            // sweep; off-lattice charges with forces: 0.862 against 0.906).
+            // 16-bit storage keeps the streaming sweep
             // (24-32% faster than the blocked one at 512^3 and 768^3)
             if (auto_blocked && tile == kTileDefault && slab == 0 && blocked_rows() != 0) return LAT_SWEEP_BLOCKED;
             return LAT_SWEEP_STREAM;
