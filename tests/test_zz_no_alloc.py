@@ -91,6 +91,25 @@ def test_noalloc_matches_sweep_and_measure(lat_mod):
     b.close()
 
 
+def test_noalloc_blocked_charge_sets(lat_mod):
+    """Several charge sets gathered inside the blocked sweep (the call's
+    last sample through the separate gather): the allocation-free entry
+    point gives the same field and samples, on two calls in a row."""
+    print("[gpu] no-alloc: blocked sweep, three charge sets gathered in the sweep", flush=True)
+    shape = (64, 24, 20)
+    sets = [_charges(shape, 200, s) for s in (6, 7, 8)]
+    a, b = _pair(lat_mod, shape, "blocked", sets, seed=24, tuning=(7, 4, 1))
+    before = a._mem.n_alloc
+    for n in (20, 9):
+        a.sweep_and_measure_noalloc(n, 1, 2)
+        b.sweep_and_measure(n, 1, 2)
+        assert a._mem.n_alloc == before
+        assert a.sample_path() == b.sample_path() == "fused"
+        _compare(a, b)
+    a.close()
+    b.close()
+
+
 def test_noalloc_resident_and_refusals(lat_mod):
     print("[gpu] no-alloc: resident kernel and refusals", flush=True)
     shape = (16, 16, 16)
