@@ -254,8 +254,9 @@ int lattice_set_variant(lattice_t *lat, int variant);
  * they divide the rows, else 32-quad tiles, with non-temporal stores where a
  * colour array is at least 256 MiB: tiles 9 / 6 / 0 / 3; tile 7 for the
  * z-slab kernel the library chose; tile 0 for the other kernels): 0..7 for LAT_SWEEP_ZSLAB (workgroup tile width x rows and
- * register budget), 0..9 for LAT_SWEEP_STREAM (tile width 128..512 sites,
- * rows, depth of the LDS plane ring, non-temporal stores); xcd_order, the
+ * register budget), 0..10 for LAT_SWEEP_STREAM (tile width 128..512 sites,
+ * or 64 for tile 10, rows, depth of the LDS plane ring, non-temporal
+ * stores); xcd_order, the
  * order of workgroups over the chip's 8 XCDs: 0 the hardware's round-robin
  * order, 1 a contiguous run of tiles per XCD, 2 (streaming kernel; 1 for
  * the others) a band of each slab's tiles per XCD with all XCDs moving
@@ -263,7 +264,7 @@ int lattice_set_variant(lattice_t *lat, int variant);
  * kernel's tile 9 at FP32, else 1).  Defaults are resolved for the kernel
  * each sweep runs.
  * LAT_ERR_ARG for a tile the selected variant does not have (and
- * lattice_set_variant(LAT_SWEEP_STREAM) with a tile above 9).  Results do
+ * lattice_set_variant(LAT_SWEEP_STREAM) with a tile above 10).  Results do
  * not depend on any of them. */
 int lattice_set_tuning(lattice_t *lat, int64_t planes, int tile, int xcd_order);
 

@@ -265,10 +265,14 @@ __device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
 __device__ __forceinline__ uint32_t sr_operand(uint32_t w) {
     return __builtin_amdgcn_perm(w, w << 15, 0x04080C0Cu) ^ 0x800000u;
 }
+// Each conversion writes one half of its destination and keeps the other, so
+// the pair starts from a's own register (both halves are overwritten), which
+// needs no zeroing move.
 __device__ __forceinline__ uint32_t bf16x2_sr(float a, float b, uint32_t wa, uint32_t wb) {
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-    bf16x2 o = {};
-    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(a), sr_operand(wa), false);
+    const float ra = fp32_reg(a);
+    bf16x2 o = __builtin_bit_cast(bf16x2, ra);
+    o = __builtin_amdgcn_cvt_sr_bf16_f32(o, ra, sr_operand(wa), false);
     o = __builtin_amdgcn_cvt_sr_bf16_f32(o, fp32_reg(b), sr_operand(wb), true);
     return __builtin_bit_cast(uint32_t, o);
 }
@@ -312,8 +316,9 @@ __device__ __forceinline__ _Float16 to_f16(float v) { return (_Float16)fp32_reg(
 // Two values stochastically rounded to FP16 and packed (a in the low half).
 __device__ __forceinline__ uint32_t f16x2_sr(float a, float b, uint32_t wa, uint32_t wb) {
     typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-    f16x2 o = {};
-    o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(a), sr_operand(wa), false);
+    const float ra = fp32_reg(a);
+    f16x2 o = __builtin_bit_cast(f16x2, ra);  // both halves are overwritten (as in bf16x2_sr)
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, ra, sr_operand(wa), false);
     o = __builtin_amdgcn_cvt_sr_f16_f32(o, fp32_reg(b), sr_operand(wb), true);
     return __builtin_bit_cast(uint32_t, o);
 }
@@ -428,12 +433,14 @@ __device__ __forceinline__ QuadOut heatbath_quad_f16(u32x2 bm, u32x2 bc, u32x2 b
 // that a thread can have the loads of several quads in flight.
 template <class St, bool kF16 = kF16Grid<St>>
 struct QuadNeighbours {
-    float4 cen, ym, yp, zm, zp;
+    using Quad = float4;
+    Quad cen, ym, yp, zm, zp;
     float e;
 };
 template <class St>
 struct QuadNeighbours<St, true> {
-    u32x2 cen, ym, yp, zm, zp;
+    using Quad = u32x2;
+    Quad cen, ym, yp, zm, zp;
     uint32_t e;
 };
 

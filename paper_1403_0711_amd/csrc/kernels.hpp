@@ -56,7 +56,7 @@ struct SweepArgs {
 };
 constexpr uint32_t kGatherEntryBytes = 20;  // staged key (4 B), Q and S (8 B each)
 constexpr int kZslabTiles = 8;
-constexpr int kStreamTiles = 10;  // tile configurations of the streaming slab kernel
+constexpr int kStreamTiles = 11;  // tile configurations of the streaming slab kernel
 // streaming kernel: odd slabs walk down z (the fused gather's lists follow
 // each tile's walk order)
 constexpr bool kStreamAltZ = true;

@@ -1,11 +1,12 @@
 // Streaming slab half-sweep: a producer wave feeds an LDS ring of planes
 // with direct buffer-to-LDS loads, the compute waves update from LDS.
 //
-// A workgroup owns a tile of 32m quads (128m same-colour sites, m = 1..4) x
-// kTY rows and walks `zc` planes along z, as the z-slab kernel does; what
-// differs is who loads.  The workgroup is m kTY/2 compute waves plus one
-// producer wave; a compute wave holds a 32-quad strip of two rows of the
-// same parity, so the x-pairing of the update is uniform per wave.  A tile
+// A workgroup owns a tile of 32m quads (128m same-colour sites, m = 1..4),
+// or of one 16-quad strip, x kTY rows and walks `zc` planes along z, as the
+// z-slab kernel does; what differs is who loads.  The workgroup is
+// (tile width) kTY / 64 compute waves plus one producer wave; a compute wave
+// holds a 32-quad strip of two rows of the same parity (or a 16-quad strip
+// of four), so the x-pairing of the update is uniform per wave.  A tile
 // as wide as the box's rows makes every plane of the tile one contiguous run
 // of memory.  The producer copies each plane of the other colour that the
 // tile needs (its kTY rows, the halo rows y0-1 and y0+kTY, and the quads
@@ -58,9 +59,10 @@
 
 namespace latcoul {
 
-template <class St, int kM, int kTY, int kRing_>
+template <class St, int kM, int kTY, int kRing_, int kQW = 32>
 struct Stream {
-    static constexpr int kTX = 32 * kM;                  // quads per tile row
+    static constexpr int kTX = kQW * kM;                 // quads per tile row
+    static constexpr int kRowsPerWave = 64 / kQW;        // rows of one parity a wave holds
     static constexpr int kRing = kRing_;                 // plane slots
     static constexpr uint32_t kEsz = St::kBytes;
     static constexpr uint32_t kQB = 4 * kEsz;            // bytes per quad
@@ -73,21 +75,23 @@ struct Stream {
     static constexpr int kNI = (int)((kChunks + 63) / 64);  // load instructions per plane
     static constexpr int kCompute = kTX * kTY;           // compute threads
     static constexpr int kThreads = kCompute + 64;
-    static_assert(kTY % 4 == 0, "rows are permuted in groups of two waves");
+    static_assert(kQW == 32 || kQW == 16, "strips of 32 or 16 quads");
+    static_assert(kTY % (2 * kRowsPerWave) == 0, "rows are permuted in groups of two waves");
     static_assert(kSlot % 16 == 0 && kRB % 16 == 0, "LDS rows must keep 16-byte alignment");
     static_assert(kRing >= 5 && kRing <= 7, "ring of 5..7 planes");
-    static_assert(kM >= 1 && kM <= 4, "tile width 32 .. 128 quads");
+    static_assert(kM >= 1 && kM <= 4, "tile width 1 .. 4 strips");
     static_assert(kRing * kSlot <= 65536, "static LDS of one workgroup");
     static_assert((kRing - 4) * kNI < 64, "vmcnt (6 bits) must count the planes left in flight");
 
-    // compute thread t -> (tile row, quad column): wave w takes 32-quad strip
-    // w % m of the row pair w / m; pair g holds rows 4(g/2) + g%2 and the row
-    // two below it (same parity), lanes 0..31 the first, 32..63 the second
+    // compute thread t -> (tile row, quad column): wave w takes strip w % m
+    // (kQW quads) of row group g = w / m, k = 64 / kQW rows of one parity:
+    // rows 2k(g/2) + g%2, and the k - 1 rows two, four, .. below it, lanes
+    // 0..kQW-1 the first (32-quad strips: two rows; 16-quad strips: four)
     static __device__ __forceinline__ void place(uint32_t t, uint32_t& row, uint32_t& col) {
         const uint32_t w = t >> 6, lane = t & 63u;
         const uint32_t g = w / kM, strip = w % kM;
-        row = 4u * (g >> 1) + (g & 1u) + 2u * (lane >> 5);
-        col = 32u * strip + (lane & 31u);
+        row = 2u * kRowsPerWave * (g >> 1) + (g & 1u) + 2u * (lane / kQW);
+        col = kQW * strip + (lane % kQW);
     }
 };
 
@@ -100,14 +104,14 @@ constexpr int kGatherRegs = 4;
 constexpr uint32_t kNoEntry = 0xFFFFFFFFu;  // plane field never matches
 
 // kNT: non-temporal stores of the updated colour.
-template <class St, int kM, int kTY, int kRing, bool kNT>
-__global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsweep_stream(
+template <class St, int kM, int kTY, int kRing, bool kNT, int kQW = 32>
+__global__ __launch_bounds__((Stream<St, kM, kTY, kRing, kQW>::kThreads)) void halfsweep_stream(
     const typename St::T* __restrict__ other, typename St::T* __restrict__ own, uint32_t lh, uint32_t ly,
     uint32_t lz, uint32_t zc, uint32_t c, uint32_t h, uint32_t k0, uint32_t k1, uint32_t chain,
     uint32_t xcd_order, const uint32_t* __restrict__ tdev, const uint32_t* __restrict__ g_off,
     const uint32_t* __restrict__ g_key, const double* __restrict__ g_Q, const double* __restrict__ g_S,
     double* __restrict__ g_part, uint32_t g_n, uint32_t g_cap, SampleFinalize fin, uint32_t zalt) {
-    using S = Stream<St, kM, kTY, kRing>;
+    using S = Stream<St, kM, kTY, kRing, kQW>;
     using T = typename St::T;
     __shared__ __align__(16) unsigned char ring[S::kRing * S::kSlot];
     // fused gather: the tile's list offsets, then its keys, Q and S (g_cap
@@ -308,61 +312,86 @@ __global__ __launch_bounds__((Stream<St, kM, kTY, kRing>::kThreads)) void halfsw
         const uint32_t rowj = y * lh + 4u * q;
         const uint32_t qoff = (row + 1u) * S::kRB + (tx + 1u) * S::kQB;  // the thread's quad in a slot
         if (finalize) finalize_in_workgroup<S::kThreads, S::kCompute>(fin);
-        for (uint32_t s = 0; s < n; ++s) {
-            __syncthreads();  // b_s
-            if (!active) continue;
-            const uint32_t z = down ? z1 - 1u - s : z0 + s;
-            // walk planes s, s + 1, s + 2: planes z -+ 1, z, z +- 1
-            const unsigned char* pw0 = ring + (s % S::kRing) * S::kSlot + qoff;
-            const unsigned char* pc = ring + ((s + 1u) % S::kRing) * S::kSlot + qoff;
-            const unsigned char* pw2 = ring + ((s + 2u) % S::kRing) * S::kSlot + qoff;
-            const unsigned char* pm = down ? pw2 : pw0;  // plane z - 1
-            const unsigned char* pn = down ? pw0 : pw2;  // plane z + 1
-            const uint32_t p = __builtin_amdgcn_readfirstlane((c + y + z) & 1u);  // uniform per wave
-            const uint32_t j0 = z * plane + rowj;
-            QuadOut out;
-            if constexpr (kF16Grid<St>) {  // halves added in mixed-precision FMAs
-                const unsigned char* pe = p == 0 ? pc - S::kEsz : pc + S::kQB;
-                out = heatbath_quad_f16(*reinterpret_cast<const u32x2*>(pm), *reinterpret_cast<const u32x2*>(pc),
-                                        *reinterpret_cast<const u32x2*>(pn),
-                                        *reinterpret_cast<const u32x2*>(pc - S::kRB),
-                                        *reinterpret_cast<const u32x2*>(pc + S::kRB),
-                                        (uint32_t)*reinterpret_cast<const uint16_t*>(pe), p, j0, h, chain, k0, k1);
-            } else {
-                const float4 bm = St::ld4(reinterpret_cast<const T*>(pm), 0);
-                const float4 bc = St::ld4(reinterpret_cast<const T*>(pc), 0);
-                const float4 bn = St::ld4(reinterpret_cast<const T*>(pn), 0);
-                const float4 up = St::ld4(reinterpret_cast<const T*>(pc - S::kRB), 0);
-                const float4 dn = St::ld4(reinterpret_cast<const T*>(pc + S::kRB), 0);
-                const float e = p == 0 ? St::ld(reinterpret_cast<const T*>(pc - S::kEsz), 0)
-                                       : St::ld(reinterpret_cast<const T*>(pc + S::kQB), 0);
-                out = heatbath_quad(bm, bc, bn, up, dn, e, p, j0, h, chain, k0, k1);
-            }
-            if constexpr (kNT)
-                St::st4_nt(own, j0, out.v, out.w);
+        // The thread's quad of walk planes s and s + 1 is kept from the two
+        // steps before (as FP32, or as raw halves for FP16, whose update adds
+        // them in mixed-precision FMAs): a step reads (and widens) only the
+        // quad of walk plane s + 2 besides plane z's rows y -+ 1 and its
+        // x-neighbour.  Steps are unrolled by three, so that the three quads
+        // rotate through registers without copies.
+        using Q = typename QuadNeighbours<St>::Quad;
+        auto ldq = [&](const unsigned char* pq) __attribute__((always_inline)) -> Q {
+            if constexpr (kF16Grid<St>)
+                return *reinterpret_cast<const u32x2*>(pq);
             else
-                St::st4(own, j0, out.v, out.w);
-        }
+                return St::ld4(reinterpret_cast<const T*>(pq), 0);
+        };
+        auto walk = [&](auto down_c) __attribute__((always_inline)) {
+            constexpr bool kDown = decltype(down_c)::value;
+            auto step = [&](uint32_t s, Q& wa, Q& wb, Q& wc, bool first) __attribute__((always_inline)) {
+                __syncthreads();  // b_s
+                if (!active) return;
+                const uint32_t z = kDown ? z1 - 1u - s : z0 + s;
+                const unsigned char* pc = ring + ((s + 1u) % S::kRing) * S::kSlot + qoff;
+                if (first) {
+                    wa = ldq(ring + (s % S::kRing) * S::kSlot + qoff);
+                    wb = ldq(pc);
+                }
+                wc = ldq(ring + ((s + 2u) % S::kRing) * S::kSlot + qoff);
+                const Q up = ldq(pc - S::kRB), dn = ldq(pc + S::kRB);
+                const uint32_t p = __builtin_amdgcn_readfirstlane((c + y + z) & 1u);  // uniform per wave
+                const unsigned char* pe = p == 0 ? pc - S::kEsz : pc + S::kQB;  // the x-neighbour beyond the quad
+                const uint32_t j0 = z * plane + rowj;
+                // walk planes s, s + 1, s + 2: planes z -+ 1, z, z +- 1
+                QuadOut out;
+                if constexpr (kF16Grid<St>) {
+                    const uint32_t e = *reinterpret_cast<const uint16_t*>(pe);
+                    out = kDown ? heatbath_quad_f16(wc, wb, wa, up, dn, e, p, j0, h, chain, k0, k1)
+                                : heatbath_quad_f16(wa, wb, wc, up, dn, e, p, j0, h, chain, k0, k1);
+                } else {
+                    const float e = St::ld(reinterpret_cast<const T*>(pe), 0);
+                    out = kDown ? heatbath_quad(wc, wb, wa, up, dn, e, p, j0, h, chain, k0, k1)
+                                : heatbath_quad(wa, wb, wc, up, dn, e, p, j0, h, chain, k0, k1);
+                }
+                if constexpr (kNT)
+                    St::st4_nt(own, j0, out.v, out.w);
+                else
+                    St::st4(own, j0, out.v, out.w);
+            };
+            Q qa = {}, qb = {}, qc = {};
+            step(0u, qa, qb, qc, true);
+            for (uint32_t s = 1; s < n; s += 3) {
+                step(s, qb, qc, qa, false);
+                if (s + 1u >= n) break;
+                step(s + 1u, qc, qa, qb, false);
+                if (s + 2u >= n) break;
+                step(s + 2u, qa, qb, qc, false);
+            }
+        };
+        if (down)
+            walk(std::true_type());
+        else
+            walk(std::false_type());
     }
 }
 
 // One configuration: grid of tiles x slabs, dynamic LDS for a staged gather
 // list.  Requires lh % 4 == 0 and the other colour's array below 2 GiB
 // (32-bit byte offsets).
-template <class St, int kM, int kTY, int kRing, bool kNT>
+template <class St, int kM, int kTY, int kRing, bool kNT, int kQW = 32>
 static void launch_stream_cfg(const SweepArgs& a, const typename St::T* other, typename St::T* own,
                               uint32_t zc, hipStream_t stream) {
-    using S = Stream<St, kM, kTY, kRing>;
+    using S = Stream<St, kM, kTY, kRing, kQW>;
     const uint32_t nq = a.lh >> 2;
     const uint32_t nb = ((nq + S::kTX - 1) / S::kTX) * ((a.ly + kTY - 1) / kTY) * ((a.lz + zc - 1) / zc);
     const uint32_t dyn = a.g_key ? kGatherEntryBytes * a.g_cap : 0u;
-    hipLaunchKernelGGL((halfsweep_stream<St, kM, kTY, kRing, kNT>), dim3(nb), dim3(S::kThreads), dyn, stream, other,
+    hipLaunchKernelGGL((halfsweep_stream<St, kM, kTY, kRing, kNT, kQW>), dim3(nb), dim3(S::kThreads), dyn, stream, other,
                        own, a.lh, a.ly, a.lz, zc, a.c, a.h, a.k0, a.k1, a.chain, a.xcd_order, a.tdev, a.g_off,
                        a.g_key, a.g_Q, a.g_S, a.g_part, a.g_n, a.g_cap, a.fin, kStreamAltZ ? 1u : 0u);
 }
 
-// Tile configurations: tile width 32m quads, rows, ring slots, non-temporal
-// stores.  LDS per workgroup at FP32 = slots * (rows + 2) * (32m + 2) * 16 bytes.
+// Tile configurations: tile width 32m quads (tile 10: one 16-quad strip),
+// rows, ring slots, non-temporal stores.  LDS per workgroup at FP32 =
+// slots * (rows + 2) * (width + 2) * 16 bytes.
 template <class St>
 static hipError_t launch_stream_t(const SweepArgs& a, const typename St::T* other, typename St::T* own,
                                   hipStream_t stream) {
@@ -378,6 +407,7 @@ static hipError_t launch_stream_t(const SweepArgs& a, const typename St::T* othe
         case 7: launch_stream_cfg<St, 3, 4, 6, false>(a, other, own, zc, stream); break;   // 56 KB
         case 8: launch_stream_cfg<St, 4, 4, 5, false>(a, other, own, zc, stream); break;   // 62 KB
         case 9: launch_stream_cfg<St, 3, 4, 5, true>(a, other, own, zc, stream); break;
+        case 10: launch_stream_cfg<St, 1, 16, 6, false, 16>(a, other, own, zc, stream); break;  // 31 KB
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -387,7 +417,7 @@ static hipError_t launch_stream_t(const SweepArgs& a, const typename St::T* othe
 // the fused gather and the LDS budget of their staging.
 bool stream_tile_geometry(uint32_t tile, uint32_t esz, StreamTileShape* out) {
     static const uint32_t kShape[kStreamTiles][3] = {{32, 8, 6},  {32, 8, 5}, {32, 16, 5}, {32, 8, 6}, {64, 4, 5},
-                                                     {64, 8, 5},  {96, 4, 5}, {96, 4, 6},  {128, 4, 5}, {96, 4, 5}};
+                                                     {64, 8, 5},  {96, 4, 5}, {96, 4, 6},  {128, 4, 5}, {96, 4, 5}, {16, 16, 6}};
     if (tile >= (uint32_t)kStreamTiles || (esz != 4 && esz != 2)) return false;
     const uint32_t q = kShape[tile][0], rows = kShape[tile][1], slots = kShape[tile][2];
     out->quads = q;

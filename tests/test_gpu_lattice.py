@@ -53,6 +53,10 @@ SHAPES = [
     ((264, 10, 7), "stream"),   # 33 quads per row: a partial x tile
     ((8, 1, 3), "stream"),      # one row per plane
     ((520, 12, 5), "stream"),   # 16-row tiles over 12 rows, 65 quads per row
+    ((16, 16, 16), "stream16"), # 16-quad strips (tile 10): 2 of 16 quads per row
+    ((264, 10, 7), "stream16"), # 33 quads per row: tiles of 16, 16 and 1; 10 of 16 rows
+    ((136, 40, 9), "stream16"), # 17 quads per row, row tiles of 16, 16 and 8
+    ((8, 1, 3), "stream16"),    # one row per plane
     ((16, 16, 16), "quad"),
     ((24, 16, 8), "quad"),
     ((40, 24, 9), "quad"),      # several tiles + ragged y and z
@@ -82,13 +86,15 @@ def test_field_parity_per_sweep_fp32(lat_mod, shape, variant):
     print(f"[gpu] field parity {shape} {variant}", flush=True)
     seed = 0x1234ABCD5678
     lat = lat_mod.Lattice(shape, "fp32", seed=seed, chain_id=3)
-    lat.set_variant(variant)
+    lat.set_variant("stream" if variant == "stream16" else variant)
     if variant == "zslab":
         lat.set_tuning(2 if shape[2] > 2 else 1, tile=(shape[0] + shape[1]) % 8, xcd_order=True)
     if variant == "fused":
         lat.set_tuning(3, 0, xcd_order=True)
     if variant == "stream":
         lat.set_tuning(2 if shape[2] > 2 else 1, tile=sum(shape) % 10, xcd_order=True)
+    if variant == "stream16":
+        lat.set_tuning(2 if shape[2] > 2 else 1, tile=10, xcd_order=sum(shape) % 3)
     if variant == "blocked":  # rows per tile and planes per slab small enough for several of each
         lat.set_tuning(2 if shape[2] > 2 else 1, tile=(3, 5, 7, 2)[sum(shape) % 4], xcd_order=sum(shape) % 3)
     ref = oracle.OracleChain(shape, "fp32", seed=seed, chain=3)
@@ -121,7 +127,8 @@ def test_variants_agree(lat_mod):
                                      ("stream", 0, 0, True), ("stream", 1, 1, False), ("stream", 7, 2, True),
                                      ("stream", 20, 3, False), ("stream", 3, 4, True), ("stream", 2, 5, True),
                                      ("stream", 9, 6, True), ("stream", 6, 7, True), ("stream", 5, 8, False),
-                                     ("stream", 4, 9, True), ("stream", 11, 4, True),
+                                     ("stream", 4, 9, True), ("stream", 11, 4, True), ("stream", 5, 10, 2),
+                                     ("stream", 1, 10, 0),
                                      ("blocked", 0, -1, 2), ("blocked", 5, 3, 1), ("blocked", 3, 8, 0),
                                      ("blocked", 1, 1, 2), ("blocked", 20, 16, 2)):
         a = lat_mod.Lattice(shape, seed=7)
@@ -151,7 +158,8 @@ def test_variants_agree_stochastic_rounding(lat_mod, storage):
     for variant, slab, tile, xcd in (("quad", 0, 0, True), ("resident", 0, 0, True), ("fused", 0, 0, True),
                                      ("fused", 5, 0, False), ("zslab", 0, 0, True), ("zslab", 7, 2, True),
                                      ("zslab", 5, 4, True), ("stream", 0, 0, True), ("stream", 7, 2, True),
-                                     ("stream", 3, 4, True), ("stream", 9, 6, True), ("blocked", 0, -1, 2),
+                                     ("stream", 3, 4, True), ("stream", 9, 6, True), ("stream", 5, 10, True),
+                                     ("blocked", 0, -1, 2),
                                      ("blocked", 5, 3, 1), ("blocked", 20, 16, 2)):
         a = lat_mod.Lattice(shape, storage, seed=7)
         a.set_variant(variant)
@@ -279,6 +287,7 @@ def test_reduced_precision_parity(lat_mod, storage, variant):
 @pytest.mark.parametrize("storage", ["bf16sr", "fp16sr"])
 @pytest.mark.parametrize("variant,shape,tuning", [
     ("stream", (264, 10, 7), (5, 0)),    # 33 quads per row: a partial x tile
+    ("stream", (136, 40, 9), (4, 10)),   # 16-quad strips: ragged x, y and z tiles
     ("zslab", (264, 10, 7), (3, 2)),
     ("quad", (40, 24, 9), None),         # several tiles, ragged y and z
     ("blocked", (96, 37, 23), (5, 4)),   # several tiles and slabs, both ragged
@@ -424,7 +433,7 @@ def test_argument_errors(lat_mod):
         lat_mod.Lattice((6, 6, 6)).set_variant("quad")  # lh = 3: rejected
     lat.set_variant("stream")
     with pytest.raises(lat_mod.LatticeError):
-        lat.set_tuning(4, 10, True)  # the streaming kernel has tiles 0 .. 9
+        lat.set_tuning(4, 11, True)  # the streaming kernel has tiles 0 .. 10
     lat.set_variant("zslab")
     lat.set_tuning(4, 7, True)
     lat.set_variant("stream")  # tile 7 exists for both slab kernels
